@@ -1,0 +1,207 @@
+/*
+ * spleaf: leaf kernels of distributed sparse tensor algebra on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library evaluates the tensor-index-notation statements of the SpDISTAL
+ * paper's evaluation (Sec. VI-A) on one GPU's share of the data: sparse
+ * operands stored with Dense and Compressed levels (Sec. II-B, III-B), split
+ * into tiles by the paper's two partition kinds (Sec. II-B): a universe
+ * partition of the row coordinates ("row split") or a non-zero partition of
+ * the fused coordinates ("non-zero split"), plus an equal split of the merged
+ * row-end/position sequence ("merge split").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every pointer inside spl_sparse and spl_dense, every output array, every
+ *   workspace and every tile-bound array is a DEVICE pointer on the context's
+ *   GPU, owned by the caller.  The library never frees or keeps them.
+ *   Pointers documented as "host" are host memory.
+ * - A Compressed level l stores pos[l] (parent count + 1 entries, int32,
+ *   pos[l][0] = 0, non-decreasing) and crd[l] (int32, one per stored
+ *   coordinate).  The coordinates of parent entry e are crd[l][pos[l][e]] ..
+ *   crd[l][pos[l][e+1]-1] (Sec. III-B; the paper's inclusive (lo, hi) pairs are
+ *   lo = pos[e], hi = pos[e+1]-1).  Coordinates must be strictly increasing
+ *   within each segment.  Only CSR = (Dense, Compressed) and
+ *   CSF = (Dense, Compressed, Compressed) are accepted.
+ * - Dense operands are row-major with leading dimension ld (in elements).
+ * - Outputs are overwritten (assignment semantics of Sec. II-A): every output
+ *   entry is written, an empty row gives +0.0.
+ * - Calls are asynchronous on `stream` (a hipStream_t) unless documented
+ *   otherwise.  Metadata (shapes, dtypes, formats, null pointers) is checked
+ *   on the host before anything is launched; the CONTENTS of pos/crd are
+ *   checked only by spl_validate, and a kernel call on invalid contents is
+ *   undefined.  HIP launch errors are reported as SPL_ERR_HIP; errors of
+ *   earlier asynchronous work surface at the next call or at spl_sync.
+ * - `workspace` may be NULL: the context then uses a device buffer of its own,
+ *   grown on demand (the grow synchronizes the device).  A caller-supplied
+ *   workspace of fewer bytes than spl_workspace_query reports is rejected
+ *   with SPL_ERR_WORKSPACE.
+ * - No C++ exception crosses this interface.  A context is not thread-safe;
+ *   use one per host thread.  Results are deterministic: no floating-point
+ *   atomics are used, so repeated calls give identical bits.
+ */
+#ifndef SPLEAF_H
+#define SPLEAF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spl_status {
+    SPL_OK = 0,
+    SPL_ERR_ARG = 1,         /* null pointer, negative size, bad enum value   */
+    SPL_ERR_FORMAT = 2,      /* level formats other than (D,C) / (D,C,C)      */
+    SPL_ERR_SHAPE = 3,       /* operand dimensions do not match               */
+    SPL_ERR_DTYPE = 4,       /* dtype combination not provided                */
+    SPL_ERR_UNSUPPORTED = 5, /* valid request this library does not implement */
+    SPL_ERR_WORKSPACE = 6,   /* caller workspace smaller than required        */
+    SPL_ERR_NOMEM = 7,       /* device allocation failed                      */
+    SPL_ERR_HIP = 8,         /* HIP runtime error                             */
+    SPL_ERR_INVALID = 9      /* spl_validate found malformed pos/crd          */
+} spl_status;
+
+typedef enum spl_dtype { SPL_F64 = 0, SPL_F32 = 1, SPL_BF16 = 2 } spl_dtype;
+
+typedef enum spl_level_format { SPL_DENSE = 0, SPL_COMPRESSED = 1 } spl_level_format;
+
+/* How the leaf iteration space is cut into tiles (Sec. II-B, II-D, IV-C). */
+typedef enum spl_sched_kind {
+    SPL_SCHED_DEFAULT = 0, /* library choice (merge split)                    */
+    SPL_ROW = 1,   /* universe partition of rows, image to positions          */
+    SPL_NNZ = 2,   /* non-zero partition of fused positions, rows by preimage */
+    SPL_MERGE = 3  /* equal split of the merged (row ends + positions) list   */
+} spl_sched_kind;
+
+typedef enum spl_op {
+    SPL_OP_SPMV = 0,   /* a(i) = B(i,j) * c(j)                                */
+    SPL_OP_SPMM = 1,   /* A(i,j) = B(i,k) * C(k,j)                            */
+    SPL_OP_SPADD3 = 2, /* A(i,j) = B(i,j) + C(i,j) + D(i,j)                   */
+    SPL_OP_SDDMM = 3,  /* A(i,j) = B(i,j) * C(i,k) * D(j,k)                   */
+    SPL_OP_SPTTV = 4,  /* A(i,j) = B(i,j,k) * c(k)                            */
+    SPL_OP_MTTKRP = 5, /* A(i,l) = B(i,j,k) * C(j,l) * D(k,l)                 */
+    SPL_OP_INNER = 6   /* a = B(i,j,k) * C(i,j,k)                             */
+} spl_op;
+
+typedef struct spl_context spl_context;
+typedef void *spl_stream; /* a hipStream_t; NULL is the null stream */
+
+/* A sparse operand (Sec. III-B).  level[0] must be SPL_DENSE and the others
+ * SPL_COMPRESSED; pos[l]/crd[l] are used for Compressed levels l >= 1 and
+ * ignored for level 0.  nnz must equal pos[order-1][last] (the caller knows
+ * it; the library does not read it back).  For CSF, F = pos[1][dims[0]]
+ * fibers is passed in nfibers. */
+typedef struct spl_sparse {
+    int32_t order;          /* 2 (CSR) or 3 (CSF)                              */
+    int32_t vtype;          /* spl_dtype of vals                               */
+    int64_t dims[3];        /* coordinate extents (rows, cols[, depth])        */
+    int32_t level[3];       /* spl_level_format per stored dimension           */
+    const int32_t *pos[3];  /* device, per Compressed level                    */
+    const int32_t *crd[3];  /* device, per Compressed level                    */
+    const void *vals;       /* device, nnz values of type vtype                */
+    int64_t nnz;            /* stored values                                   */
+    int64_t nfibers;        /* CSF only: entries of the middle level           */
+} spl_sparse;
+
+/* A dense operand: vector (ndim 1) or row-major matrix (ndim 2). */
+typedef struct spl_dense {
+    void *data;       /* device                                               */
+    int32_t dtype;    /* spl_dtype                                            */
+    int32_t ndim;     /* 1 or 2                                               */
+    int64_t dims[2];  /* extents; dims[1] ignored for ndim 1                  */
+    int64_t ld;       /* leading dimension in elements (>= dims[1]); 1 for vectors */
+} spl_dense;
+
+/* Tiling of one call.  Zero fields mean "library default". */
+typedef struct spl_schedule {
+    int32_t kind;           /* spl_sched_kind                                 */
+    int32_t lanes_per_row;  /* SPL_ROW: lanes sharing one row: 1,2,..,64      */
+    int32_t tile;           /* SPL_NNZ: positions per tile; SPL_MERGE: merged
+                               items per tile                                 */
+    int32_t items_per_lane; /* merged items one lane (SpMV) or lane group
+                               (SpMM, MTTKRP) walks per chunk: 4, 8 or 16      */
+    int32_t col_tile;       /* SpMM: dense columns per lane group: 8,16,32,64 */
+    int32_t variant;        /* op-specific kernel variant, 0 = default        */
+} spl_schedule;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device`.  *out receives the handle. */
+spl_status spl_context_create(int device, spl_context **out);
+/* Destroy a context and free its own workspace.  NULL is accepted. */
+spl_status spl_context_destroy(spl_context *ctx);
+/* Detail of the last error on this context (static storage inside ctx). */
+const char *spl_last_error(const spl_context *ctx);
+/* Name of a status code. */
+const char *spl_status_string(spl_status s);
+/* Wait for all work on `stream`; reports asynchronous HIP errors. */
+spl_status spl_sync(spl_context *ctx, spl_stream stream);
+
+/* ------------------------------------------------------ index notation */
+
+/* The index-notation statement an op evaluates (Sec. II-A, VI-A). */
+const char *spl_op_tin(spl_op op);
+/* Parse one of the seven statements (up to renaming of index variables and
+ * tensors' case-preserving names B, C, D, and white space); any other
+ * statement gives SPL_ERR_UNSUPPORTED.  `tin` is a host string. */
+spl_status spl_op_parse(const char *tin, spl_op *out);
+
+/* ------------------------------------------------------------ helpers */
+
+/* Device bytes of workspace that `op` needs for operand B, `ncols` dense
+ * columns (SpMM N, MTTKRP R; 1 otherwise) and schedule `sched`.  *bytes is
+ * host memory. */
+spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
+                               int64_t ncols, const spl_schedule *sched,
+                               size_t *bytes);
+
+/* The level partition of the leaf iteration space (Sec. IV-B, Table I;
+ * Sec. III-A image and preimage), as used by the kernels: for tile t,
+ * tile_row[t] is the first row the tile finishes and tile_pos[t] its first
+ * position; tile t covers positions [tile_pos[t], tile_pos[t+1]) and
+ * finishes rows [tile_row[t], tile_row[t+1]); the last entry is (n, nnz).
+ * Row r counts as finished at position p when pos[r+1] <= p, so a tile that
+ * begins at position p > 0 begins after every row ending at or before p.
+ *   SPL_ROW   : tile t = rows [t*R, (t+1)*R), R = sched->tile (image).
+ *   SPL_NNZ   : tile t = positions [t*T, (t+1)*T), T = sched->tile (preimage).
+ *   SPL_MERGE : tile t = merged items [t*M, (t+1)*M), M = sched->tile.
+ * For CSF operands the split applies to the last level (fibers as rows).
+ * `capacity` is the length of both device arrays; *ntiles (host) receives
+ * the tile count (capacity must be >= ntiles+1, else SPL_ERR_ARG). */
+spl_status spl_tile_bounds(spl_context *ctx, const spl_sparse *B,
+                           const spl_schedule *sched, int32_t *tile_row,
+                           int32_t *tile_pos, int64_t capacity,
+                           int64_t *ntiles, spl_stream stream);
+
+/* Check pos/crd contents on the device: pos[0] = 0, non-decreasing pos,
+ * last pos = child count (nnz or nfibers), every crd in [0, extent),
+ * strictly increasing within each segment.  Returns SPL_OK or
+ * SPL_ERR_INVALID with the first failing condition in spl_last_error.
+ * Synchronizes on `stream`. */
+spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream);
+
+/* ------------------------------------------------------------ kernels */
+
+/* SpMV  a(i) = B(i,j) * c(j)   (Sec. VI-A; the leaf of Fig. 8b).
+ * B CSR n x m; c vector m; a vector n.  dtypes: vals, c, a all F64, or all
+ * F32 (products and sums in F64, rounded once per output).  Schedules: ROW,
+ * NNZ, MERGE (default MERGE). */
+spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
+                    spl_dense *a, const spl_schedule *sched, void *workspace,
+                    size_t workspace_bytes, spl_stream stream);
+
+/* SpMM  A(i,j) = B(i,k) * C(k,j)   (Sec. VI-A).
+ * B CSR n x m; C dense m x N; A dense n x N.  dtypes (vals, C, A): all F64;
+ * all F32; or vals and C BF16 with A F32 (F32 accumulation).  Schedules:
+ * ROW, NNZ, MERGE (default MERGE); col_tile 8..64 columns per lane group. */
+spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
+                    spl_dense *A, const spl_schedule *sched, void *workspace,
+                    size_t workspace_bytes, spl_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLEAF_H */

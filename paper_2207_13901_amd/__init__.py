@@ -1,0 +1,248 @@
+"""spleaf: sparse tensor algebra leaf kernels for one MI355X (gfx950).
+
+A thin binding of libspleaf's C ABI (include/spleaf.h): the functions below
+only marshal torch tensors (device memory) and the current HIP stream into
+the C structs; every step of every operation runs in the library's HIP
+kernels.  The names follow the C entry points without the ``spl_`` prefix.
+
+Sparse operands are ``CSR`` (Dense, Compressed) and ``CSF`` (Dense,
+Compressed, Compressed) objects holding int32 pos/crd and a value tensor,
+all on the same GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _native as N
+from ._native import SpleafError
+
+__all__ = [
+    "CSR", "CSF", "Context", "schedule", "spmv", "spmm", "tile_bounds",
+    "validate", "op_parse", "op_tin", "workspace_query", "SpleafError",
+]
+
+_DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
+_KIND = {"default": N.SCHED_DEFAULT, "row": N.ROW, "nnz": N.NNZ, "merge": N.MERGE}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}") from None
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class CSR:
+    """CSR matrix: pos int32[n+1], crd int32[nnz], vals[nnz]; shape (n, m)."""
+    pos: torch.Tensor
+    crd: torch.Tensor
+    vals: torch.Tensor
+    shape: tuple
+
+    def struct(self) -> N.SplSparse:
+        s = N.SplSparse()
+        s.order = 2
+        s.vtype = _dtype_code(self.vals)
+        s.dims[0], s.dims[1], s.dims[2] = self.shape[0], self.shape[1], 0
+        s.level[0], s.level[1] = N.DENSE, N.COMPRESSED
+        s.pos[1] = _ptr(self.pos)
+        s.crd[1] = _ptr(self.crd)
+        s.vals = _ptr(self.vals)
+        s.nnz = self.crd.numel()
+        return s
+
+    def with_vals(self, vals: torch.Tensor) -> "CSR":
+        return CSR(self.pos, self.crd, vals, self.shape)
+
+
+@dataclass
+class CSF:
+    """CSF 3-tensor: pos1 int32[I+1], crd1 int32[F] (j per fiber),
+    pos2 int32[F+1], crd2 int32[nnz] (k per value), vals[nnz]."""
+    pos1: torch.Tensor
+    crd1: torch.Tensor
+    pos2: torch.Tensor
+    crd2: torch.Tensor
+    vals: torch.Tensor
+    shape: tuple
+
+    def struct(self) -> N.SplSparse:
+        s = N.SplSparse()
+        s.order = 3
+        s.vtype = _dtype_code(self.vals)
+        for d in range(3):
+            s.dims[d] = self.shape[d]
+        s.level[0], s.level[1], s.level[2] = N.DENSE, N.COMPRESSED, N.COMPRESSED
+        s.pos[1], s.crd[1] = _ptr(self.pos1), _ptr(self.crd1)
+        s.pos[2], s.crd[2] = _ptr(self.pos2), _ptr(self.crd2)
+        s.vals = _ptr(self.vals)
+        s.nnz = self.crd2.numel()
+        s.nfibers = self.crd1.numel()
+        return s
+
+    def with_vals(self, vals: torch.Tensor) -> "CSF":
+        return CSF(self.pos1, self.crd1, self.pos2, self.crd2, vals, self.shape)
+
+
+def _dense(t: torch.Tensor) -> N.SplDense:
+    d = N.SplDense()
+    d.data = t.data_ptr()
+    d.dtype = _dtype_code(t)
+    d.ndim = t.dim()
+    if t.dim() == 1:
+        if t.numel() and t.stride(0) != 1:
+            raise ValueError("dense vector must be contiguous")
+        d.dims[0], d.dims[1], d.ld = t.shape[0], 1, 1
+    elif t.dim() == 2:
+        if t.numel() and t.stride(1) != 1:
+            raise ValueError("dense matrix must be row-major (unit column stride)")
+        d.dims[0], d.dims[1] = t.shape
+        d.ld = t.stride(0) if t.shape[0] > 1 else t.shape[1]
+    else:
+        raise ValueError("dense operand must have 1 or 2 dimensions")
+    return d
+
+
+def schedule(kind: str = "default", lanes_per_row: int = 0, tile: int = 0,
+             items_per_lane: int = 0, col_tile: int = 0, variant: int = 0) -> N.SplSchedule:
+    """Build a spl_schedule; zero fields take the library default."""
+    s = N.SplSchedule()
+    s.kind = _KIND[kind] if isinstance(kind, str) else int(kind)
+    s.lanes_per_row, s.tile, s.items_per_lane = lanes_per_row, tile, items_per_lane
+    s.col_tile, s.variant = col_tile, variant
+    return s
+
+
+class Context:
+    """Owns one spl_context for a device."""
+
+    _per_device: dict = {}
+
+    def __init__(self, device: int = 0):
+        self.lib = N.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self.lib.spl_context_create(device, ctypes.byref(h))
+        if st != N.OK:
+            raise SpleafError(st, f"spl_context_create({device})")
+        self.h = h
+
+    @classmethod
+    def get(cls, device: Optional[int] = None) -> "Context":
+        if device is None:
+            device = torch.cuda.current_device()
+        if device not in cls._per_device:
+            cls._per_device[device] = cls(device)
+        return cls._per_device[device]
+
+    def check(self, st: int, what: str):
+        if st != N.OK:
+            raise SpleafError(st, f"{what}: {self.lib.spl_last_error(self.h).decode()}")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.spl_context_destroy(self.h)
+        except Exception:
+            pass
+
+
+def _ctx_stream(t: torch.Tensor, ctx: Optional[Context]):
+    ctx = ctx or Context.get(t.device.index)
+    stream = torch.cuda.current_stream(t.device).cuda_stream
+    return ctx, stream
+
+
+def workspace_query(op: int, B, ncols: int = 1, sched=None,
+                    ctx: Optional[Context] = None) -> int:
+    ctx = ctx or Context.get()
+    nbytes = ctypes.c_size_t()
+    s = B.struct()
+    ctx.check(ctx.lib.spl_workspace_query(ctx.h, op, ctypes.byref(s), ncols,
+                                          ctypes.byref(sched) if sched else None,
+                                          ctypes.byref(nbytes)), "spl_workspace_query")
+    return nbytes.value
+
+
+def _workspace(op, B, ncols, sched, ctx, device):
+    nbytes = workspace_query(op, B, ncols, sched, ctx)
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def spmv(B: CSR, c: torch.Tensor, a: Optional[torch.Tensor] = None, sched=None,
+         ctx: Optional[Context] = None) -> torch.Tensor:
+    """a(i) = B(i,j) * c(j)."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if a is None:
+        a = torch.empty(B.shape[0], dtype=B.vals.dtype, device=B.vals.device)
+    s = B.struct()
+    ws, nb = _workspace(N.OP_SPMV, B, 1, sched, ctx, B.vals.device)
+    ctx.check(ctx.lib.spl_spmv(ctx.h, ctypes.byref(s), ctypes.byref(_dense(c)),
+                               ctypes.byref(_dense(a)),
+                               ctypes.byref(sched) if sched else None,
+                               _ptr(ws), nb, stream), "spl_spmv")
+    return a
+
+
+def spmm(B: CSR, C: torch.Tensor, A: Optional[torch.Tensor] = None, sched=None,
+         ctx: Optional[Context] = None) -> torch.Tensor:
+    """A(i,j) = B(i,k) * C(k,j); BF16 inputs give an FP32 output."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if A is None:
+        odt = torch.float32 if C.dtype == torch.bfloat16 else C.dtype
+        A = torch.empty(B.shape[0], C.shape[1], dtype=odt, device=C.device)
+    s = B.struct()
+    ws, nb = _workspace(N.OP_SPMM, B, C.shape[1], sched, ctx, B.vals.device)
+    ctx.check(ctx.lib.spl_spmm(ctx.h, ctypes.byref(s), ctypes.byref(_dense(C)),
+                               ctypes.byref(_dense(A)),
+                               ctypes.byref(sched) if sched else None,
+                               _ptr(ws), nb, stream), "spl_spmm")
+    return A
+
+
+def tile_bounds(B, sched, ctx: Optional[Context] = None):
+    """The level partition of B for `sched` (ROW, NNZ or MERGE with a tile
+    size): returns (tile_row, tile_pos) int32 tensors of ntiles + 1."""
+    dev = (B.pos if isinstance(B, CSR) else B.pos2).device
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    s = B.struct()
+    rows = B.shape[0] if isinstance(B, CSR) else B.crd1.numel()
+    items = rows + s.nnz
+    cap = items // max(sched.tile, 1) + 3
+    tr = torch.empty(cap, dtype=torch.int32, device=dev)
+    tp = torch.empty(cap, dtype=torch.int32, device=dev)
+    nt = ctypes.c_int64()
+    ctx.check(ctx.lib.spl_tile_bounds(ctx.h, ctypes.byref(s), ctypes.byref(sched),
+                                      tr.data_ptr(), tp.data_ptr(), cap, ctypes.byref(nt),
+                                      stream), "spl_tile_bounds")
+    return tr[:nt.value + 1], tp[:nt.value + 1]
+
+
+def validate(B, ctx: Optional[Context] = None) -> None:
+    """Raise SpleafError(ERR_INVALID) if B's pos/crd contents are malformed."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    s = B.struct()
+    ctx.check(ctx.lib.spl_validate(ctx.h, ctypes.byref(s), stream), "spl_validate")
+
+
+def op_tin(op: int) -> str:
+    return N.load().spl_op_tin(op).decode()
+
+
+def op_parse(tin: str) -> int:
+    out = ctypes.c_int32()
+    st = N.load().spl_op_parse(tin.encode(), ctypes.byref(out))
+    if st != N.OK:
+        raise SpleafError(st, f"not one of the supported statements: {tin!r}")
+    return out.value

@@ -1,0 +1,95 @@
+// Level partitions of a Compressed level (paper Sec. III-A image/preimage,
+// Sec. IV-B Table I level functions), computed on the GPU.
+//
+// A tile is described by the point at which it starts on the merged
+// sequence of row ends and positions: (first row it finishes, first
+// position it covers).  Row r is finished once position pos[r+1]-1 has been
+// covered, i.e. at any point (i, p) with pos[r+1] <= p; an empty row is
+// finished as soon as the position walk reaches its start.
+//
+//  - Row split (universe partition of the Dense level in blocks of R rows,
+//    carried down by an image through pos): tile t starts at
+//    (t*R, pos[t*R]).
+//  - Non-zero split (non-zero partition of the fused coordinates in blocks of
+//    T positions, rows recovered by a preimage through pos): tile t starts at
+//    (number of rows finished at position t*T, t*T); tile 0 starts at (0, 0)
+//    so that leading empty rows belong to it.
+//  - Merge split: tile t starts at the point t*M of the merged sequence.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spl {
+namespace {
+
+// Number of rows r in [0, rows) with pos[r+1] <= p (binary search; pos is
+// non-decreasing).
+__device__ __forceinline__ int64_t rows_finished(const int32_t *pos, int64_t rows, int64_t p) {
+    int64_t lo = 0, hi = rows;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (static_cast<int64_t>(pos[mid + 1]) <= p)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_bounds(int64_t rows, const int32_t *pos,
+                                                       int64_t R, int64_t ntiles,
+                                                       int32_t *trow, int32_t *tpos) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t > ntiles) return;
+    int64_t r = t * R < rows ? t * R : rows;
+    trow[t] = static_cast<int32_t>(r);
+    tpos[t] = pos[r];
+}
+
+__global__ __launch_bounds__(kBlock) void k_nnz_bounds(int64_t rows, const int32_t *pos,
+                                                       int64_t nnz, int64_t T, int64_t ntiles,
+                                                       int32_t *trow, int32_t *tpos) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t > ntiles) return;
+    int64_t p = (t == ntiles || t * T > nnz) ? nnz : t * T;
+    tpos[t] = static_cast<int32_t>(p);
+    trow[t] = static_cast<int32_t>(t == 0 ? 0 : rows_finished(pos, rows, p));
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const int32_t *pos,
+                                                         int64_t nnz, int64_t M, int64_t ntiles,
+                                                         int32_t *trow, int32_t *tpos) {
+    int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t > ntiles) return;
+    int64_t total = rows + nnz;
+    int64_t d = (t == ntiles || t * M > total) ? total : t * M;
+    int64_t i = merge_search(d, rows, nnz, 0, [&](int64_t k) { return pos[k + 1]; });
+    trow[t] = static_cast<int32_t>(i);
+    tpos[t] = static_cast<int32_t>(d - i);
+}
+
+}  // namespace
+
+int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size) {
+    int64_t items = kind == SPL_ROW ? rows : kind == SPL_NNZ ? nnz : rows + nnz;
+    int64_t nt = (items + size - 1) / size;
+    return nt > 0 ? nt : 1;
+}
+
+hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_t nnz,
+                              int64_t size, const Tiles &t, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((t.ntiles + 1 + kBlock - 1) / kBlock));
+    switch (kind) {
+    case SPL_ROW:
+        k_row_bounds<<<grid, kBlock, 0, s>>>(rows, pos, size, t.ntiles, t.row, t.pos);
+        break;
+    case SPL_NNZ:
+        k_nnz_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
+        break;
+    default:
+        k_merge_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spl

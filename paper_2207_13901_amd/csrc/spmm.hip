@@ -1,0 +1,292 @@
+// SpMM leaf  A(i,j) = B(i,k) * C(k,j)  for CSR B and row-major dense C
+// (paper Sec. VI-A).  The dense operand is named `Bd` here and the output
+// `Out` to keep the sparse operand's name B.
+//
+// A lane group of W lanes (W = col_tile) owns W consecutive dense columns:
+// lane l accumulates column blockIdx.y*W + l, so every gathered row of Bd is
+// one coalesced W-element read (128 bytes for W = 32 FP32 columns).
+//
+//  * k_spmm_row: row split; group g of the workgroup owns one row.  The
+//    row's crd/vals are read W at a time by the group's lanes (coalesced) and
+//    broadcast with shuffles, then one Bd row is gathered per position.
+//
+//  * k_spmm_tiles: non-zero or merge split (the load-balanced GPU SpMM
+//    schedule of Sec. VI-A, GPU results).  A workgroup owns one tile of the
+//    merged (row ends, positions) sequence and processes it in chunks of
+//    G*ITEMS items (G = 256/W groups).  The chunk's row ends, crd and vals are
+//    staged in LDS; each group walks ITEMS consecutive merged items, first
+//    issuing all of its Bd gathers (up to ITEMS rows in flight per group) and
+//    then consuming them in order.  Rows a group finishes after its first
+//    are written directly; the first finished row and the row left open are
+//    combined across groups in order by group 0 (G steps), and the row open
+//    at the tile end is written to the tile's carry vector.  k_spmm_fixup adds
+//    carries into their rows in tile order.  Deterministic, no atomics.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spl {
+namespace {
+
+template <int W, typename V, typename BT, typename OT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_spmm_row(int64_t n, int64_t N,
+                                                     const int32_t *__restrict__ pos,
+                                                     const int32_t *__restrict__ crd,
+                                                     const V *__restrict__ vals,
+                                                     const BT *__restrict__ Bd, int64_t ldb,
+                                                     OT *__restrict__ Out, int64_t ldo) {
+    constexpr int G = kBlock / W;
+    const int g = threadIdx.x / W, lane = threadIdx.x % W;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * G + g;
+    const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
+    const bool colok = col < N;
+    Acc acc = 0;
+    if (row < n) {
+        const int p0 = pos[row], p1 = pos[row + 1];
+        for (int base = p0; base < p1; base += W) {
+            const int cnt = min(W, p1 - base);
+            int my_c = 0;
+            Acc my_v = 0;
+            if (lane < cnt) {
+                my_c = load_stream(crd + base + lane);
+                my_v = widen<Acc>(load_stream(vals + base + lane));
+            }
+            // eight gathers in flight per lane, then eight FMAs
+            for (int k0 = 0; k0 < cnt; k0 += 8) {
+                Acc bv[8], vv[8];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    const int k = (k0 + kk) & (W - 1);
+                    const int c = __shfl(my_c, k, W);
+                    vv[kk] = __shfl(my_v, k, W);
+                    bv[kk] = (k0 + kk < cnt && colok)
+                                 ? widen<Acc>(Bd[static_cast<int64_t>(c) * ldb + col])
+                                 : Acc(0);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) acc += vv[kk] * bv[kk];
+            }
+        }
+        if (colok) Out[row * ldo + col] = narrow<OT>(acc);
+    }
+}
+
+template <int W, int ITEMS, typename V, typename BT, typename OT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_spmm_tiles(
+    int64_t n, int64_t N, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
+    int64_t ldo, const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos,
+    Acc *__restrict__ carry) {
+    constexpr int G = kBlock / W;
+    constexpr int kChunk = G * ITEMS;
+    __shared__ int32_t s_end[kChunk];
+    __shared__ int32_t s_crd[kChunk];
+    __shared__ Acc s_val[kChunk];
+    __shared__ Acc s_head[G][W];
+    __shared__ Acc s_tail[G][W];
+    __shared__ int s_done[G];
+    __shared__ int s_a0[G];
+    __shared__ int64_t s_next[2];
+
+    const int tid = threadIdx.x;
+    const int g = tid / W, lane = tid % W;
+    const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
+    const bool colok = col < N;
+    const int64_t t = blockIdx.x;
+    const int64_t i_end = trow[t + 1], p_end = tpos[t + 1];
+    int64_t ci = trow[t], cp = tpos[t];
+    Acc open = 0;  // group 0: partial of row ci carried between chunks
+
+    for (;;) {
+        if (tid == 0) {
+            int64_t d = ci + cp + kChunk;
+            int64_t ei = i_end, ep = p_end;
+            if (d < i_end + p_end) {
+                int64_t k = merge_search(d - ci - cp, i_end - ci, p_end - cp, cp,
+                                         [&](int64_t m) { return pos[ci + m + 1]; });
+                ei = ci + k;
+                ep = d - ei;
+            }
+            s_next[0] = ei;
+            s_next[1] = ep;
+        }
+        __syncthreads();
+        const int64_t ei = s_next[0], ep = s_next[1];
+        const int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
+        for (int k = tid; k < nr; k += kBlock) s_end[k] = pos[ci + 1 + k];
+        for (int k = tid; k < np; k += kBlock) {
+            s_crd[k] = load_stream(crd + cp + k);
+            s_val[k] = widen<Acc>(load_stream(vals + cp + k));
+        }
+        __syncthreads();
+
+        const int total = nr + np;
+        const int d0 = min(g * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        auto end_at = [&](int64_t m) { return s_end[m]; };
+        const int a0 = static_cast<int>(merge_search(d0, nr, np, cp, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, np, cp, end_at));
+        const int b0 = d0 - a0, b1 = d1 - a1;
+
+        // Issue every gather of this group's positions before consuming any.
+        Acc pv[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            pv[k] = 0;
+            if (b0 + k < b1 && colok)
+                pv[k] = s_val[b0 + k] *
+                        widen<Acc>(Bd[static_cast<int64_t>(s_crd[b0 + k]) * ldb + col]);
+        }
+        Acc acc = 0;
+        int a = a0;
+        bool first = true;
+        auto finish = [&](int r) {
+            if (first) {
+                s_head[g][lane] = acc;
+                first = false;
+            } else if (colok) {
+                Out[(ci + r) * ldo + col] = narrow<OT>(acc);
+            }
+            acc = 0;
+        };
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (b0 + k < b1) {
+                while (a < a1 && s_end[a] <= cp + b0 + k) finish(a++);
+                acc += pv[k];
+            }
+        }
+        while (a < a1) finish(a++);
+        s_tail[g][lane] = acc;
+        if (lane == 0) {
+            s_done[g] = a1 - a0;
+            s_a0[g] = a0;
+        }
+        __syncthreads();
+
+        if (g == 0) {
+            Acc c = open;
+            for (int gg = 0; gg < G; ++gg) {
+                if (s_done[gg] > 0) {
+                    const Acc v = c + s_head[gg][lane];
+                    if (colok) Out[(ci + s_a0[gg]) * ldo + col] = narrow<OT>(v);
+                    c = s_tail[gg][lane];
+                } else {
+                    c += s_tail[gg][lane];
+                }
+            }
+            open = c;
+        }
+        ci = ei;
+        cp = ep;
+        if (ci == i_end && cp == p_end) break;
+        __syncthreads();
+    }
+    if (g == 0 && colok) carry[t * N + col] = open;
+}
+
+// Add carry vectors into the row left open at each tile's end, summing a
+// run of tiles open on the same row in tile order (one lane per column).
+template <typename OT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_spmm_fixup(int64_t n, int64_t N,
+                                                       const int32_t *__restrict__ trow,
+                                                       int64_t ntiles, const Acc *__restrict__ carry,
+                                                       OT *__restrict__ Out, int64_t ldo) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (idx >= ntiles * N) return;
+    const int64_t t = idx / N, col = idx % N;
+    const int32_t r = trow[t + 1];
+    if (r >= n) return;
+    if (t > 0 && trow[t] == r) return;
+    Acc total = 0;
+    for (int64_t u = t; u < ntiles && trow[u + 1] == r; ++u) total += carry[u * N + col];
+    OT *o = Out + static_cast<int64_t>(r) * ldo + col;
+    *o = narrow<OT>(static_cast<Acc>(*o) + total);
+}
+
+template <typename V, typename BT, typename OT, typename Acc>
+struct SpmmTypes {
+    static hipError_t row(int W, int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
+                          const void *vals, const void *Bd, int64_t ldb, void *Out, int64_t ldo,
+                          hipStream_t s) {
+        auto go = [&](auto kern, int w) {
+            const int64_t G = kBlock / w;
+            dim3 grid(static_cast<unsigned>((n + G - 1) / G), static_cast<unsigned>((N + w - 1) / w));
+            if (grid.x == 0 || grid.y == 0) return hipSuccess;
+            kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
+                                         static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out), ldo);
+            return hipGetLastError();
+        };
+        switch (W) {
+        case 8: return go(k_spmm_row<8, V, BT, OT, Acc>, 8);
+        case 16: return go(k_spmm_row<16, V, BT, OT, Acc>, 16);
+        case 64: return go(k_spmm_row<64, V, BT, OT, Acc>, 64);
+        default: return go(k_spmm_row<32, V, BT, OT, Acc>, 32);
+        }
+    }
+
+    template <int W, int ITEMS>
+    static hipError_t tiles_w(int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
+                              const void *vals, const void *Bd, int64_t ldb, void *Out,
+                              int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
+        dim3 grid(static_cast<unsigned>(t.ntiles), static_cast<unsigned>((N + W - 1) / W));
+        if (grid.y == 0) return hipSuccess;
+        k_spmm_tiles<W, ITEMS, V, BT, OT, Acc><<<grid, kBlock, 0, s>>>(
+            n, N, pos, crd, static_cast<const V *>(vals), static_cast<const BT *>(Bd), ldb,
+            static_cast<OT *>(Out), ldo, t.row, t.pos, static_cast<Acc *>(carry));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t work = t.ntiles * N;
+        k_spmm_fixup<OT, Acc><<<dim3(static_cast<unsigned>((work + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
+            n, N, t.row, t.ntiles, static_cast<const Acc *>(carry), static_cast<OT *>(Out), ldo);
+        return hipGetLastError();
+    }
+
+    static hipError_t tiles(int W, int items, int64_t n, int64_t N, const int32_t *pos,
+                            const int32_t *crd, const void *vals, const void *Bd, int64_t ldb,
+                            void *Out, int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
+#define SPL_SPMM_ITEMS(Wv)                                                                  \
+    if (items <= 8) return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s); \
+    if (items <= 16) return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s); \
+    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s);
+        switch (W) {
+        case 8: SPL_SPMM_ITEMS(8)
+        case 16: SPL_SPMM_ITEMS(16)
+        case 64: SPL_SPMM_ITEMS(64)
+        default: SPL_SPMM_ITEMS(32)
+        }
+#undef SPL_SPMM_ITEMS
+    }
+};
+
+}  // namespace
+
+hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_t N,
+                           const int32_t *pos, const int32_t *crd, const void *vals,
+                           const void *Bd, int64_t ldb, void *Out, int64_t ldo, hipStream_t s) {
+    (void)otype;
+    if (vtype == SPL_F64)
+        return SpmmTypes<double, double, double, double>::row(col_tile, n, N, pos, crd, vals, Bd,
+                                                              ldb, Out, ldo, s);
+    if (vtype == SPL_F32)
+        return SpmmTypes<float, float, float, float>::row(col_tile, n, N, pos, crd, vals, Bd, ldb,
+                                                          Out, ldo, s);
+    return SpmmTypes<bf16, bf16, float, float>::row(col_tile, n, N, pos, crd, vals, Bd, ldb, Out,
+                                                    ldo, s);
+}
+
+hipError_t launch_spmm_tiles(int vtype, int otype, int col_tile, int items, int64_t n,
+                             int64_t N, const int32_t *pos, const int32_t *crd,
+                             const void *vals, const void *Bd, int64_t ldb, void *Out,
+                             int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
+    (void)otype;
+    if (vtype == SPL_F64)
+        return SpmmTypes<double, double, double, double>::tiles(col_tile, items, n, N, pos, crd,
+                                                                vals, Bd, ldb, Out, ldo, t, carry, s);
+    if (vtype == SPL_F32)
+        return SpmmTypes<float, float, float, float>::tiles(col_tile, items, n, N, pos, crd, vals,
+                                                            Bd, ldb, Out, ldo, t, carry, s);
+    return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, n, N, pos, crd, vals, Bd,
+                                                      ldb, Out, ldo, t, carry, s);
+}
+
+}  // namespace spl

@@ -1,0 +1,254 @@
+// SpMV leaf  a(i) = B(i,j) * c(j)  for CSR B (paper Sec. VI-A, leaf loop of
+// Fig. 8b), on one GPU.
+//
+// Two kernel families, one per partition kind:
+//
+//  * k_spmv_row<L>: row split.  A group of L lanes owns one row (a universe
+//    partition of the rows into blocks of 256/L per workgroup, image to the
+//    positions).  No carries: every row is finished by the group that owns
+//    it.  Good for short, even rows; a long row serializes on its group.
+//
+//  * k_spmv_tiles: non-zero or merge split.  A workgroup owns one tile of
+//    the merged (row ends, positions) sequence, whose bounds come from
+//    partition.hip.  The tile is processed in chunks of 256*ITEMS merged
+//    items: the chunk's products vals[p]*c[crd[p]] and row ends are staged in
+//    LDS with coalesced loads, every lane walks ITEMS consecutive merged
+//    items (a merge-path split inside the chunk, so empty and long rows cost
+//    the same as positions), and the partial sum a lane holds for the row it
+//    is inside when its items run out is combined with its neighbours' by a
+//    wavefront segmented scan (xor/up shuffles) plus a 4-entry cross-wave
+//    pass through LDS.  The sum of the row still open at the end of the tile
+//    is the tile's carry; k_spmv_fixup adds carries into their rows in tile
+//    order after the leaf kernel, the reduction into boundary rows that the
+//    non-zero algorithm of Sec. II-D requires.  No floating-point atomics,
+//    so results are bitwise reproducible.
+//
+// Accumulation is in double for both double and float data (a float output
+// is rounded once from the double sum, then once more if a carry lands on it).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spl {
+namespace {
+
+template <int L, typename V>
+__global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *__restrict__ pos,
+                                                     const int32_t *__restrict__ crd,
+                                                     const V *__restrict__ vals,
+                                                     const V *__restrict__ x, V *__restrict__ y) {
+    constexpr int kRows = kBlock / L;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * kRows + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    double acc = 0.0;
+    if (row < n) {
+        const int p0 = pos[row], p1 = pos[row + 1];
+        int p = p0 + lane;
+        // two independent partial sums keep two gathers in flight per lane
+        double acc2 = 0.0;
+        for (; p + L < p1; p += 2 * L) {
+            acc += to_f64(load_stream(vals + p)) * to_f64(x[load_stream(crd + p)]);
+            acc2 += to_f64(load_stream(vals + p + L)) * to_f64(x[load_stream(crd + p + L)]);
+        }
+        if (p < p1) acc += to_f64(load_stream(vals + p)) * to_f64(x[load_stream(crd + p)]);
+        acc += acc2;
+    }
+    acc = group_sum<L>(acc);
+    if (row < n && lane == 0) y[row] = static_cast<V>(acc);
+}
+
+// Inclusive segmented sum across the 256 lanes of a workgroup.  Lanes are
+// ordered by key (non-decreasing); each lane ends with the sum of `v` over
+// all lanes up to itself that share its key.
+__device__ __forceinline__ double block_segmented_scan(double v, int key, int *s_first_key,
+                                                      int *s_last_key, double *s_last_val) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        double vu = __shfl_up(v, off);
+        int ku = __shfl_up(key, off);
+        if (lane >= off && ku == key) v += vu;
+    }
+    if (lane == 0) s_first_key[wave] = key;
+    if (lane == kWave - 1) {
+        s_last_key[wave] = key;
+        s_last_val[wave] = v;
+    }
+    __syncthreads();
+    for (int w = wave - 1; w >= 0; --w) {
+        if (s_last_key[w] != key) break;
+        v += s_last_val[w];
+        if (s_first_key[w] != key) break;
+    }
+    return v;
+}
+
+template <typename V, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_spmv_tiles(
+    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
+    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, double *__restrict__ carry) {
+    constexpr int kChunk = kBlock * ITEMS;
+    __shared__ double s_prod[kChunk];
+    __shared__ double s_out[kChunk];
+    __shared__ int32_t s_end[kChunk];
+    __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
+    __shared__ double s_last_val[kBlock / kWave];
+    __shared__ int64_t s_next[2];
+    __shared__ double s_open;
+
+    const int tid = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t i_end = trow[t + 1], p_end = tpos[t + 1];
+    int64_t ci = trow[t], cp = tpos[t];
+    double open = 0.0;  // partial sum of row ci carried between chunks
+
+    for (;;) {
+        // Chunk end: the merge-path point kChunk items further, or the tile end.
+        if (tid == 0) {
+            int64_t d = ci + cp + kChunk;
+            int64_t ei = i_end, ep = p_end;
+            if (d < i_end + p_end) {
+                // search rows [ci, i_end] for the split of diagonal d
+                int64_t k = merge_search(d - ci - cp, i_end - ci, p_end - cp, cp,
+                                         [&](int64_t m) { return pos[ci + m + 1]; });
+                ei = ci + k;
+                ep = d - ei;
+            }
+            s_next[0] = ei;
+            s_next[1] = ep;
+        }
+        __syncthreads();
+        const int64_t ei = s_next[0], ep = s_next[1];
+        const int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
+
+        for (int k = tid; k < nr; k += kBlock) s_end[k] = pos[ci + 1 + k];
+        for (int k = tid; k < np; k += kBlock) {
+            const int64_t p = cp + k;
+            s_prod[k] = to_f64(load_stream(vals + p)) * to_f64(x[load_stream(crd + p)]);
+        }
+        __syncthreads();
+
+        // This lane's share of the chunk's merged items.
+        const int total = nr + np;
+        const int d0 = min(tid * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        int a = static_cast<int>(merge_search(d0, nr, np, cp, [&](int64_t m) { return s_end[m]; }));
+        int b = d0 - a;
+        double acc = tid == 0 ? open : 0.0;
+#pragma unroll
+        for (int s = 0; s < ITEMS; ++s) {
+            if (d0 + s < d1) {
+                if (a < nr && s_end[a] <= cp + b) {
+                    s_out[a] = acc;  // row a finished by this lane
+                    acc = 0.0;
+                    ++a;
+                } else {
+                    acc += s_prod[b];
+                    ++b;
+                }
+            }
+        }
+        // `acc` belongs to row a (a == nr: the row still open at chunk end).
+        double v = block_segmented_scan(acc, a, s_first_key, s_last_key, s_last_val);
+        // The last lane of each run of equal keys holds the run total; the
+        // key of the next lane comes from a shuffle inside the wave and from
+        // the next wave's first key (stored by the scan) at a wave edge.
+        int next_key = __shfl_down(a, 1);
+        const int lane = tid & (kWave - 1), wave = tid / kWave;
+        if (lane == kWave - 1) next_key = wave + 1 < kBlock / kWave ? s_first_key[wave + 1] : -1;
+        if (next_key != a) {
+            if (a < nr)
+                s_out[a] += v;
+            else
+                s_open = v;
+        }
+        __syncthreads();
+        for (int k = tid; k < nr; k += kBlock) y[ci + k] = static_cast<V>(s_out[k]);
+        open = s_open;
+        ci = ei;
+        cp = ep;
+        if (ci == i_end && cp == p_end) break;
+        __syncthreads();
+    }
+    if (tid == 0) carry[t] = open;
+}
+
+// Add each tile's carry into the row still open at its end.  The first tile
+// of a run of tiles open on the same row sums the run's carries in tile
+// order, so the result does not depend on scheduling.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_spmv_fixup(int64_t n, const int32_t *__restrict__ trow,
+                                                       int64_t ntiles, const double *__restrict__ carry,
+                                                       V *__restrict__ y) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t >= ntiles) return;
+    const int32_t r = trow[t + 1];
+    if (r >= n) return;
+    if (t > 0 && trow[t] == r) return;  // not the first tile open on row r
+    double total = 0.0;
+    for (int64_t u = t; u < ntiles && trow[u + 1] == r; ++u) total += carry[u];
+    y[r] = static_cast<V>(static_cast<double>(y[r]) + total);
+}
+
+template <typename V>
+hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int32_t *crd,
+                             const V *vals, const V *x, V *y, hipStream_t s) {
+    auto go = [&](auto kern, int rows_per_block) {
+        int64_t blocks = (n + rows_per_block - 1) / rows_per_block;
+        if (blocks == 0) return hipSuccess;
+        kern<<<dim3(static_cast<unsigned>(blocks)), kBlock, 0, s>>>(n, pos, crd, vals, x, y);
+        return hipGetLastError();
+    };
+    switch (lanes) {
+    case 1: return go(k_spmv_row<1, V>, 256);
+    case 2: return go(k_spmv_row<2, V>, 128);
+    case 4: return go(k_spmv_row<4, V>, 64);
+    case 8: return go(k_spmv_row<8, V>, 32);
+    case 16: return go(k_spmv_row<16, V>, 16);
+    case 32: return go(k_spmv_row<32, V>, 8);
+    default: return go(k_spmv_row<64, V>, 4);
+    }
+}
+
+template <typename V>
+hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const int32_t *crd,
+                               const V *vals, const V *x, V *y, const Tiles &t, double *carry,
+                               hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(t.ntiles));
+    if (items <= 4)
+        k_spmv_tiles<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos, carry);
+    else
+        k_spmv_tiles<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos, carry);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 fgrid(static_cast<unsigned>((t.ntiles + kBlock - 1) / kBlock));
+    k_spmv_fixup<V><<<fgrid, kBlock, 0, s>>>(n, t.row, t.ntiles, carry, y);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
+                           const int32_t *crd, const void *vals, const void *x, void *y,
+                           hipStream_t s) {
+    if (dtype == SPL_F64)
+        return spmv_row_dispatch<double>(lanes, n, pos, crd, static_cast<const double *>(vals),
+                                         static_cast<const double *>(x), static_cast<double *>(y), s);
+    return spmv_row_dispatch<float>(lanes, n, pos, crd, static_cast<const float *>(vals),
+                                    static_cast<const float *>(x), static_cast<float *>(y), s);
+}
+
+hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
+                             const int32_t *crd, const void *vals, const void *x, void *y,
+                             const Tiles &t, double *carry, hipStream_t s) {
+    if (dtype == SPL_F64)
+        return spmv_tiles_dispatch<double>(items, n, pos, crd, static_cast<const double *>(vals),
+                                           static_cast<const double *>(x),
+                                           static_cast<double *>(y), t, carry, s);
+    return spmv_tiles_dispatch<float>(items, n, pos, crd, static_cast<const float *>(vals),
+                                      static_cast<const float *>(x), static_cast<float *>(y), t,
+                                      carry, s);
+}
+
+}  // namespace spl
