@@ -1,0 +1,267 @@
+"""Benchmark of the sparse leaf path on one MI355X.
+
+Workload: the power-law CSR matrix of 2,000,000 x 2,000,000 with Pareto
+(alpha = 2) row degrees, 32,000,000 nonzeros and a degree cap of 50,000,
+uniform distinct columns, values uniform[-1, 1]; a dense vector of 2,000,000
+and a dense 2,000,000 x 32 row-major operand.  Inputs are generated on the
+GPU and resident in HBM before timing starts.
+
+One step is the whole hot path on that batch in FP32: the tile partition of
+the matrix, the SpMV leaf a = B c, the SpMM leaf A = B C and their carry
+fix-ups, each with the schedule the exhaustive autotuner picked (untimed,
+before warm-up).  `value` is GFLOP/s of the step (2 nnz + 2 nnz N flops).
+
+Besides the headline line it reports, from the same run:
+ - roofline: the dominant leaf kernel (SpMM) against the 8 TB/s HBM peak,
+   with its duration taken from HIP events the library records around that
+   kernel on its own stream during the timed steps;
+ - variants: FP64 SpMV/SpMM and BF16 SpMM (FP32 accumulation) with the same
+   schedules, and the row / non-zero / merge schedules compared;
+ - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_COLS = 32
+
+
+def algorithmic_bytes(n, m, nnz, N, vbytes, dbytes, obytes):
+    """Compulsory bytes of one leaf launch: pos, crd, vals read once, each
+    dense input row read once and each output row written once."""
+    spmv = 4 * (n + 1) + (4 + vbytes) * nnz + dbytes * m + obytes * n
+    spmm = 4 * (n + 1) + (4 + vbytes) * nnz + dbytes * m * N + obytes * n * N
+    return spmv, spmm
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="shrink the workload (testing only; the headline uses 1.0)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip variant measurements")
+    ap.add_argument("--profile", action="store_true",
+                    help="only the timed steps (for rocprofv3 runs)")
+    ap.add_argument("--sched-spmv", type=str, default=None,
+                    help="JSON schedule for SpMV instead of autotuning")
+    ap.add_argument("--sched-spmm", type=str, default=None,
+                    help="JSON schedule for SpMM instead of autotuning")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run a 1 GiB device copy first (counter scale reference)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2207_13901_amd as spl
+    from paper_2207_13901_amd import autotune
+    from paper_2207_13901_amd import _native as N
+    from workloads import configs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    c2 = configs.config2(device=dev, scale=args.scale, N=N_COLS)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    n = c2["n"]
+    nnz = int(c2["crd"].numel())
+    print(f"[bench] generated n={n} nnz={nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    def csr(dtype):
+        return spl.CSR(c2["pos"], c2["crd"], c2["vals"].to(dtype), (n, n))
+
+    B32, B64, B16 = csr(torch.float32), csr(torch.float64), csr(torch.bfloat16)
+    x32, x64 = c2["x"].to(torch.float32), c2["x"]
+    D32, D64, D16 = c2["B"].to(torch.float32), c2["B"], c2["B"].to(torch.float32).to(torch.bfloat16)
+    y32, y64 = torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float64, device=dev)
+    A32 = torch.empty(n, N_COLS, dtype=torch.float32, device=dev)
+    A64 = torch.empty(n, N_COLS, dtype=torch.float64, device=dev)
+
+    if args.calibrate:
+        # plain copy of 1 GiB: 1 GiB read + 1 GiB written per dispatch
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # -- exhaustive schedule search (untimed) ---------------------------------
+    reps = 3 if args.profile else 5
+    if args.sched_spmv:
+        best_v, res_v = json.loads(args.sched_spmv), []
+    else:
+        best_v, res_v = autotune.search(lambda s: (lambda: spl.spmv(B32, x32, y32, sched=s)),
+                                        autotune.SPMV_CANDIDATES, reps=reps)
+    if args.sched_spmm:
+        best_m, res_m = json.loads(args.sched_spmm), []
+    else:
+        best_m, res_m = autotune.search(lambda s: (lambda: spl.spmm(B32, D32, A32, sched=s)),
+                                        autotune.SPMM_CANDIDATES, reps=reps)
+    sv, sm = spl.schedule(**best_v), spl.schedule(**best_m)
+    ws_v = spl.workspace(N.OP_SPMV, B32, 1, sv)
+    ws_m = spl.workspace(N.OP_SPMM, B32, N_COLS, sm)
+    print(f"[bench] schedules spmv={best_v} spmm={best_m}", file=sys.stderr, flush=True)
+
+    def step():
+        spl.spmv(B32, x32, y32, sched=sv, ws=ws_v)
+        spl.spmm(B32, D32, A32, sched=sm, ws=ws_m)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    spl.timing_read(N.OP_SPMV)
+    spl.timing_read(N.OP_SPMM)
+    spl.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    spl.timing_enable(False)
+    lv, msv = spl.timing_read(N.OP_SPMV)
+    lm, msm = spl.timing_read(N.OP_SPMM)
+    ms_per_step = 1e3 * elapsed / args.steps
+    flops = 2.0 * nnz + 2.0 * nnz * N_COLS
+    gflops = flops / (ms_per_step * 1e-3) / 1e9
+
+    bytes_v32, bytes_m32 = algorithmic_bytes(n, n, nnz, N_COLS, 4, 4, 4)
+    spmm_ms = msm / max(lm, 1)
+    spmv_ms = msv / max(lv, 1)
+    achieved = bytes_m32 / (spmm_ms * 1e-3) / 1e9
+    out = {
+        "metric": "GFLOP/s + % HBM roofline (SpMV/SpMM/MTTKRP); BF16 & learned vs FP32 autotuned",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("CSR 2,000,000 x 2,000,000 power-law rows (Pareto alpha=2, "
+                         "32,000,000 nnz, cap 50,000), SpMV + SpMM with N=32, FP32, "
+                         "autotuned schedules") if args.scale == 1.0 else
+                        f"scaled power-law CSR n={n} nnz={nnz}",
+            "n": n, "nnz": nnz, "N": N_COLS,
+            "schedule_spmv": best_v, "schedule_spmm": best_m,
+        },
+        "roofline": {
+            "kernel": "SpMM leaf (k_spmm_tiles / k_spmm_row), FP32",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_m32,
+            "avg_launch_ms": round(spmm_ms, 5),
+            "launches": lm,
+        },
+        "kernels": {
+            "spmv_f32": {"avg_ms": round(spmv_ms, 5), "launches": lv,
+                         "GB_s": round(bytes_v32 / (spmv_ms * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(bytes_v32 / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "GFLOP_s": round(2 * nnz / (spmv_ms * 1e-3) / 1e9, 2)},
+            "spmm_f32": {"avg_ms": round(spmm_ms, 5), "launches": lm,
+                         "GB_s": round(achieved, 1),
+                         "frac_hbm": round(achieved / HBM_PEAK_GBS, 4),
+                         "GFLOP_s": round(2 * nnz * N_COLS / (spmm_ms * 1e-3) / 1e9, 2)},
+        },
+        "autotune": {
+            "spmv_ms": {json.dumps(c, sort_keys=True): round(t, 4) for c, t in res_v},
+            "spmm_ms": {json.dumps(c, sort_keys=True): round(t, 4) for c, t in res_m},
+        },
+    }
+
+    if not args.profile and not args.no_variants and res_v and res_m:
+        var = {}
+        bv64, bm64 = algorithmic_bytes(n, n, nnz, N_COLS, 8, 8, 8)
+        _, bm16 = algorithmic_bytes(n, n, nnz, N_COLS, 2, 2, 4)
+        for name, fn, nbytes, fl in (
+            ("spmv_f64", lambda: spl.spmv(B64, x64, y64, sched=sv), bv64, 2 * nnz),
+            ("spmm_f64", lambda: spl.spmm(B64, D64, A64, sched=sm), bm64, 2 * nnz * N_COLS),
+            ("spmm_bf16_f32acc", lambda: spl.spmm(B16, D16, A32, sched=sm), bm16, 2 * nnz * N_COLS),
+        ):
+            ms = autotune.time_call(fn, reps=10, warmup=3)
+            var[name] = {"ms": round(ms, 5), "GFLOP_s": round(fl / (ms * 1e-3) / 1e9, 2),
+                         "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the paper's fixed rules: SpMV row split, SpMM non-zero split
+        rule_v = min((t for c, t in res_v if c["kind"] == "row"))
+        rule_m = min((t for c, t in res_m if c["kind"] == "nnz"))
+        var["fixed_rules_vs_autotuned"] = {
+            "spmv_row_best_ms": round(rule_v, 5), "spmm_nnz_best_ms": round(rule_m, 5),
+            "spmv_autotuned_ms": round(min(t for _, t in res_v), 5),
+            "spmm_autotuned_ms": round(min(t for _, t in res_m), 5)}
+        out["variants"] = var
+
+    if not args.profile and not args.no_variants:
+        # memory-system ceilings the leaves run against
+        big = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB
+        ms = autotune.time_call(lambda: spl.probe(0, big), reps=5, warmup=2)
+        ceil = {"stream_read_GB_s": round(big.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
+        del big
+        for name, table, row_bytes in (("gather_4B_rows_from_8MB", x32, 4),
+                                       ("gather_8B_rows_from_16MB", x64, 8),
+                                       ("gather_128B_rows_from_256MB", D32, 128),
+                                       ("gather_256B_rows_from_512MB", D64, 256)):
+            ms = autotune.time_call(lambda: spl.probe(1, table, row_bytes=row_bytes, count=nnz),
+                                    reps=5, warmup=2)
+            ceil[name] = {"ms_per_nnz_gathers": round(ms, 5),
+                          "GB_s_useful": round(nnz * row_bytes / (ms * 1e-3) / 1e9, 1)}
+        out["ceilings"] = ceil
+
+    if not args.profile and not args.no_cpu:
+        import oracle
+        pos = c2["pos"].cpu().numpy()
+        crd = c2["crd"].cpu().numpy()
+        vals = c2["vals"].to(torch.float32).to(torch.float64).cpu().numpy()
+        xh = x32.to(torch.float64).cpu().numpy()
+        Dh = D32.to(torch.float64).cpu().numpy()
+        # sample: every row for SpMV, a contiguous row block for SpMM sized
+        # to about a quarter of the nonzeros
+        rows_m = int(np.searchsorted(pos, nnz // 4))
+        t1 = time.perf_counter()
+        oracle.spmv(pos, crd, vals, xh)
+        t2 = time.perf_counter()
+        oracle.spmm(pos[:rows_m + 1], crd[:pos[rows_m]], vals[:pos[rows_m]], Dh)
+        t3 = time.perf_counter()
+        flops_sample = 2.0 * nnz + 2.0 * int(pos[rows_m]) * N_COLS
+        out["cpu_baseline"] = {
+            "value": round(flops_sample / (t3 - t1) / 1e9, 4),
+            "unit": "GFLOP/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": (f"SpMV over all {n} rows ({nnz} nnz, {t2 - t1:.2f}s) + SpMM N=32 over "
+                       f"rows 0..{rows_m} ({int(pos[rows_m])} nnz, {t3 - t2:.2f}s); "
+                       "single-threaded long-double C loops"),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

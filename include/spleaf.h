@@ -182,6 +182,31 @@ spl_status spl_tile_bounds(spl_context *ctx, const spl_sparse *B,
  * Synchronizes on `stream`. */
 spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream);
 
+/* ---------------------------------------------------------- measurement */
+
+/* Kernel timing for roofline reports.  While enabled (enable != 0), every
+ * subsequent call brackets its leaf kernel -- the one that streams the
+ * sparse operand, not the tile-bound or carry fix-up kernels -- with a pair
+ * of hipEvents recorded on the call's own stream.  Disabling keeps the
+ * recorded pairs for spl_timing_read. */
+spl_status spl_timing_enable(spl_context *ctx, int enable);
+/* Wait for the recorded events of `op`, return how many leaf launches were
+ * recorded (*launches, host) and their summed duration in milliseconds
+ * (*total_ms, host), and forget them. */
+spl_status spl_timing_read(spl_context *ctx, spl_op op, int64_t *launches, double *total_ms);
+
+/* Memory-system probes that bound the leaf kernels from above.
+ *   kind 0: stream-read `bytes` of `buf` once (16-byte loads; `bytes` a
+ *           multiple of 16): the HBM read ceiling for streamed arrays.
+ *   kind 1: read `count` rows of `row_bytes` (4, 8, 32, 64, 128 or 256) at
+ *           pseudo-random row indices of the table `buf` of `bytes` bytes:
+ *           the ceiling for random dense-operand gathers.
+ * `out` (device) receives one double per workgroup (`blocks` of them, at
+ * least 1); `buf` must be 16-byte aligned. */
+spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
+                     int64_t row_bytes, int64_t count, double *out, int64_t blocks,
+                     spl_stream stream);
+
 /* ------------------------------------------------------------ kernels */
 
 /* SpMV  a(i) = B(i,j) * c(j)   (Sec. VI-A; the leaf of Fig. 8b).
@@ -199,6 +224,71 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
 spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                     spl_dense *A, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);
+
+/* SpTTV  A(i,j) = B(i,j,k) * c(k)   (Sec. VI-A).
+ * B CSF I x J x K; c vector K.  The output keeps B's (i,j) pattern
+ * (pattern-preserving output, Sec. V-B): A shares B's first two levels
+ * (A.pos = B.pos[1], A.crd = B.crd[1]) and only its values are written,
+ * one per fiber, into the vector A of length B->nfibers.  dtypes: vals, c, A
+ * all F64, or all F32 (F64 sums).  The schedule applies to the fiber level
+ * (fibers play the role of SpMV rows): ROW, NNZ or MERGE (default). */
+spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
+                     spl_dense *A, const spl_schedule *sched, void *workspace,
+                     size_t workspace_bytes, spl_stream stream);
+
+/* SpMTTKRP  A(i,l) = B(i,j,k) * C(j,l) * D(k,l)   (Sec. VI-A).
+ * B CSF I x J x K; C dense J x R; D dense K x R; A dense I x R, F32.
+ * dtypes (vals, C, D, A): (F32,F32,F32,F32) or (BF16,BF16,BF16,F32) with F32
+ * accumulation.  Schedules: MERGE (default; equal runs of the merged slice
+ * ends and fibers), NNZ (blocks of `tile` positions snapped to fiber starts:
+ * the fused non-zero partition), ROW (blocks of `tile` slices); col_tile 16,
+ * 32 or 64 rank columns per lane group. */
+spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
+                      const spl_dense *D, spl_dense *A, const spl_schedule *sched,
+                      void *workspace, size_t workspace_bytes, spl_stream stream);
+
+/* Inner product  a = B(i,j,k) * C(i,j,k)  (every index summed; order-2
+ * operands are accepted too).  B and C must share one pattern: identical
+ * pos and crd pointers (else SPL_ERR_UNSUPPORTED).  Values both F64 or both
+ * F32, summed in F64 with a fixed reduction order; the result is one double
+ * written to `out` (device). */
+spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C, double *out,
+                     const spl_schedule *sched, void *workspace, size_t workspace_bytes,
+                     spl_stream stream);
+
+/* SDDMM  A(i,j) = B(i,j) * C(i,k) * D(j,k)   (Sec. VI-A; the paper's last
+ * factor D(k,j) is stored here transposed, one row per column coordinate j).
+ * B CSR n x m; C dense n x K; D dense m x K.  The output keeps B's pattern
+ * (Sec. V-B): A is the vector of B->nnz output values (A.pos = B.pos,
+ * A.crd = B.crd).  dtypes (vals, C, D, A): all F64; all F32; or
+ * (F32, BF16, BF16, F32) with F32 accumulation.  sched->variant: 0 = vector
+ * ALU dot products (default), 1 = matrix cores (BF16 factors only, K a
+ * multiple of 32, ld a multiple of 8, 16-byte aligned factors).  Schedules:
+ * MERGE (default), NNZ, ROW. */
+spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
+                     const spl_dense *D, spl_dense *A, const spl_schedule *sched,
+                     void *workspace, size_t workspace_bytes, spl_stream stream);
+
+/* SpAdd3  A(i,j) = B(i,j) + C(i,j) + D(i,j)   (Sec. VI-A), assembled in
+ * two phases (Sec. V-B).  B, C, D CSR with equal dimensions.
+ * Symbolic phase: writes A_pos (n+1 entries, device) for the union of the
+ * three patterns and the output nonzero count to *nnz_out (host); it
+ * synchronizes on `stream` to read that count back.  Values are not read.
+ * Only the row split is accepted: sched kind NNZ or MERGE gives
+ * SPL_ERR_UNSUPPORTED (a non-zero split of a sum of CSR operands does not
+ * align their positions). */
+spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
+                               const spl_sparse *D, int32_t *A_pos, int64_t *nnz_out,
+                               const spl_schedule *sched, void *workspace,
+                               size_t workspace_bytes, spl_stream stream);
+/* Numeric phase: with A_pos from the symbolic phase, writes A_crd (strictly
+ * increasing per row, *nnz_out entries) and A_vals (same dtype as the
+ * operands, F64 or F32): each value sums the operands present at that
+ * coordinate in the order B, C, D; a sum that cancels to zero keeps its
+ * coordinate. */
+spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
+                              const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
+                              void *A_vals, const spl_schedule *sched, spl_stream stream);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,9 @@ from ._native import SpleafError
 
 __all__ = [
     "CSR", "CSF", "Context", "schedule", "spmv", "spmm", "tile_bounds",
-    "validate", "op_parse", "op_tin", "workspace_query", "SpleafError",
+    "validate", "op_parse", "op_tin", "workspace_query", "workspace", "SpleafError",
+    "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
+    "spadd3",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -173,21 +175,30 @@ def workspace_query(op: int, B, ncols: int = 1, sched=None,
     return nbytes.value
 
 
-def _workspace(op, B, ncols, sched, ctx, device):
+def _workspace(op, B, ncols, sched, ctx, device, given=None):
+    if given is not None:
+        return given, given.numel()
     nbytes = workspace_query(op, B, ncols, sched, ctx)
     if nbytes == 0:
         return None, 0
     return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
 
 
+def workspace(op: int, B, ncols: int = 1, sched=None, ctx: Optional[Context] = None):
+    """A uint8 device tensor large enough for one call of `op` (or None)."""
+    dev = B.vals.device
+    ws, _ = _workspace(op, B, ncols, sched, ctx or Context.get(dev.index), dev)
+    return ws
+
+
 def spmv(B: CSR, c: torch.Tensor, a: Optional[torch.Tensor] = None, sched=None,
-         ctx: Optional[Context] = None) -> torch.Tensor:
+         ctx: Optional[Context] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """a(i) = B(i,j) * c(j)."""
     ctx, stream = _ctx_stream(B.vals, ctx)
     if a is None:
         a = torch.empty(B.shape[0], dtype=B.vals.dtype, device=B.vals.device)
     s = B.struct()
-    ws, nb = _workspace(N.OP_SPMV, B, 1, sched, ctx, B.vals.device)
+    ws, nb = _workspace(N.OP_SPMV, B, 1, sched, ctx, B.vals.device, ws)
     ctx.check(ctx.lib.spl_spmv(ctx.h, ctypes.byref(s), ctypes.byref(_dense(c)),
                                ctypes.byref(_dense(a)),
                                ctypes.byref(sched) if sched else None,
@@ -196,14 +207,14 @@ def spmv(B: CSR, c: torch.Tensor, a: Optional[torch.Tensor] = None, sched=None,
 
 
 def spmm(B: CSR, C: torch.Tensor, A: Optional[torch.Tensor] = None, sched=None,
-         ctx: Optional[Context] = None) -> torch.Tensor:
+         ctx: Optional[Context] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """A(i,j) = B(i,k) * C(k,j); BF16 inputs give an FP32 output."""
     ctx, stream = _ctx_stream(B.vals, ctx)
     if A is None:
         odt = torch.float32 if C.dtype == torch.bfloat16 else C.dtype
         A = torch.empty(B.shape[0], C.shape[1], dtype=odt, device=C.device)
     s = B.struct()
-    ws, nb = _workspace(N.OP_SPMM, B, C.shape[1], sched, ctx, B.vals.device)
+    ws, nb = _workspace(N.OP_SPMM, B, C.shape[1], sched, ctx, B.vals.device, ws)
     ctx.check(ctx.lib.spl_spmm(ctx.h, ctypes.byref(s), ctypes.byref(_dense(C)),
                                ctypes.byref(_dense(A)),
                                ctypes.byref(sched) if sched else None,
@@ -246,3 +257,117 @@ def op_parse(tin: str) -> int:
     if st != N.OK:
         raise SpleafError(st, f"not one of the supported statements: {tin!r}")
     return out.value
+
+
+def timing_enable(enable: bool = True, ctx: Optional[Context] = None) -> None:
+    """Bracket every subsequent leaf kernel with HIP events on its stream."""
+    ctx = ctx or Context.get()
+    ctx.check(ctx.lib.spl_timing_enable(ctx.h, int(enable)), "spl_timing_enable")
+
+
+def timing_read(op: int, ctx: Optional[Context] = None):
+    """(launches, total_ms) of the leaf kernels of `op` recorded so far."""
+    ctx = ctx or Context.get()
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    ctx.check(ctx.lib.spl_timing_read(ctx.h, op, ctypes.byref(n), ctypes.byref(ms)),
+              "spl_timing_read")
+    return n.value, ms.value
+
+
+def probe(kind: int, buf: torch.Tensor, row_bytes: int = 128, count: int = 0,
+          blocks: int = 4096, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Memory-system probe (kind 0: stream-read `buf`; kind 1: `count`
+    random `row_bytes` reads from table `buf`).  Returns the per-workgroup
+    partial sums (device)."""
+    ctx, stream = _ctx_stream(buf, ctx)
+    out = torch.empty(blocks, dtype=torch.float64, device=buf.device)
+    nbytes = buf.numel() * buf.element_size()
+    ctx.check(ctx.lib.spl_probe(ctx.h, kind, buf.data_ptr(), nbytes, row_bytes, count,
+                                out.data_ptr(), blocks, stream), "spl_probe")
+    return out
+
+
+def _sched_ptr(sched):
+    return ctypes.byref(sched) if sched else None
+
+
+def spttv(B: CSF, c: torch.Tensor, A: Optional[torch.Tensor] = None, sched=None,
+          ctx: Optional[Context] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A(i,j) = B(i,j,k) * c(k): returns the values of A, one per fiber of B
+    (A's pos/crd are B's pos1/crd1)."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if A is None:
+        A = torch.empty(B.crd1.numel(), dtype=B.vals.dtype, device=B.vals.device)
+    s = B.struct()
+    ws, nb = _workspace(N.OP_SPTTV, B, 1, sched, ctx, B.vals.device, ws)
+    ctx.check(ctx.lib.spl_spttv(ctx.h, ctypes.byref(s), ctypes.byref(_dense(c)),
+                                ctypes.byref(_dense(A)), _sched_ptr(sched), _ptr(ws), nb,
+                                stream), "spl_spttv")
+    return A
+
+
+def mttkrp(B: CSF, C: torch.Tensor, D: torch.Tensor, A: Optional[torch.Tensor] = None,
+           sched=None, ctx: Optional[Context] = None,
+           ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A(i,l) = B(i,j,k) * C(j,l) * D(k,l); FP32 output."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if A is None:
+        A = torch.empty(B.shape[0], C.shape[1], dtype=torch.float32, device=C.device)
+    s = B.struct()
+    ws, nb = _workspace(N.OP_MTTKRP, B, C.shape[1], sched, ctx, B.vals.device, ws)
+    ctx.check(ctx.lib.spl_mttkrp(ctx.h, ctypes.byref(s), ctypes.byref(_dense(C)),
+                                 ctypes.byref(_dense(D)), ctypes.byref(_dense(A)),
+                                 _sched_ptr(sched), _ptr(ws), nb, stream), "spl_mttkrp")
+    return A
+
+
+def inner(B, C, out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None,
+          ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """a = sum of B * C over the shared pattern; a one-element float64 tensor."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=B.vals.device)
+    sb, sc = B.struct(), C.struct()
+    ws, nb = _workspace(N.OP_INNER, B, 1, None, ctx, B.vals.device, ws)
+    ctx.check(ctx.lib.spl_inner(ctx.h, ctypes.byref(sb), ctypes.byref(sc), out.data_ptr(),
+                                None, _ptr(ws), nb, stream), "spl_inner")
+    return out
+
+
+def sddmm(B: CSR, C: torch.Tensor, D: torch.Tensor, A: Optional[torch.Tensor] = None,
+          sched=None, ctx: Optional[Context] = None,
+          ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A(i,j) = B(i,j) * C(i,k) * D(j,k) on B's pattern: returns A's values."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if A is None:
+        A = torch.empty(B.crd.numel(), dtype=B.vals.dtype, device=B.vals.device)
+    s = B.struct()
+    ws, nb = _workspace(N.OP_SDDMM, B, C.shape[1], sched, ctx, B.vals.device, ws)
+    ctx.check(ctx.lib.spl_sddmm(ctx.h, ctypes.byref(s), ctypes.byref(_dense(C)),
+                                ctypes.byref(_dense(D)), ctypes.byref(_dense(A)),
+                                _sched_ptr(sched), _ptr(ws), nb, stream), "spl_sddmm")
+    return A
+
+
+def spadd3(B: CSR, C: CSR, D: CSR, sched=None, ctx: Optional[Context] = None) -> CSR:
+    """A = B + C + D, assembled in two phases (the symbolic phase reads the
+    output size back to the host to allocate A)."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    dev = B.vals.device
+    n = B.shape[0]
+    sb, sc, sd = B.struct(), C.struct(), D.struct()
+    apos = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ws, nb = _workspace(N.OP_SPADD3, B, 1, None, ctx, dev)
+    nnz = ctypes.c_int64()
+    ctx.check(ctx.lib.spl_spadd3_symbolic(ctx.h, ctypes.byref(sb), ctypes.byref(sc),
+                                          ctypes.byref(sd), apos.data_ptr(), ctypes.byref(nnz),
+                                          _sched_ptr(sched), _ptr(ws), nb, stream),
+              "spl_spadd3_symbolic")
+    acrd = torch.empty(nnz.value, dtype=torch.int32, device=dev)
+    avals = torch.empty(nnz.value, dtype=B.vals.dtype, device=dev)
+    ctx.check(ctx.lib.spl_spadd3_numeric(ctx.h, ctypes.byref(sb), ctypes.byref(sc),
+                                         ctypes.byref(sd), apos.data_ptr(), _ptr(acrd),
+                                         _ptr(avals), _sched_ptr(sched), stream),
+              "spl_spadd3_numeric")
+    return CSR(apos, acrd, avals, B.shape)

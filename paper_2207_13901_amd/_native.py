@@ -75,8 +75,18 @@ SIGNATURES = {
     "spl_workspace_query": (_I32, [_P, _I32, _SP, _I64, _SCH, ctypes.POINTER(_SZ)]),
     "spl_tile_bounds": (_I32, [_P, _SP, _SCH, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "spl_validate": (_I32, [_P, _SP, _P]),
+    "spl_timing_enable": (_I32, [_P, ctypes.c_int]),
+    "spl_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
+    "spl_probe": (_I32, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _I64, _P]),
     "spl_spmv": (_I32, [_P, _SP, _DP, _DP, _SCH, _P, _SZ, _P]),
     "spl_spmm": (_I32, [_P, _SP, _DP, _DP, _SCH, _P, _SZ, _P]),
+    "spl_spttv": (_I32, [_P, _SP, _DP, _DP, _SCH, _P, _SZ, _P]),
+    "spl_mttkrp": (_I32, [_P, _SP, _DP, _DP, _DP, _SCH, _P, _SZ, _P]),
+    "spl_inner": (_I32, [_P, _SP, _SP, _P, _SCH, _P, _SZ, _P]),
+    "spl_sddmm": (_I32, [_P, _SP, _DP, _DP, _DP, _SCH, _P, _SZ, _P]),
+    "spl_spadd3_symbolic": (_I32, [_P, _SP, _SP, _SP, _P, ctypes.POINTER(_I64), _SCH, _P, _SZ,
+                                   _P]),
+    "spl_spadd3_numeric": (_I32, [_P, _SP, _SP, _SP, _P, _P, _P, _SCH, _P]),
 }
 
 _lib = None

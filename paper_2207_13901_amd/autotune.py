@@ -1,0 +1,56 @@
+"""Exhaustive schedule search for SpMV and SpMM.
+
+A schedule is a partition kind plus its tile parameters (spl_schedule).  The
+autotuner times every candidate on the operand it is given (the same calls a
+user makes; each timing brackets the whole call, tile bounds and carry
+fix-up included) and returns the fastest.  The candidate grids are bounded so
+that tuning stays cheap relative to the work it tunes.
+"""
+from __future__ import annotations
+
+from typing import Callable, Dict, List, Tuple
+
+import torch
+
+from . import schedule
+
+SPMV_CANDIDATES: List[Dict] = (
+    [dict(kind="row", lanes_per_row=L) for L in (1, 2, 4, 8, 16, 32, 64)] +
+    [dict(kind="nnz", tile=T, items_per_lane=8) for T in (1024, 2048, 4096)] +
+    [dict(kind="merge", tile=256 * it, items_per_lane=it) for it in (4, 8)]
+)
+
+SPMM_CANDIDATES: List[Dict] = (
+    [dict(kind="row", col_tile=32)] +
+    [dict(kind="nnz", tile=T, col_tile=32, items_per_lane=16) for T in (256, 1024)] +
+    [dict(kind="merge", tile=8 * it * k, col_tile=32, items_per_lane=it)
+     for it in (8, 16, 32) for k in (1, 4)]
+)
+
+
+def time_call(fn: Callable[[], object], reps: int = 5, warmup: int = 2) -> float:
+    """Median milliseconds of fn() over `reps` runs on the current stream."""
+    for _ in range(warmup):
+        fn()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def search(make_call: Callable[[object], Callable[[], object]], candidates: List[Dict],
+           reps: int = 5) -> Tuple[Dict, List[Tuple[Dict, float]]]:
+    """Time every candidate; return (best candidate, [(candidate, ms), ...])."""
+    results = []
+    for cand in candidates:
+        ms = time_call(make_call(schedule(**cand)), reps=reps)
+        results.append((cand, ms))
+    best = min(results, key=lambda r: r[1])[0]
+    return best, results

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "spleaf.h"
@@ -20,6 +21,14 @@ struct spl_context {
     void *ws = nullptr;   // context-owned workspace (used when the caller gives none)
     size_t ws_bytes = 0;
     int64_t *flags = nullptr;  // 2 x int64 device scratch for spl_validate
+    // leaf-kernel timing (spl_timing_enable / spl_timing_read)
+    struct Mark {
+        hipEvent_t start, stop;
+        int op;
+    };
+    bool timing = false;
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
 };
 
 namespace {
@@ -160,12 +169,6 @@ spl_status resolve_spmm(spl_context *ctx, const spl_sparse *B, int64_t N, const 
     return SPL_OK;
 }
 
-// Workspace of a tiled leaf: tile bounds then per-tile carries.
-size_t tiled_bytes(int64_t ntiles, int64_t carry_elems_per_tile, size_t carry_elem) {
-    return 2 * align_up(static_cast<size_t>(ntiles + 1) * 4) +
-           align_up(static_cast<size_t>(ntiles) * carry_elems_per_tile * carry_elem);
-}
-
 struct Carved {
     Tiles tiles;
     void *carry;
@@ -223,6 +226,40 @@ spl_status set_device(spl_context *ctx) {
     return SPL_OK;
 }
 
+hipEvent_t take_event(spl_context *ctx) {
+    if (!ctx->spare.empty()) {
+        hipEvent_t e = ctx->spare.back();
+        ctx->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets one leaf launch with events when timing is on.
+struct LeafTimer {
+    spl_context *ctx;
+    hipStream_t s;
+    int op;
+    hipEvent_t a = nullptr, b = nullptr;
+    LeafTimer(spl_context *c, int o, hipStream_t st) : ctx(c), s(st), op(o) {
+        if (!ctx->timing) return;
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    void stop() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, s);
+        ctx->marks.push_back({a, b, op});
+        a = b = nullptr;
+    }
+};
+
 #define SPL_CHECK(expr)                  \
     do {                                 \
         spl_status _st = (expr);         \
@@ -235,16 +272,130 @@ spl_status set_device(spl_context *ctx) {
         if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
     } while (0)
 
+// Tiled leaf layout: the level partition is cut into pieces (merge split:
+// pieces of exactly one chunk of the leaf kernel, so the kernel never
+// searches; non-zero split: pieces of T positions), and each workgroup walks
+// `stride` consecutive pieces, producing one carry.
+struct Pieces {
+    int64_t size;     // partition tile size of one piece
+    int64_t stride;   // pieces per workgroup
+    int64_t count;    // number of pieces
+    int64_t blocks;   // workgroups = carries
+};
+
+Pieces pieces_for(const Plan &p, int64_t rows, int64_t nnz, int64_t chunk) {
+    Pieces q;
+    if (p.kind == SPL_MERGE) {
+        q.size = chunk;
+        q.stride = std::max<int64_t>(1, (p.tile + chunk - 1) / chunk);
+    } else {
+        q.size = p.tile;
+        q.stride = 1;
+    }
+    q.count = spl::tile_count(p.kind, rows, nnz, q.size);
+    q.blocks = (q.count + q.stride - 1) / q.stride;
+    return q;
+}
+
+int64_t spmv_chunk(const Plan &p) { return 256 * p.items; }
+int64_t spmm_chunk(const Plan &p) { return (256 / p.col_tile) * p.items; }
+
+size_t tiled_ws(const Pieces &q, int64_t ncols, size_t elem) {
+    return 2 * align_up(static_cast<size_t>(q.count + 1) * 4) +
+           align_up(static_cast<size_t>(q.blocks) * ncols * elem);
+}
+
 size_t spmv_ws(const spl_sparse *B, const Plan &p) {
     if (p.kind == SPL_ROW) return 0;
-    const int64_t nt = spl::tile_count(p.kind, B->dims[0], B->nnz, p.tile);
-    return tiled_bytes(nt, 1, sizeof(double));
+    return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spmv_chunk(p)), 1, sizeof(double));
 }
 
 size_t spmm_ws(const spl_sparse *B, int64_t N, const Plan &p) {
     if (p.kind == SPL_ROW) return 0;
-    const int64_t nt = spl::tile_count(p.kind, B->dims[0], B->nnz, p.tile);
-    return tiled_bytes(nt, N, B->vtype == SPL_F64 ? 8 : 4);
+    return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spmm_chunk(p)), N,
+                    B->vtype == SPL_F64 ? 8 : 4);
+}
+
+// SpTTV runs the SpMV leaf on the fiber level: a CSR view whose rows are the
+// fibers of B (pos = pos[2], crd = crd[2]).
+spl_sparse fiber_view(const spl_sparse *B) {
+    spl_sparse v = *B;
+    v.order = 2;
+    v.dims[0] = B->nfibers;
+    v.dims[1] = B->dims[2];
+    v.dims[2] = 0;
+    v.pos[1] = B->pos[2];
+    v.crd[1] = B->crd[2];
+    v.level[2] = SPL_DENSE;
+    return v;
+}
+
+spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Plan &p) {
+    spl_schedule d{};
+    if (!s) s = &d;
+    p.kind = s->kind == SPL_SCHED_DEFAULT ? SPL_MERGE : s->kind;
+    if (p.kind != SPL_ROW && p.kind != SPL_NNZ && p.kind != SPL_MERGE)
+        return fail(ctx, SPL_ERR_ARG, "unknown schedule kind %d", s->kind);
+    int ct = s->col_tile;
+    if (!ct) {
+        ct = 16;
+        while (ct < 64 && ct < R) ct <<= 1;
+    }
+    if (ct != 16 && ct != 32 && ct != 64)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP col_tile must be 16, 32 or 64");
+    p.col_tile = ct;
+    p.items = s->items_per_lane ? s->items_per_lane : 16;
+    if (p.items != 8 && p.items != 16)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 8 or 16");
+    const int64_t chunk = (256 / ct) * p.items;
+    p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
+    if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
+    return SPL_OK;
+}
+
+int64_t mttkrp_chunk(const Plan &p) { return (256 / p.col_tile) * p.items; }
+
+// MTTKRP pieces live in (slice, fiber) coordinates.
+Pieces mttkrp_pieces(const spl_sparse *B, const Plan &p) {
+    Pieces q = pieces_for(p, B->dims[0], B->nfibers, mttkrp_chunk(p));
+    if (p.kind == SPL_NNZ) {
+        q.count = spl::tile_count(SPL_NNZ, 0, B->nnz, p.tile);
+        q.blocks = q.count;
+    }
+    return q;
+}
+
+size_t mttkrp_ws(const spl_sparse *B, int64_t R, const Plan &p) {
+    return tiled_ws(mttkrp_pieces(B, p), R, sizeof(float));
+}
+
+spl_status resolve_sddmm(spl_context *ctx, const spl_schedule *s, Plan &p) {
+    spl_schedule d{};
+    if (!s) s = &d;
+    p.kind = s->kind == SPL_SCHED_DEFAULT ? SPL_MERGE : s->kind;
+    if (p.kind != SPL_ROW && p.kind != SPL_NNZ && p.kind != SPL_MERGE)
+        return fail(ctx, SPL_ERR_ARG, "unknown schedule kind %d", s->kind);
+    p.tile = s->tile ? s->tile
+                     : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 1024 : 4 * spl::sddmm_chunk());
+    if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
+    p.items = s->variant;
+    return SPL_OK;
+}
+
+size_t sddmm_ws(const spl_sparse *B, const Plan &p) {
+    return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spl::sddmm_chunk()), 0, 1);
+}
+
+constexpr int64_t kInnerParts = 2048;
+
+size_t spadd3_ws(int64_t n) {
+    return align_up(static_cast<size_t>(spl::spadd3_scan_tiles(n)) * 8) + align_up(8);
+}
+
+bool same_dims(const spl_sparse *a, const spl_sparse *b) {
+    for (int l = 0; l < a->order; ++l)
+        if (a->dims[l] != b->dims[l]) return false;
+    return true;
 }
 
 // ------------------------------------------------------------- TIN parse
@@ -354,12 +505,54 @@ spl_status spl_context_destroy(spl_context *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->flags) (void)hipFree(ctx->flags);
+    for (const auto &m : ctx->marks) {
+        (void)hipEventDestroy(m.start);
+        (void)hipEventDestroy(m.stop);
+    }
+    for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
     delete ctx;
     return SPL_OK;
     SPL_GUARD_END
 }
 
 const char *spl_last_error(const spl_context *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+spl_status spl_timing_enable(spl_context *ctx, int enable) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    ctx->timing = enable != 0;
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_timing_read(spl_context *ctx, spl_op op, int64_t *launches, double *total_ms) {
+    SPL_GUARD_BEGIN
+    if (!ctx || !launches || !total_ms) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    SPL_CHECK(set_device(ctx));
+    int64_t count = 0;
+    double sum = 0.0;
+    std::vector<spl_context::Mark> keep;
+    spl_status st = SPL_OK;
+    for (const auto &m : ctx->marks) {
+        if (m.op != op) {
+            keep.push_back(m);
+            continue;
+        }
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(m.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.start, m.stop);
+        if (e != hipSuccess && st == SPL_OK) st = hip_fail(ctx, e, "hipEventElapsedTime");
+        sum += ms;
+        ++count;
+        ctx->spare.push_back(m.start);
+        ctx->spare.push_back(m.stop);
+    }
+    ctx->marks.swap(keep);
+    *launches = count;
+    *total_ms = sum;
+    return st;
+    SPL_GUARD_END
+}
 
 spl_status spl_sync(spl_context *ctx, spl_stream stream) {
     SPL_GUARD_BEGIN
@@ -412,6 +605,31 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
         SPL_CHECK(check_sparse(ctx, B, 2));
         SPL_CHECK(resolve_spmm(ctx, B, ncols, sched, p));
         *bytes = spmm_ws(B, ncols, p);
+        return SPL_OK;
+    case SPL_OP_SPTTV: {
+        SPL_CHECK(check_sparse(ctx, B, 3));
+        const spl_sparse v = fiber_view(B);
+        SPL_CHECK(resolve_spmv(ctx, &v, sched, p));
+        *bytes = spmv_ws(&v, p);
+        return SPL_OK;
+    }
+    case SPL_OP_MTTKRP:
+        SPL_CHECK(check_sparse(ctx, B, 3));
+        SPL_CHECK(resolve_mttkrp(ctx, ncols, sched, p));
+        *bytes = mttkrp_ws(B, ncols, p);
+        return SPL_OK;
+    case SPL_OP_SDDMM:
+        SPL_CHECK(check_sparse(ctx, B, 2));
+        SPL_CHECK(resolve_sddmm(ctx, sched, p));
+        *bytes = sddmm_ws(B, p);
+        return SPL_OK;
+    case SPL_OP_INNER:
+        if (!B) return fail(ctx, SPL_ERR_ARG, "sparse operand is NULL");
+        *bytes = align_up(kInnerParts * sizeof(double));
+        return SPL_OK;
+    case SPL_OP_SPADD3:
+        SPL_CHECK(check_sparse(ctx, B, 2));
+        *bytes = spadd3_ws(B->dims[0]);
         return SPL_OK;
     default:
         return fail(ctx, SPL_ERR_UNSUPPORTED, "op %d has no workspace query yet", op);
@@ -484,6 +702,34 @@ spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream
     SPL_GUARD_END
 }
 
+spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
+                     int64_t row_bytes, int64_t count, double *out, int64_t blocks,
+                     spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (!buf || !out) return fail(ctx, SPL_ERR_ARG, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0)
+        return fail(ctx, SPL_ERR_ARG, "buffer must be 16-byte aligned");
+    if (blocks < 1 || blocks > (1LL << 31) - 1) return fail(ctx, SPL_ERR_ARG, "bad block count");
+    if (kind == 0) {
+        if (bytes < 16 || bytes % 16 != 0)
+            return fail(ctx, SPL_ERR_ARG, "stream probe needs a positive multiple of 16 bytes");
+    } else if (kind == 1) {
+        if (row_bytes != 4 && row_bytes != 8 && row_bytes != 32 && row_bytes != 64 &&
+            row_bytes != 128 && row_bytes != 256)
+            return fail(ctx, SPL_ERR_ARG, "row_bytes must be 4, 8, 32, 64, 128 or 256");
+        if (bytes < row_bytes || count < 0) return fail(ctx, SPL_ERR_ARG, "bad table or count");
+    } else {
+        return fail(ctx, SPL_ERR_ARG, "unknown probe kind %d", kind);
+    }
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(spl::launch_probe(kind, buf, bytes, row_bytes, count, out, blocks,
+                              static_cast<hipStream_t>(stream)),
+            "probe launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
 spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, spl_dense *a,
                     const spl_schedule *sched, void *workspace, size_t workspace_bytes,
                     spl_stream stream) {
@@ -501,20 +747,27 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     const int64_t n = B->dims[0];
     if (n == 0) return SPL_OK;
     if (p.kind == SPL_ROW) {
+        LeafTimer tm(ctx, SPL_OP_SPMV, s);
         SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, B->pos[1], B->crd[1], B->vals, c->data,
                                      a->data, s),
                 "SpMV row launch");
+        tm.stop();
         return SPL_OK;
     }
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmv_ws(B, p), &ws));
-    const int64_t nt = spl::tile_count(p.kind, n, B->nnz, p.tile);
-    Carved cv = carve(ws, nt);
-    SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, p.tile, cv.tiles, s),
+    const Pieces q = pieces_for(p, n, B->nnz, spmv_chunk(p));
+    Carved cv = carve(ws, q.count);
+    SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
+    LeafTimer tm(ctx, SPL_OP_SPMV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, n, B->pos[1], B->crd[1], B->vals, c->data,
-                                   a->data, cv.tiles, static_cast<double *>(cv.carry), s),
+                                   a->data, cv.tiles, q.stride, static_cast<double *>(cv.carry), s),
             "SpMV tile launch");
+    tm.stop();
+    SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
+                                   static_cast<double *>(cv.carry), a->data, s),
+            "SpMV fix-up launch");
     return SPL_OK;
     SPL_GUARD_END
 }
@@ -542,21 +795,278 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     const int64_t n = B->dims[0];
     if (n == 0 || N == 0) return SPL_OK;
     if (p.kind == SPL_ROW) {
+        LeafTimer tm(ctx, SPL_OP_SPMM, s);
         SPL_HIP(spl::launch_spmm_row(B->vtype, A->dtype, p.col_tile, n, N, B->pos[1], B->crd[1],
                                      B->vals, C->data, C->ld, A->data, A->ld, s),
                 "SpMM row launch");
+        tm.stop();
         return SPL_OK;
     }
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmm_ws(B, N, p), &ws));
-    const int64_t nt = spl::tile_count(p.kind, n, B->nnz, p.tile);
-    Carved cv = carve(ws, nt);
-    SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, p.tile, cv.tiles, s),
+    const Pieces q = pieces_for(p, n, B->nnz, spmm_chunk(p));
+    Carved cv = carve(ws, q.count);
+    SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
+    LeafTimer tm(ctx, SPL_OP_SPMM, s);
     SPL_HIP(spl::launch_spmm_tiles(B->vtype, A->dtype, p.col_tile, p.items, n, N, B->pos[1],
                                    B->crd[1], B->vals, C->data, C->ld, A->data, A->ld, cv.tiles,
-                                   cv.carry, s),
+                                   q.stride, cv.carry, s),
             "SpMM tile launch");
+    tm.stop();
+    SPL_HIP(spl::launch_spmm_fixup(B->vtype, n, N, cv.tiles, q.stride, cv.carry, A->data, A->ld,
+                                   s),
+            "SpMM fix-up launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, spl_dense *A,
+                     const spl_schedule *sched, void *workspace, size_t workspace_bytes,
+                     spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 3));
+    SPL_CHECK(check_dense(ctx, c, "c", 1, B->dims[2], -1));
+    SPL_CHECK(check_dense(ctx, A, "A", 1, B->nfibers, -1));
+    if (B->vtype == SPL_BF16 || c->dtype != B->vtype || A->dtype != B->vtype)
+        return fail(ctx, SPL_ERR_DTYPE, "SpTTV needs vals, c and A all F64 or all F32");
+    const spl_sparse v = fiber_view(B);
+    Plan p;
+    SPL_CHECK(resolve_spmv(ctx, &v, sched, p));
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t F = B->nfibers;
+    if (F == 0) return SPL_OK;
+    if (p.kind == SPL_ROW) {
+        LeafTimer tm(ctx, SPL_OP_SPTTV, s);
+        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, F, v.pos[1], v.crd[1], B->vals, c->data,
+                                     A->data, s),
+                "SpTTV row launch");
+        tm.stop();
+        return SPL_OK;
+    }
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmv_ws(&v, p), &ws));
+    const Pieces q = pieces_for(p, F, B->nnz, spmv_chunk(p));
+    Carved cv = carve(ws, q.count);
+    SPL_HIP(spl::launch_tile_bounds(p.kind, F, v.pos[1], B->nnz, q.size, cv.tiles, s),
+            "tile bounds launch");
+    LeafTimer tm(ctx, SPL_OP_SPTTV, s);
+    SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, F, v.pos[1], v.crd[1], B->vals, c->data,
+                                   A->data, cv.tiles, q.stride, static_cast<double *>(cv.carry), s),
+            "SpTTV tile launch");
+    tm.stop();
+    SPL_HIP(spl::launch_spmv_fixup(B->vtype, F, cv.tiles, q.stride,
+                                   static_cast<double *>(cv.carry), A->data, s),
+            "SpTTV fix-up launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
+                      const spl_dense *D, spl_dense *A, const spl_schedule *sched,
+                      void *workspace, size_t workspace_bytes, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 3));
+    if (!C || !D) return fail(ctx, SPL_ERR_ARG, "dense factor is NULL");
+    const int64_t R = C->ndim == 2 ? C->dims[1] : -1;
+    SPL_CHECK(check_dense(ctx, C, "C", 2, B->dims[1], -1));
+    SPL_CHECK(check_dense(ctx, D, "D", 2, B->dims[2], R));
+    SPL_CHECK(check_dense(ctx, A, "A", 2, B->dims[0], R));
+    const bool ok = A->dtype == SPL_F32 &&
+                    ((B->vtype == SPL_F32 && C->dtype == SPL_F32 && D->dtype == SPL_F32) ||
+                     (B->vtype == SPL_BF16 && C->dtype == SPL_BF16 && D->dtype == SPL_BF16));
+    if (!ok)
+        return fail(ctx, SPL_ERR_DTYPE,
+                    "MTTKRP dtypes (vals, C, D, A) must be (F32,F32,F32,F32) or (BF16,BF16,BF16,F32)");
+    Plan p;
+    SPL_CHECK(resolve_mttkrp(ctx, R, sched, p));
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t I = B->dims[0];
+    if (I == 0 || R == 0) return SPL_OK;
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, mttkrp_ws(B, R, p), &ws));
+    const Pieces q = mttkrp_pieces(B, p);
+    Carved cv = carve(ws, q.count);
+    if (p.kind == SPL_NNZ)
+        SPL_HIP(spl::launch_csf_nnz_bounds(I, B->pos[1], B->nfibers, B->pos[2], B->nnz, p.tile,
+                                           cv.tiles, s),
+                "CSF bounds launch");
+    else
+        SPL_HIP(spl::launch_tile_bounds(p.kind, I, B->pos[1], B->nfibers, q.size, cv.tiles, s),
+                "tile bounds launch");
+    LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
+    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.col_tile, p.items, I, R, B->pos[1], B->crd[1],
+                                     B->pos[2], B->crd[2], B->vals, C->data, C->ld, D->data,
+                                     D->ld, static_cast<float *>(A->data), A->ld, cv.tiles,
+                                     q.stride, static_cast<float *>(cv.carry), s),
+            "MTTKRP tile launch");
+    tm.stop();
+    SPL_HIP(spl::launch_mttkrp_fixup(I, R, cv.tiles, q.stride, static_cast<float *>(cv.carry),
+                                     static_cast<float *>(A->data), A->ld, s),
+            "MTTKRP fix-up launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C, double *out,
+                     const spl_schedule *sched, void *workspace, size_t workspace_bytes,
+                     spl_stream stream) {
+    SPL_GUARD_BEGIN
+    (void)sched;
+    if (!ctx) return SPL_ERR_ARG;
+    if (!B || !C || !out) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    const int order = B->order;
+    if (order != 2 && order != 3) return fail(ctx, SPL_ERR_FORMAT, "order must be 2 or 3");
+    SPL_CHECK(check_sparse(ctx, B, order));
+    SPL_CHECK(check_sparse(ctx, C, order));
+    if (!same_dims(B, C) || B->nnz != C->nnz)
+        return fail(ctx, SPL_ERR_SHAPE, "operands differ in shape or nnz");
+    if (B->vtype != C->vtype || B->vtype == SPL_BF16)
+        return fail(ctx, SPL_ERR_DTYPE, "inner product needs both F64 or both F32 values");
+    for (int l = 1; l < order; ++l)
+        if (B->pos[l] != C->pos[l] || B->crd[l] != C->crd[l])
+            return fail(ctx, SPL_ERR_UNSUPPORTED,
+                        "operands must share one pattern (identical pos/crd arrays)");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
+                            align_up(kInnerParts * sizeof(double)), &ws));
+    LeafTimer tm(ctx, SPL_OP_INNER, s);
+    SPL_HIP(spl::launch_inner(B->vtype, B->nnz, B->vals, C->vals, static_cast<double *>(ws),
+                              kInnerParts, out, s),
+            "inner product launch");
+    tm.stop();
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
+                     const spl_dense *D, spl_dense *A, const spl_schedule *sched,
+                     void *workspace, size_t workspace_bytes, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    if (!C || !D) return fail(ctx, SPL_ERR_ARG, "dense factor is NULL");
+    const int64_t K = C->ndim == 2 ? C->dims[1] : -1;
+    SPL_CHECK(check_dense(ctx, C, "C", 2, B->dims[0], -1));
+    SPL_CHECK(check_dense(ctx, D, "D", 2, B->dims[1], K));
+    SPL_CHECK(check_dense(ctx, A, "A", 1, B->nnz, -1));
+    const bool ok = (B->vtype == SPL_F64 && C->dtype == SPL_F64 && D->dtype == SPL_F64 &&
+                     A->dtype == SPL_F64) ||
+                    (B->vtype == SPL_F32 && A->dtype == SPL_F32 && C->dtype == D->dtype &&
+                     (C->dtype == SPL_F32 || C->dtype == SPL_BF16));
+    if (!ok)
+        return fail(ctx, SPL_ERR_DTYPE,
+                    "SDDMM dtypes (vals, C, D, A) must be all F64, all F32 or (F32,BF16,BF16,F32)");
+    Plan p;
+    SPL_CHECK(resolve_sddmm(ctx, sched, p));
+    const int variant = p.items;
+    if (variant == 1) {
+        if (C->dtype != SPL_BF16)
+            return fail(ctx, SPL_ERR_UNSUPPORTED, "the matrix-core variant needs BF16 factors");
+        if (K % 32 != 0 || C->ld % 8 != 0 || D->ld % 8 != 0 ||
+            reinterpret_cast<uintptr_t>(C->data) % 16 != 0 ||
+            reinterpret_cast<uintptr_t>(D->data) % 16 != 0)
+            return fail(ctx, SPL_ERR_UNSUPPORTED,
+                        "the matrix-core variant needs K % 32 == 0, ld % 8 == 0 and 16-byte "
+                        "aligned factors");
+    } else if (variant != 0) {
+        return fail(ctx, SPL_ERR_ARG, "SDDMM variant must be 0 (VALU) or 1 (matrix cores)");
+    }
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = B->dims[0];
+    if (n == 0 || B->nnz == 0) return SPL_OK;
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, sddmm_ws(B, p), &ws));
+    const Pieces q = pieces_for(p, n, B->nnz, spl::sddmm_chunk());
+    Carved cv = carve(ws, q.count);
+    SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
+            "tile bounds launch");
+    LeafTimer tm(ctx, SPL_OP_SDDMM, s);
+    SPL_HIP(spl::launch_sddmm(B->vtype, C->dtype, variant, K, B->pos[1], B->crd[1], B->vals,
+                              C->data, C->ld, D->data, D->ld, A->data, cv.tiles, q.stride, s),
+            "SDDMM launch");
+    tm.stop();
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+namespace {
+spl_status check_spadd3(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
+                        const spl_sparse *D, const spl_schedule *sched) {
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    SPL_CHECK(check_sparse(ctx, C, 2));
+    SPL_CHECK(check_sparse(ctx, D, 2));
+    if (!same_dims(B, C) || !same_dims(B, D))
+        return fail(ctx, SPL_ERR_SHAPE, "SpAdd3 operands must have equal dimensions");
+    if (sched && sched->kind != SPL_SCHED_DEFAULT && sched->kind != SPL_ROW)
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "SpAdd3 on CSR supports only the row split (a non-zero split of a sum of "
+                    "CSR operands does not align their positions)");
+    return SPL_OK;
+}
+}  // namespace
+
+spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
+                               const spl_sparse *D, int32_t *A_pos, int64_t *nnz_out,
+                               const spl_schedule *sched, void *workspace,
+                               size_t workspace_bytes, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (!A_pos || !nnz_out) return fail(ctx, SPL_ERR_ARG, "NULL output");
+    SPL_CHECK(check_spadd3(ctx, B, C, D, sched));
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = B->dims[0];
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spadd3_ws(n), &ws));
+    int64_t *tile_sum = static_cast<int64_t *>(ws);
+    int64_t *total =
+        reinterpret_cast<int64_t *>(static_cast<char *>(ws) +
+                                    align_up(static_cast<size_t>(spl::spadd3_scan_tiles(n)) * 8));
+    LeafTimer tm(ctx, SPL_OP_SPADD3, s);
+    SPL_HIP(spl::launch_spadd3_symbolic(n, B->pos[1], B->crd[1], C->pos[1], C->crd[1], D->pos[1],
+                                        D->crd[1], A_pos, tile_sum, total, s),
+            "SpAdd3 symbolic launch");
+    tm.stop();
+    int64_t host_total = 0;
+    SPL_HIP(hipMemcpyAsync(&host_total, total, sizeof host_total, hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync");
+    SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (host_total > kIndexMax)
+        return fail(ctx, SPL_ERR_SHAPE, "output nnz %lld exceeds int32 positions",
+                    static_cast<long long>(host_total));
+    *nnz_out = host_total;
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
+                              const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
+                              void *A_vals, const spl_schedule *sched, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (!A_pos) return fail(ctx, SPL_ERR_ARG, "NULL A_pos");
+    SPL_CHECK(check_spadd3(ctx, B, C, D, sched));
+    if (B->vtype != C->vtype || B->vtype != D->vtype || B->vtype == SPL_BF16)
+        return fail(ctx, SPL_ERR_DTYPE, "SpAdd3 needs three F64 or three F32 operands");
+    const int64_t n = B->dims[0];
+    if (n > 0 && (B->nnz + C->nnz + D->nnz > 0) && (!A_crd || !A_vals))
+        return fail(ctx, SPL_ERR_ARG, "NULL output arrays");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LeafTimer tm(ctx, SPL_OP_SPADD3, s);
+    SPL_HIP(spl::launch_spadd3_numeric(B->vtype, n, B->pos[1], B->crd[1], B->vals, C->pos[1],
+                                       C->crd[1], C->vals, D->pos[1], D->crd[1], D->vals, A_pos,
+                                       A_crd, A_vals, s),
+            "SpAdd3 numeric launch");
+    tm.stop();
     return SPL_OK;
     SPL_GUARD_END
 }

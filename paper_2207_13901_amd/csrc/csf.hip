@@ -1,0 +1,286 @@
+// Leaves over CSF = (Dense, Compressed, Compressed) 3-tensors (paper
+// Sec. VI-A): SpMTTKRP and the inner product.  (SpTTV is the SpMV leaf run on
+// the fiber level; see abi.cpp.)
+//
+// Level partition of a CSF tensor for MTTKRP: pieces are contiguous runs of
+// the merged sequence of slice ends (pos1) and fibers, described like the
+// CSR pieces by (first slice the piece finishes, first fiber it covers).
+//  - merge split: equal numbers of merged items (slices + fibers);
+//  - non-zero split: blocks of T positions (the fused xyz -> f non-zero
+//    partition, Sec. II-B) snapped back to the first fiber not finished at
+//    the block boundary, slices derived by preimage through pos1.
+//
+// k_mttkrp_tiles: A(i,l) = sum_{f in slice i} C(j_f,l) * sum_{p in f} v_p D(k_p,l).
+// As in the SpMM leaf, a lane group of W lanes owns W rank columns and walks
+// ITEMS consecutive merged items of a chunk staged in LDS; here the items
+// are fibers.  For its fibers the group first issues every C-row gather and
+// (up to kPosCap positions) every D-row gather, keeping the scaled D rows in
+// a per-group LDS slab so the fiber loop can index them; then it walks the
+// fibers: t = sum over the fiber's positions, acc += C(j_f,:) * t, and a
+// slice end writes acc (first finished slice and the open one go through
+// the cross-group pass and the tile carry exactly as the SpMM rows do).
+#include "carry.hpp"
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spl {
+namespace {
+
+__device__ __forceinline__ int64_t finished_at(const int32_t *pos, int64_t rows, int64_t p) {
+    int64_t lo = 0, hi = rows;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (static_cast<int64_t>(pos[mid + 1]) <= p)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Fiber-aligned non-zero split bounds (tile t: slice, fiber).
+__global__ __launch_bounds__(kBlock) void k_csf_nnz_bounds(int64_t I, const int32_t *pos1,
+                                                           int64_t F, const int32_t *pos2,
+                                                           int64_t nnz, int64_t T, int64_t ntiles,
+                                                           int32_t *tslice, int32_t *tfib) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (t > ntiles) return;
+    const int64_t p = (t == ntiles || t * T > nnz) ? nnz : t * T;
+    const int64_t f = t == 0 ? 0 : finished_at(pos2, F, p);
+    tfib[t] = static_cast<int32_t>(f);
+    tslice[t] = static_cast<int32_t>(t == 0 ? 0 : finished_at(pos1, I, f));
+}
+
+template <int W, int ITEMS, typename V, typename FT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
+    int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
+    const int32_t *__restrict__ pos2, const int32_t *__restrict__ crd2,
+    const V *__restrict__ vals, const FT *__restrict__ C, int64_t ldc,
+    const FT *__restrict__ D, int64_t ldd, float *__restrict__ A, int64_t lda,
+    const int32_t *__restrict__ tslice, const int32_t *__restrict__ tfib, int64_t npieces,
+    int64_t stride, Acc *__restrict__ carry) {
+    constexpr int G = kBlock / W;
+    constexpr int kChunk = G * ITEMS;
+    constexpr int kPosCap = 2 * ITEMS;  // positions per group kept in LDS
+    __shared__ int32_t s_end[kChunk];         // slice ends (fiber index)
+    __shared__ int32_t s_j[kChunk];           // crd1 of each fiber
+    __shared__ int32_t s_fp[kChunk + 1];      // pos2 of each fiber (+ end)
+    __shared__ Acc s_dv[G][kPosCap][W];       // v_p * D(k_p, :) per group
+    __shared__ Acc s_head[G][W];
+    __shared__ Acc s_tail[G][W];
+    __shared__ int s_done[G];
+    __shared__ int s_a0[G];
+    __shared__ int64_t s_next[2];
+
+    const int tid = threadIdx.x;
+    const int g = tid / W, lane = tid % W;
+    const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
+    const bool colok = col < R;
+    int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
+    int64_t ci = tslice[piece], cf = tfib[piece];
+    Acc open = 0;
+
+    while (piece < piece_end) {
+        const int64_t next = chunk_end(pos1, tslice, tfib, piece, ci, cf, kChunk, s_next);
+        const int64_t ei = s_next[0], ef = s_next[1];
+        piece = next;
+        const int nr = static_cast<int>(ei - ci), nf = static_cast<int>(ef - cf);
+        for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
+        for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
+        for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+        __syncthreads();
+
+        const int total = nr + nf;
+        const int d0 = min(g * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        auto end_at = [&](int64_t m) { return s_end[m]; };
+        const int a0 = static_cast<int>(merge_search(d0, nr, nf, cf, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, nf, cf, end_at));
+        const int b0 = d0 - a0, b1 = d1 - a1;
+
+        // all C-row gathers of the group's fibers, then all D-row gathers of
+        // its first kPosCap positions
+        Acc cv[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            cv[k] = (b0 + k < b1 && colok)
+                        ? widen<Acc>(C[static_cast<int64_t>(s_j[b0 + k]) * ldc + col])
+                        : Acc(0);
+        const int64_t P0 = s_fp[b0], P1 = s_fp[b1];
+        const int np = static_cast<int>(P1 - P0);
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+            Acc dv = 0;
+            if (q < np && colok) {
+                const int64_t p = P0 + q;
+                dv = widen<Acc>(load_stream(vals + p)) *
+                     widen<Acc>(D[static_cast<int64_t>(load_stream(crd2 + p)) * ldd + col]);
+            }
+            s_dv[g][q][lane] = dv;
+        }
+
+        Acc acc = 0;
+        int a = a0;
+        bool first = true;
+        auto finish = [&](int r) {
+            if (first) {
+                s_head[g][lane] = acc;
+                first = false;
+            } else if (colok) {
+                A[(ci + r) * lda + col] = acc;
+            }
+            acc = 0;
+        };
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (b0 + k < b1) {
+                while (a < a1 && s_end[a] <= cf + b0 + k) finish(a++);
+                Acc t = 0;
+                const int q0 = static_cast<int>(s_fp[b0 + k] - P0);
+                const int q1 = static_cast<int>(s_fp[b0 + k + 1] - P0);
+                for (int q = q0; q < q1; ++q) {
+                    if (q < kPosCap) {
+                        t += s_dv[g][q][lane];
+                    } else if (colok) {
+                        const int64_t p = P0 + q;
+                        t += widen<Acc>(load_stream(vals + p)) *
+                             widen<Acc>(D[static_cast<int64_t>(load_stream(crd2 + p)) * ldd + col]);
+                    }
+                }
+                acc += cv[k] * t;
+            }
+        }
+        while (a < a1) finish(a++);
+        s_tail[g][lane] = acc;
+        if (lane == 0) {
+            s_done[g] = a1 - a0;
+            s_a0[g] = a0;
+        }
+        __syncthreads();
+
+        if (g == 0) {
+            Acc c = open;
+            for (int gg = 0; gg < G; ++gg) {
+                if (s_done[gg] > 0) {
+                    const Acc v = c + s_head[gg][lane];
+                    if (colok) A[(ci + s_a0[gg]) * lda + col] = v;
+                    c = s_tail[gg][lane];
+                } else {
+                    c += s_tail[gg][lane];
+                }
+            }
+            open = c;
+        }
+        ci = ei;
+        cf = ef;
+        __syncthreads();
+    }
+    if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * R + col] = open;
+}
+
+// Inner product of two value arrays on one pattern: per-workgroup FP64
+// partial sums over a fixed grid-stride assignment, then one workgroup adds
+// the partials in a fixed tree.  Bitwise reproducible for a fixed grid.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_inner_partial(int64_t nnz, const V *__restrict__ a,
+                                                          const V *__restrict__ b,
+                                                          double *__restrict__ part) {
+    double acc = 0.0, acc2 = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    for (; i + stride < nnz; i += 2 * stride) {
+        acc += to_f64(load_stream(a + i)) * to_f64(load_stream(b + i));
+        acc2 += to_f64(load_stream(a + i + stride)) * to_f64(load_stream(b + i + stride));
+    }
+    if (i < nnz) acc += to_f64(load_stream(a + i)) * to_f64(load_stream(b + i));
+    acc += acc2;
+    __shared__ double s[kBlock];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_inner_final(int64_t nparts,
+                                                        const double *__restrict__ part,
+                                                        double *__restrict__ out) {
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];
+    __shared__ double s[kBlock];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+template <typename V, typename FT>
+hipError_t mttkrp_types(int W, int items, int64_t I, int64_t R, const int32_t *pos1,
+                        const int32_t *crd1, const int32_t *pos2, const int32_t *crd2,
+                        const void *vals, const void *C, int64_t ldc, const void *D, int64_t ldd,
+                        float *A, int64_t lda, const Tiles &t, int64_t stride, float *carry,
+                        hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)), static_cast<unsigned>(ceil_div(R, W)));
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, s>>>(I, R, pos1, crd1, pos2, crd2, static_cast<const V *>(vals),
+                                     static_cast<const FT *>(C), ldc, static_cast<const FT *>(D),
+                                     ldd, A, lda, t.row, t.pos, t.ntiles, stride, carry);
+        return hipGetLastError();
+    };
+    if (W == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
+                                   : go(k_mttkrp_tiles<16, 16, V, FT, float>);
+    if (W == 64) return items <= 8 ? go(k_mttkrp_tiles<64, 8, V, FT, float>)
+                                   : go(k_mttkrp_tiles<64, 16, V, FT, float>);
+    return items <= 8 ? go(k_mttkrp_tiles<32, 8, V, FT, float>)
+                      : go(k_mttkrp_tiles<32, 16, V, FT, float>);
+}
+
+}  // namespace
+
+hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
+                                 int64_t nnz, int64_t T, const Tiles &t, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((t.ntiles + 1 + kBlock - 1) / kBlock));
+    k_csf_nnz_bounds<<<grid, kBlock, 0, s>>>(I, pos1, F, pos2, nnz, T, t.ntiles, t.row, t.pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int64_t I, int64_t R,
+                               const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
+                               const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
+                               const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
+                               int64_t stride, float *carry, hipStream_t s) {
+    if (vtype == SPL_F32)
+        return mttkrp_types<float, float>(col_tile, items, I, R, pos1, crd1, pos2, crd2, vals, C,
+                                          ldc, D, ldd, A, lda, t, stride, carry, s);
+    return mttkrp_types<bf16, bf16>(col_tile, items, I, R, pos1, crd1, pos2, crd2, vals, C, ldc, D,
+                                    ldd, A, lda, t, stride, carry, s);
+}
+
+hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t stride,
+                               const float *carry, float *A, int64_t lda, hipStream_t s) {
+    return launch_carry_fixup<float, float>(I, R, t.row, t.ntiles, stride,
+                                            ceil_div(t.ntiles, stride), carry, A, lda, s);
+}
+
+hipError_t launch_inner(int vtype, int64_t nnz, const void *a, const void *b, double *part,
+                        int64_t nparts, double *out, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(nparts));
+    if (vtype == SPL_F64)
+        k_inner_partial<double><<<grid, kBlock, 0, s>>>(nnz, static_cast<const double *>(a),
+                                                         static_cast<const double *>(b), part);
+    else
+        k_inner_partial<float><<<grid, kBlock, 0, s>>>(nnz, static_cast<const float *>(a),
+                                                        static_cast<const float *>(b), part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_inner_final<<<1, kBlock, 0, s>>>(nparts, part, out);
+    return hipGetLastError();
+}
+
+}  // namespace spl

@@ -74,4 +74,35 @@ __device__ __forceinline__ int64_t merge_search(int64_t d, int64_t nr, int64_t n
     return lo;
 }
 
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// End of the next chunk of a leaf workgroup walking the merged sequence of
+// row ends and positions from (ci, cp), inside partition piece `piece`
+// (bounds trow/tpos[piece+1]): the piece's end if it lies within `chunk`
+// items, else the merge-path point `chunk` items ahead, found by thread 0
+// with a binary search over pos.  Writes (ei, ep) to s_next and returns the
+// piece the walk is in afterwards.  Contains a workgroup barrier; every
+// thread must call it.
+__device__ __forceinline__ int64_t chunk_end(const int32_t *__restrict__ pos,
+                                             const int32_t *__restrict__ trow,
+                                             const int32_t *__restrict__ tpos, int64_t piece,
+                                             int64_t ci, int64_t cp, int chunk,
+                                             int64_t *s_next) {
+    const int64_t bi = trow[piece + 1], bp = tpos[piece + 1];
+    const bool whole = bi + bp - ci - cp <= chunk;
+    if (threadIdx.x == 0) {
+        if (whole) {
+            s_next[0] = bi;
+            s_next[1] = bp;
+        } else {
+            const int64_t k = merge_search(chunk, bi - ci, bp - cp, cp,
+                                           [&](int64_t m) { return pos[ci + m + 1]; });
+            s_next[0] = ci + k;
+            s_next[1] = cp + chunk - k;
+        }
+    }
+    __syncthreads();
+    return whole ? piece + 1 : piece;
+}
+
 }  // namespace spl

@@ -29,9 +29,14 @@ hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_
 hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
                            const int32_t *crd, const void *vals, const void *x, void *y,
                            hipStream_t s);
+// Tiled leaves: one workgroup per `stride` consecutive partition pieces of
+// `t`; carries are one per workgroup.
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
-                             const Tiles &t, double *carry, hipStream_t s);
+                             const Tiles &t, int64_t stride, double *carry, hipStream_t s);
+// Adds workgroup carries into the rows left open (after the leaf).
+hipError_t launch_spmv_fixup(int dtype, int64_t n, const Tiles &t, int64_t stride,
+                             const double *carry, void *y, hipStream_t s);
 
 // ---- spmm.hip ------------------------------------------------------------
 hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_t N,
@@ -40,7 +45,47 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
 hipError_t launch_spmm_tiles(int vtype, int otype, int col_tile, int items, int64_t n,
                              int64_t N, const int32_t *pos, const int32_t *crd,
                              const void *vals, const void *B, int64_t ldb, void *C,
-                             int64_t ldc, const Tiles &t, void *carry, hipStream_t s);
+                             int64_t ldc, const Tiles &t, int64_t stride, void *carry,
+                             hipStream_t s);
+hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, int64_t stride,
+                             const void *carry, void *C, int64_t ldc, hipStream_t s);
+
+// ---- csf.hip -------------------------------------------------------------
+// Fiber-aligned non-zero split of a CSF tensor: t.row = slice, t.pos = fiber.
+hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
+                                 int64_t nnz, int64_t T, const Tiles &t, hipStream_t s);
+hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int64_t I, int64_t R,
+                               const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
+                               const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
+                               const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
+                               int64_t stride, float *carry, hipStream_t s);
+hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t stride,
+                               const float *carry, float *A, int64_t lda, hipStream_t s);
+hipError_t launch_inner(int vtype, int64_t nnz, const void *a, const void *b, double *part,
+                        int64_t nparts, double *out, hipStream_t s);
+
+// ---- sddmm.hip -----------------------------------------------------------
+int64_t sddmm_chunk();
+hipError_t launch_sddmm(int vtype, int ftype, int variant, int64_t K, const int32_t *pos,
+                        const int32_t *crd, const void *bv, const void *C, int64_t ldc,
+                        const void *D, int64_t ldd, void *out, const Tiles &t, int64_t stride,
+                        hipStream_t s);
+
+// ---- spadd3.hip ----------------------------------------------------------
+int64_t spadd3_scan_tiles(int64_t n);
+hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
+                                  const int32_t *cp, const int32_t *cc, const int32_t *dp,
+                                  const int32_t *dc, int32_t *apos, int64_t *tile_sum,
+                                  int64_t *total, hipStream_t s);
+hipError_t launch_spadd3_numeric(int vtype, int64_t n, const int32_t *bp, const int32_t *bc,
+                                 const void *bv, const int32_t *cp, const int32_t *cc,
+                                 const void *cv, const int32_t *dp, const int32_t *dc,
+                                 const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
+                                 hipStream_t s);
+
+// ---- probe.hip -----------------------------------------------------------
+hipError_t launch_probe(int kind, const void *buf, int64_t bytes, int64_t row_bytes,
+                        int64_t count, double *out, int64_t blocks, hipStream_t s);
 
 // ---- validate.hip --------------------------------------------------------
 // Writes a failure code (0 = valid) and the first failing index to flags[0..1].

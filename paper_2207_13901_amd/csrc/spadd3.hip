@@ -1,0 +1,198 @@
+// SpAdd3 leaf  A(i,j) = B(i,j) + C(i,j) + D(i,j)  for CSR operands (paper
+// Sec. VI-A), fused so no pairwise intermediate is built, with the output
+// assembled in two phases (Sec. V-B): a symbolic phase counts the union of
+// the three coordinate lists of every row and an exclusive scan turns the
+// counts into A.pos; the numeric phase writes A.crd and A.vals at those
+// positions with no synchronization between rows.  Row split only: the
+// non-zero split does not apply to a sum of CSR operands (Sec. VI-A, CPU
+// results).
+//
+// One lane per row merges the three sorted coordinate lists; values are
+// summed in operand order B, C, D over the operands present (a cancellation
+// to zero keeps its coordinate).  The scan is three passes: per-workgroup
+// totals, one workgroup scanning the totals, per-workgroup rescan.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spl {
+namespace {
+
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+struct Csr3 {
+    const int32_t *bp, *bc, *cp, *cc, *dp, *dc;
+};
+
+template <bool kNumeric, typename V>
+__device__ __forceinline__ int32_t merge3(const Csr3 &m, int64_t i, const V *bv, const V *cv,
+                                          const V *dv, int32_t *ocrd, V *oval) {
+    int32_t a = m.bp[i], ae = m.bp[i + 1];
+    int32_t b = m.cp[i], be = m.cp[i + 1];
+    int32_t d = m.dp[i], de = m.dp[i + 1];
+    int32_t k = 0;
+    constexpr int32_t kInf = 0x7fffffff;
+    int32_t xa = a < ae ? m.bc[a] : kInf;
+    int32_t xb = b < be ? m.cc[b] : kInf;
+    int32_t xd = d < de ? m.dc[d] : kInf;
+    for (;;) {
+        const int32_t c = min(xa, min(xb, xd));
+        if (c == kInf) break;
+        V sum = 0;
+        if (xa == c) {
+            if (kNumeric) sum = bv[a];
+            ++a;
+            xa = a < ae ? m.bc[a] : kInf;
+        }
+        if (xb == c) {
+            if (kNumeric) sum = sum + cv[b];
+            ++b;
+            xb = b < be ? m.cc[b] : kInf;
+        }
+        if (xd == c) {
+            if (kNumeric) sum = sum + dv[d];
+            ++d;
+            xd = d < de ? m.dc[d] : kInf;
+        }
+        if (kNumeric) {
+            ocrd[k] = c;
+            oval[k] = sum;
+        }
+        ++k;
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int32_t *apos) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i == 0) apos[0] = 0;
+    if (i >= n) return;
+    apos[i + 1] = merge3<false, float>(m, i, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const V *bv,
+                                                        const V *cv, const V *dv,
+                                                        const int32_t *apos, int32_t *acrd,
+                                                        V *aval) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = apos[i];
+    merge3<true, V>(m, i, bv, cv, dv, acrd + o, aval + o);
+}
+
+// Block sums of x[0..n) in tiles of kScanTile.
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t n, const int32_t *x,
+                                                           int64_t *tile_sum) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int64_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j * kBlock + threadIdx.x;
+        if (i < n) acc += x[i];
+    }
+    __shared__ int64_t s[kBlock];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s[0];
+}
+
+// Exclusive scan of the tile sums by one workgroup; total to *total.
+__global__ __launch_bounds__(kBlock) void k_scan_tile_prefix(int64_t ntiles, int64_t *tile_sum,
+                                                             int64_t *total) {
+    __shared__ int64_t s[kBlock];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < ntiles; b0 += kBlock) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = i < ntiles ? tile_sum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const int64_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < ntiles) tile_sum[i] = carry + s[threadIdx.x] - v;
+        carry += s[kBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// In place: x[i] <- tile prefix + inclusive scan within the tile, i.e. with
+// x = counts at apos + 1 this leaves apos[i+1] = sum of counts[0..i].
+__global__ __launch_bounds__(kBlock) void k_scan_tile_apply(int64_t n, int32_t *x,
+                                                            const int64_t *tile_sum) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        run += i < n ? x[i] : 0;
+        v[j] = run;
+    }
+    __shared__ int64_t s[kBlock];
+    s[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int64_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int64_t before = tile_sum[blockIdx.x] + s[threadIdx.x] - run;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        if (i < n) x[i] = static_cast<int32_t>(before + v[j]);
+    }
+}
+
+}  // namespace
+
+int64_t spadd3_scan_tiles(int64_t n) { return ceil_div(n > 0 ? n : 1, kScanTile); }
+
+hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
+                                  const int32_t *cp, const int32_t *cc, const int32_t *dp,
+                                  const int32_t *dc, int32_t *apos, int64_t *tile_sum,
+                                  int64_t *total, hipStream_t s) {
+    Csr3 m{bp, bc, cp, cc, dp, dc};
+    const int64_t rows_grid = ceil_div(n > 0 ? n : 1, kBlock);
+    k_spadd3_count<<<dim3(static_cast<unsigned>(rows_grid)), kBlock, 0, s>>>(n, m, apos);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = spadd3_scan_tiles(n);
+    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, tile_sum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_prefix<<<1, kBlock, 0, s>>>(nt, tile_sum, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, tile_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_spadd3_numeric(int vtype, int64_t n, const int32_t *bp, const int32_t *bc,
+                                 const void *bv, const int32_t *cp, const int32_t *cc,
+                                 const void *cv, const int32_t *dp, const int32_t *dc,
+                                 const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
+                                 hipStream_t s) {
+    Csr3 m{bp, bc, cp, cc, dp, dc};
+    if (n == 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(ceil_div(n, kBlock)));
+    if (vtype == SPL_F64)
+        k_spadd3_fill<double><<<grid, kBlock, 0, s>>>(
+            n, m, static_cast<const double *>(bv), static_cast<const double *>(cv),
+            static_cast<const double *>(dv), apos, acrd, static_cast<double *>(aval));
+    else
+        k_spadd3_fill<float><<<grid, kBlock, 0, s>>>(
+            n, m, static_cast<const float *>(bv), static_cast<const float *>(cv),
+            static_cast<const float *>(dv), apos, acrd, static_cast<float *>(aval));
+    return hipGetLastError();
+}
+
+}  // namespace spl

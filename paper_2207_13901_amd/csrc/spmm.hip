@@ -11,16 +11,19 @@
 //    broadcast with shuffles, then one Bd row is gathered per position.
 //
 //  * k_spmm_tiles: non-zero or merge split (the load-balanced GPU SpMM
-//    schedule of Sec. VI-A, GPU results).  A workgroup owns one tile of the
-//    merged (row ends, positions) sequence and processes it in chunks of
-//    G*ITEMS items (G = 256/W groups).  The chunk's row ends, crd and vals are
+//    schedule of Sec. VI-A, GPU results).  A workgroup owns `stride`
+//    consecutive pieces of the level partition (merge split: pieces of
+//    exactly one chunk; non-zero split: pieces of T positions cut into chunks
+//    by a merge-path search) and processes them in chunks of G*ITEMS merged
+//    items (G = 256/W groups).  The chunk's row ends, crd and vals are
 //    staged in LDS; each group walks ITEMS consecutive merged items, first
 //    issuing all of its Bd gathers (up to ITEMS rows in flight per group) and
 //    then consuming them in order.  Rows a group finishes after its first
 //    are written directly; the first finished row and the row left open are
 //    combined across groups in order by group 0 (G steps), and the row open
-//    at the tile end is written to the tile's carry vector.  k_spmm_fixup adds
-//    carries into their rows in tile order.  Deterministic, no atomics.
+//    at the tile end is written to the tile's carry vector.  k_carry_fixup
+//    (carry.hpp) adds carries into their rows in a fixed order.  Deterministic, no atomics.
+#include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
     int64_t n, int64_t N, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
     int64_t ldo, const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos,
-    Acc *__restrict__ carry) {
+    int64_t npieces, int64_t stride, Acc *__restrict__ carry) {
     constexpr int G = kBlock / W;
     constexpr int kChunk = G * ITEMS;
     __shared__ int32_t s_end[kChunk];
@@ -91,26 +94,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
     const int g = tid / W, lane = tid % W;
     const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
     const bool colok = col < N;
-    const int64_t t = blockIdx.x;
-    const int64_t i_end = trow[t + 1], p_end = tpos[t + 1];
-    int64_t ci = trow[t], cp = tpos[t];
+    // this workgroup walks partition pieces [piece, piece_end)
+    int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
+    int64_t ci = trow[piece], cp = tpos[piece];
     Acc open = 0;  // group 0: partial of row ci carried between chunks
 
-    for (;;) {
-        if (tid == 0) {
-            int64_t d = ci + cp + kChunk;
-            int64_t ei = i_end, ep = p_end;
-            if (d < i_end + p_end) {
-                int64_t k = merge_search(d - ci - cp, i_end - ci, p_end - cp, cp,
-                                         [&](int64_t m) { return pos[ci + m + 1]; });
-                ei = ci + k;
-                ep = d - ei;
-            }
-            s_next[0] = ei;
-            s_next[1] = ep;
-        }
-        __syncthreads();
+    while (piece < piece_end) {
+        const int64_t next = chunk_end(pos, trow, tpos, piece, ci, cp, kChunk, s_next);
         const int64_t ei = s_next[0], ep = s_next[1];
+        piece = next;
         const int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
         for (int k = tid; k < nr; k += kBlock) s_end[k] = pos[ci + 1 + k];
         for (int k = tid; k < np; k += kBlock) {
@@ -178,29 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
         }
         ci = ei;
         cp = ep;
-        if (ci == i_end && cp == p_end) break;
         __syncthreads();
     }
-    if (g == 0 && colok) carry[t * N + col] = open;
-}
-
-// Add carry vectors into the row left open at each tile's end, summing a
-// run of tiles open on the same row in tile order (one lane per column).
-template <typename OT, typename Acc>
-__global__ __launch_bounds__(kBlock) void k_spmm_fixup(int64_t n, int64_t N,
-                                                       const int32_t *__restrict__ trow,
-                                                       int64_t ntiles, const Acc *__restrict__ carry,
-                                                       OT *__restrict__ Out, int64_t ldo) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (idx >= ntiles * N) return;
-    const int64_t t = idx / N, col = idx % N;
-    const int32_t r = trow[t + 1];
-    if (r >= n) return;
-    if (t > 0 && trow[t] == r) return;
-    Acc total = 0;
-    for (int64_t u = t; u < ntiles && trow[u + 1] == r; ++u) total += carry[u * N + col];
-    OT *o = Out + static_cast<int64_t>(r) * ldo + col;
-    *o = narrow<OT>(static_cast<Acc>(*o) + total);
+    if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * N + col] = open;
 }
 
 template <typename V, typename BT, typename OT, typename Acc>
@@ -227,27 +200,36 @@ struct SpmmTypes {
     template <int W, int ITEMS>
     static hipError_t tiles_w(int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
                               const void *vals, const void *Bd, int64_t ldb, void *Out,
-                              int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
-        dim3 grid(static_cast<unsigned>(t.ntiles), static_cast<unsigned>((N + W - 1) / W));
+                              int64_t ldo, const Tiles &t, int64_t stride, void *carry,
+                              hipStream_t s) {
+        dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)),
+                  static_cast<unsigned>((N + W - 1) / W));
         if (grid.y == 0) return hipSuccess;
         k_spmm_tiles<W, ITEMS, V, BT, OT, Acc><<<grid, kBlock, 0, s>>>(
             n, N, pos, crd, static_cast<const V *>(vals), static_cast<const BT *>(Bd), ldb,
-            static_cast<OT *>(Out), ldo, t.row, t.pos, static_cast<Acc *>(carry));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        const int64_t work = t.ntiles * N;
-        k_spmm_fixup<OT, Acc><<<dim3(static_cast<unsigned>((work + kBlock - 1) / kBlock)), kBlock, 0, s>>>(
-            n, N, t.row, t.ntiles, static_cast<const Acc *>(carry), static_cast<OT *>(Out), ldo);
+            static_cast<OT *>(Out), ldo, t.row, t.pos, t.ntiles, stride,
+            static_cast<Acc *>(carry));
         return hipGetLastError();
+    }
+
+    static hipError_t fixup(int64_t n, int64_t N, const Tiles &t, int64_t stride,
+                            const void *carry, void *Out, int64_t ldo, hipStream_t s) {
+        return launch_carry_fixup<OT, Acc>(n, N, t.row, t.ntiles, stride,
+                                           ceil_div(t.ntiles, stride),
+                                           static_cast<const Acc *>(carry),
+                                           static_cast<OT *>(Out), ldo, s);
     }
 
     static hipError_t tiles(int W, int items, int64_t n, int64_t N, const int32_t *pos,
                             const int32_t *crd, const void *vals, const void *Bd, int64_t ldb,
-                            void *Out, int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
-#define SPL_SPMM_ITEMS(Wv)                                                                  \
-    if (items <= 8) return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s); \
-    if (items <= 16) return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s); \
-    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, carry, s);
+                            void *Out, int64_t ldo, const Tiles &t, int64_t stride, void *carry,
+                            hipStream_t s) {
+#define SPL_SPMM_ITEMS(Wv)                                                                      \
+    if (items <= 8)                                                                             \
+        return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);    \
+    if (items <= 16)                                                                            \
+        return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);   \
+    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);
         switch (W) {
         case 8: SPL_SPMM_ITEMS(8)
         case 16: SPL_SPMM_ITEMS(16)
@@ -259,6 +241,13 @@ struct SpmmTypes {
 };
 
 }  // namespace
+
+hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, int64_t stride,
+                             const void *carry, void *Out, int64_t ldo, hipStream_t s) {
+    if (vtype == SPL_F64)
+        return SpmmTypes<double, double, double, double>::fixup(n, N, t, stride, carry, Out, ldo, s);
+    return SpmmTypes<float, float, float, float>::fixup(n, N, t, stride, carry, Out, ldo, s);
+}
 
 hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_t N,
                            const int32_t *pos, const int32_t *crd, const void *vals,
@@ -277,16 +266,18 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
 hipError_t launch_spmm_tiles(int vtype, int otype, int col_tile, int items, int64_t n,
                              int64_t N, const int32_t *pos, const int32_t *crd,
                              const void *vals, const void *Bd, int64_t ldb, void *Out,
-                             int64_t ldo, const Tiles &t, void *carry, hipStream_t s) {
+                             int64_t ldo, const Tiles &t, int64_t stride, void *carry,
+                             hipStream_t s) {
     (void)otype;
     if (vtype == SPL_F64)
         return SpmmTypes<double, double, double, double>::tiles(col_tile, items, n, N, pos, crd,
-                                                                vals, Bd, ldb, Out, ldo, t, carry, s);
+                                                                vals, Bd, ldb, Out, ldo, t, stride,
+                                                                carry, s);
     if (vtype == SPL_F32)
         return SpmmTypes<float, float, float, float>::tiles(col_tile, items, n, N, pos, crd, vals,
-                                                            Bd, ldb, Out, ldo, t, carry, s);
+                                                            Bd, ldb, Out, ldo, t, stride, carry, s);
     return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, n, N, pos, crd, vals, Bd,
-                                                      ldb, Out, ldo, t, carry, s);
+                                                      ldb, Out, ldo, t, stride, carry, s);
 }
 
 }  // namespace spl

@@ -8,9 +8,11 @@
 //    positions).  No carries: every row is finished by the group that owns
 //    it.  Good for short, even rows; a long row serializes on its group.
 //
-//  * k_spmv_tiles: non-zero or merge split.  A workgroup owns one tile of
-//    the merged (row ends, positions) sequence, whose bounds come from
-//    partition.hip.  The tile is processed in chunks of 256*ITEMS merged
+//  * k_spmv_tiles: non-zero or merge split.  A workgroup owns `stride`
+//    consecutive pieces of the level partition computed by partition.hip
+//    (for the merge split, pieces of exactly one chunk, so no search is
+//    needed; for the non-zero split, pieces of T positions, cut into chunks
+//    by a merge-path search).  Each chunk has at most 256*ITEMS merged
 //    items: the chunk's products vals[p]*c[crd[p]] and row ends are staged in
 //    LDS with coalesced loads, every lane walks ITEMS consecutive merged
 //    items (a merge-path split inside the chunk, so empty and long rows cost
@@ -18,13 +20,14 @@
 //    is inside when its items run out is combined with its neighbours' by a
 //    wavefront segmented scan (xor/up shuffles) plus a 4-entry cross-wave
 //    pass through LDS.  The sum of the row still open at the end of the tile
-//    is the tile's carry; k_spmv_fixup adds carries into their rows in tile
-//    order after the leaf kernel, the reduction into boundary rows that the
+//    is the tile's carry; k_carry_fixup (carry.hpp) adds carries into their
+//    rows in a fixed order after the leaf kernel, the reduction into boundary rows that the
 //    non-zero algorithm of Sec. II-D requires.  No floating-point atomics,
 //    so results are bitwise reproducible.
 //
 // Accumulation is in double for both double and float data (a float output
 // is rounded once from the double sum, then once more if a carry lands on it).
+#include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -87,7 +90,8 @@ template <typename V, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
-    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, double *__restrict__ carry) {
+    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
+    int64_t stride, double *__restrict__ carry) {
     constexpr int kChunk = kBlock * ITEMS;
     __shared__ double s_prod[kChunk];
     __shared__ double s_out[kChunk];
@@ -98,34 +102,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     __shared__ double s_open;
 
     const int tid = threadIdx.x;
-    const int64_t t = blockIdx.x;
-    const int64_t i_end = trow[t + 1], p_end = tpos[t + 1];
-    int64_t ci = trow[t], cp = tpos[t];
+    // this workgroup walks partition pieces [piece, piece_end)
+    int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
+    int64_t ci = trow[piece], cp = tpos[piece];
     double open = 0.0;  // partial sum of row ci carried between chunks
 
-    for (;;) {
-        // Chunk end: the merge-path point kChunk items further, or the tile end.
-        if (tid == 0) {
-            int64_t d = ci + cp + kChunk;
-            int64_t ei = i_end, ep = p_end;
-            if (d < i_end + p_end) {
-                // search rows [ci, i_end] for the split of diagonal d
-                int64_t k = merge_search(d - ci - cp, i_end - ci, p_end - cp, cp,
-                                         [&](int64_t m) { return pos[ci + m + 1]; });
-                ei = ci + k;
-                ep = d - ei;
-            }
-            s_next[0] = ei;
-            s_next[1] = ep;
-        }
-        __syncthreads();
+    while (piece < piece_end) {
+        const int64_t next = chunk_end(pos, trow, tpos, piece, ci, cp, kChunk, s_next);
         const int64_t ei = s_next[0], ep = s_next[1];
+        piece = next;
         const int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
 
         for (int k = tid; k < nr; k += kBlock) s_end[k] = pos[ci + 1 + k];
-        for (int k = tid; k < np; k += kBlock) {
-            const int64_t p = cp + k;
-            s_prod[k] = to_f64(load_stream(vals + p)) * to_f64(x[load_stream(crd + p)]);
+        {
+            // all ITEMS index loads, then all ITEMS gathers, then the products:
+            // ITEMS independent gathers in flight per lane
+            int c[ITEMS];
+            V v[ITEMS], xv[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const int k = tid + j * kBlock;
+                if (k < np) {
+                    c[j] = load_stream(crd + cp + k);
+                    v[j] = load_stream(vals + cp + k);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                if (tid + j * kBlock < np) xv[j] = x[c[j]];
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const int k = tid + j * kBlock;
+                if (k < np) s_prod[k] = to_f64(v[j]) * to_f64(xv[j]);
+            }
         }
         __syncthreads();
 
@@ -168,27 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
         open = s_open;
         ci = ei;
         cp = ep;
-        if (ci == i_end && cp == p_end) break;
         __syncthreads();
     }
-    if (tid == 0) carry[t] = open;
-}
-
-// Add each tile's carry into the row still open at its end.  The first tile
-// of a run of tiles open on the same row sums the run's carries in tile
-// order, so the result does not depend on scheduling.
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_spmv_fixup(int64_t n, const int32_t *__restrict__ trow,
-                                                       int64_t ntiles, const double *__restrict__ carry,
-                                                       V *__restrict__ y) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (t >= ntiles) return;
-    const int32_t r = trow[t + 1];
-    if (r >= n) return;
-    if (t > 0 && trow[t] == r) return;  // not the first tile open on row r
-    double total = 0.0;
-    for (int64_t u = t; u < ntiles && trow[u + 1] == r; ++u) total += carry[u];
-    y[r] = static_cast<V>(static_cast<double>(y[r]) + total);
+    if (tid == 0) carry[blockIdx.x] = open;
 }
 
 template <typename V>
@@ -213,21 +205,33 @@ hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int
 
 template <typename V>
 hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const int32_t *crd,
-                               const V *vals, const V *x, V *y, const Tiles &t, double *carry,
-                               hipStream_t s) {
-    dim3 grid(static_cast<unsigned>(t.ntiles));
+                               const V *vals, const V *x, V *y, const Tiles &t, int64_t stride,
+                               double *carry, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
     if (items <= 4)
-        k_spmv_tiles<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos, carry);
+        k_spmv_tiles<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                    t.ntiles, stride, carry);
     else
-        k_spmv_tiles<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos, carry);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    dim3 fgrid(static_cast<unsigned>((t.ntiles + kBlock - 1) / kBlock));
-    k_spmv_fixup<V><<<fgrid, kBlock, 0, s>>>(n, t.row, t.ntiles, carry, y);
+        k_spmv_tiles<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                    t.ntiles, stride, carry);
     return hipGetLastError();
 }
 
+template <typename V>
+hipError_t spmv_fixup_dispatch(int64_t n, const Tiles &t, int64_t stride, const double *carry,
+                               V *y, hipStream_t s) {
+    return launch_carry_fixup<V, double>(n, 1, t.row, t.ntiles, stride, ceil_div(t.ntiles, stride),
+                                         carry, y, 1, s);
+}
+
 }  // namespace
+
+hipError_t launch_spmv_fixup(int dtype, int64_t n, const Tiles &t, int64_t stride,
+                             const double *carry, void *y, hipStream_t s) {
+    if (dtype == SPL_F64)
+        return spmv_fixup_dispatch<double>(n, t, stride, carry, static_cast<double *>(y), s);
+    return spmv_fixup_dispatch<float>(n, t, stride, carry, static_cast<float *>(y), s);
+}
 
 hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
                            const int32_t *crd, const void *vals, const void *x, void *y,
@@ -241,14 +245,14 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
 
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
-                             const Tiles &t, double *carry, hipStream_t s) {
+                             const Tiles &t, int64_t stride, double *carry, hipStream_t s) {
     if (dtype == SPL_F64)
         return spmv_tiles_dispatch<double>(items, n, pos, crd, static_cast<const double *>(vals),
                                            static_cast<const double *>(x),
-                                           static_cast<double *>(y), t, carry, s);
+                                           static_cast<double *>(y), t, stride, carry, s);
     return spmv_tiles_dispatch<float>(items, n, pos, crd, static_cast<const float *>(vals),
                                       static_cast<const float *>(x), static_cast<float *>(y), t,
-                                      carry, s);
+                                      stride, carry, s);
 }
 
 }  // namespace spl

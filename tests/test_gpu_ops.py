@@ -1,0 +1,231 @@
+"""GPU parity of SpTTV, SpMTTKRP, the inner product, SDDMM and SpAdd3
+against the CPU oracle, through the C ABI.
+
+Output patterns (SpAdd3 pos/crd) are compared bit for bit; values satisfy
+|got - ref| <= rtol * S with rtol 1e-12 (FP64) or 1e-5 (FP32, and BF16
+inputs with FP32 accumulation compared with the oracle run on the same
+BF16-rounded inputs); small-integer values are bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests import tiny
+from tests.gpu_util import RTOL, assert_close, dev, host64, need_gpu
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+TTV_SCHEDULES = [dict(kind="default"), dict(kind="row", lanes_per_row=2),
+                 dict(kind="nnz", tile=500), dict(kind="merge", tile=4096, items_per_lane=4)]
+MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=32, items_per_lane=8),
+                    dict(kind="nnz", tile=300), dict(kind="nnz", tile=4096, col_tile=16),
+                    dict(kind="row", tile=3), dict(kind="merge", tile=5000, col_tile=64,
+                                                   items_per_lane=16)]
+SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
+                   dict(kind="merge", tile=512)]
+
+
+def _spl():
+    need_gpu()
+    import paper_2207_13901_amd as spl
+    return spl
+
+
+def _t(a, dtype=torch.int32):
+    return torch.as_tensor(np.asarray(a)).to(dtype).to(dev())
+
+
+def _csf(spl, c, dtype, vals_key="vals"):
+    shape = (c["I"], c["J"], c["K"])
+    return spl.CSF(_t(c["pos1"]), _t(c["crd1"]), _t(c["pos2"]), _t(c["crd2"]),
+                   _t(c[vals_key], torch.float64).to(dtype), shape)
+
+
+def _tiny_csf(seed, kind="float"):
+    rs = np.random.RandomState(seed)
+    p1, c1, p2, c2, v = tiny.csf(rs, 40, 9, 300, 0.05, kind=kind, empty_slices={0, 5, 39})
+    return dict(I=40, J=9, K=300, pos1=p1, crd1=c1, pos2=p2, crd2=c2, vals=v,
+                vals2=rs.uniform(-1, 1, len(v)))
+
+
+def _numpy(c):
+    return {k: (v.numpy() if isinstance(v, torch.Tensor) else v) for k, v in c.items()}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spttv(dtype):
+    spl = _spl()
+    for c in (_numpy(configs.config4(scale=0.001, with_dense=False)), _tiny_csf(1)):
+        B = _csf(spl, c, dtype)
+        cv = _t(np.linspace(-1, 1, c["K"]), torch.float64).to(dtype)
+        ref, S = oracle.spttv(c["pos1"], c["pos2"], c["crd2"], host64(B.vals), host64(cv))
+        for sc in TTV_SCHEDULES:
+            A = spl.spttv(B, cv, sched=spl.schedule(**sc))
+            assert A.numel() == len(c["crd1"])
+            assert_close(host64(A), ref, S, RTOL[dtype], f"spttv {sc}")
+
+
+def test_spttv_unit_vector_extracts_entries():
+    spl = _spl()
+    c = _tiny_csf(2)
+    B = _csf(spl, c, torch.float64)
+    for k in (0, 17, 299):
+        e = torch.zeros(c["K"], dtype=torch.float64, device=dev())
+        e[k] = 1.0
+        A = spl.spttv(B, e)
+        ref, _ = oracle.spttv(c["pos1"], c["pos2"], c["crd2"], c["vals"], e.cpu().numpy())
+        assert np.array_equal(host64(A), ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("R", [32, 5, 70])
+def test_mttkrp(dtype, R):
+    spl = _spl()
+    c4 = _numpy(configs.config4(scale=0.001, R=R))
+    for c in (c4, dict(_tiny_csf(3), C=np.random.RandomState(4).normal(size=(9, R)),
+                       D=np.random.RandomState(5).normal(size=(300, R)))):
+        B = _csf(spl, c, dtype)
+        C = _t(c["C"], torch.float64).to(torch.float32).to(dtype)
+        D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
+        ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
+                               host64(C), host64(D))
+        for sc in MTTKRP_SCHEDULES:
+            A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+            assert A.dtype == torch.float32
+            assert_close(host64(A), ref, S, 1e-5, f"mttkrp {dtype} R={R} {sc}")
+
+
+def test_mttkrp_integer_values_bit_exact():
+    spl = _spl()
+    c = _tiny_csf(6, kind="int")
+    rs = np.random.RandomState(7)
+    C = _t(rs.randint(-4, 5, (9, 32)), torch.float32)
+    D = _t(rs.randint(-4, 5, (300, 32)), torch.float32)
+    B = _csf(spl, c, torch.float32)
+    ref, _ = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], c["vals"],
+                           host64(C), host64(D))
+    for sc in MTTKRP_SCHEDULES:
+        A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+        assert np.array_equal(host64(A), ref), sc
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inner_product(dtype):
+    spl = _spl()
+    for c in (_numpy(configs.config4(scale=0.001, with_dense=False)), _tiny_csf(8)):
+        B = _csf(spl, c, dtype)
+        C = B.with_vals(_t(c["vals2"], torch.float64).to(dtype))
+        a = spl.inner(B, C)
+        ref, S = oracle.inner((c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals)),
+                              (c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(C.vals)))
+        assert_close(host64(a), np.array([ref]), np.array([S]), 1e-12, "inner")
+        # equal to the sum of the Hadamard product of the aligned values
+        had = float(np.sum(host64(B.vals) * host64(C.vals)))
+        assert abs(float(a.item()) - had) <= 1e-12 * S
+        a2 = spl.inner(B, C)
+        assert torch.equal(a, a2)  # fixed reduction order
+    # distinct pattern arrays are refused
+    other = spl.CSF(B.pos1.clone(), B.crd1, B.pos2, B.crd2, C.vals, B.shape)
+    with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
+        spl.inner(B, other)
+
+
+def _c3(scale=0.002, K=128, kind="sym"):
+    return configs.config3(scale=scale, K=K, kind=kind)
+
+
+@pytest.mark.parametrize("case", ["f64", "f32", "bf16_valu", "bf16_mfma"])
+def test_sddmm(case):
+    spl = _spl()
+    c = _c3()
+    Bm = c["B"]
+    vdt = torch.float64 if case == "f64" else torch.float32
+    fdt = {"f64": torch.float64, "f32": torch.float32}.get(case, torch.bfloat16)
+    B = spl.CSR(Bm["pos"].to(dev()), Bm["crd"].to(dev()), Bm["vals"].to(vdt).to(dev()),
+                (c["n"], c["m"]))
+    C = c["Cd"].to(torch.float32 if fdt == torch.bfloat16 else fdt).to(fdt).to(dev())
+    D = c["Dd"].to(torch.float32 if fdt == torch.bfloat16 else fdt).to(fdt).to(dev())
+    ref, S = oracle.sddmm(Bm["pos"].numpy(), Bm["crd"].numpy(), host64(B.vals), host64(C),
+                          host64(D))
+    variant = 1 if case == "bf16_mfma" else 0
+    for sc in SDDMM_SCHEDULES:
+        A = spl.sddmm(B, C, D, sched=spl.schedule(**sc, variant=variant))
+        assert_close(host64(A), ref, S, 1e-12 if case == "f64" else 1e-5, f"sddmm {case} {sc}")
+
+
+def test_sddmm_edge_cases():
+    spl = _spl()
+    rs = np.random.RandomState(9)
+    pos, crd, vals = tiny.csr(rs, 200, 150, 0.05, empty_rows={0, 1, 50, 199}, full_rows={3})
+    B = spl.CSR(_t(pos), _t(crd), _t(vals, torch.float32), (200, 150))
+    # K = 1 with unit factors gives A = B exactly
+    A = spl.sddmm(B, torch.ones(200, 1, device=dev()), torch.ones(150, 1, device=dev()))
+    assert np.array_equal(host64(A), host64(B.vals))
+    # ragged K for the vector path, and K = 32 on the matrix cores
+    for K, variant, dt in ((40, 0, torch.float32), (32, 1, torch.bfloat16), (96, 1, torch.bfloat16)):
+        C = _t(rs.uniform(-1, 1, (200, K)), torch.float32).to(dt)
+        D = _t(rs.uniform(-1, 1, (150, K)), torch.float32).to(dt)
+        ref, S = oracle.sddmm(pos, crd, host64(B.vals), host64(C), host64(D))
+        A = spl.sddmm(B, C, D, sched=spl.schedule(variant=variant))
+        assert_close(host64(A), ref, S, 1e-5, f"K={K} variant={variant}")
+    with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
+        spl.sddmm(B, _t(rs.uniform(-1, 1, (200, 40)), torch.bfloat16),
+                  _t(rs.uniform(-1, 1, (150, 40)), torch.bfloat16),
+                  sched=spl.schedule(variant=1))
+
+
+def _csr_dev(spl, m, shape, dtype):
+    return spl.CSR(m["pos"].to(dev()), m["crd"].to(dev()), m["vals"].to(dtype).to(dev()), shape)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spadd3(dtype):
+    spl = _spl()
+    c = configs.config3(scale=0.003, with_dense=False)
+    shape = (c["n"], c["m"])
+    ops = [_csr_dev(spl, c[k], shape, dtype) for k in "BCD"]
+    A = spl.spadd3(*ops)
+    host = [(c[k]["pos"].numpy(), c[k]["crd"].numpy(), host64(o.vals)) for k, o in zip("BCD", ops)]
+    rpos, rcrd, rvals, rS, rnnz = oracle.spadd3(*host)
+    assert np.array_equal(A.pos.cpu().numpy(), rpos)
+    assert np.array_equal(A.crd.cpu().numpy(), rcrd)
+    assert A.crd.numel() == rnnz
+    assert_close(host64(A.vals), rvals, rS, RTOL[dtype], "spadd3")
+    # the pattern does not depend on operand order; B and C swap exactly
+    A2 = spl.spadd3(ops[1], ops[0], ops[2])
+    assert torch.equal(A2.pos, A.pos) and torch.equal(A2.crd, A.crd)
+    assert torch.equal(A2.vals, A.vals)
+    A3 = spl.spadd3(ops[2], ops[1], ops[0])
+    assert torch.equal(A3.crd, A.crd)
+    assert_close(host64(A3.vals), rvals, rS, RTOL[dtype], "spadd3 permuted")
+
+
+def test_spadd3_invariants_and_errors():
+    spl = _spl()
+    rs = np.random.RandomState(10)
+    n, m = 300, 200
+    pos, crd, vals = tiny.csr(rs, n, m, 0.05, empty_rows={0, 7, 299}, kind="int")
+    B = spl.CSR(_t(pos), _t(crd), _t(vals, torch.float32), (n, m))
+    E = spl.CSR(_t(np.zeros(n + 1)), _t(np.zeros(0)), _t(np.zeros(0), torch.float32), (n, m))
+    A = spl.spadd3(B, E, E)
+    assert torch.equal(A.pos, B.pos) and torch.equal(A.crd, B.crd) and torch.equal(A.vals, B.vals)
+    A3 = spl.spadd3(B, B, B)
+    assert torch.equal(A3.pos, B.pos) and torch.equal(A3.crd, B.crd)
+    assert torch.equal(A3.vals, 3 * B.vals)
+    negB = B.with_vals(-B.vals)
+    A0 = spl.spadd3(B, negB, E)
+    assert torch.equal(A0.crd, B.crd) and bool(torch.all(A0.vals == 0))
+    with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
+        spl.spadd3(B, B, B, sched=spl.schedule("nnz", tile=64))
+    # integer values: bit-exact against the oracle
+    p2, c2, v2 = tiny.csr(rs, n, m, 0.05, kind="int")
+    p3, c3, v3 = tiny.csr(rs, n, m, 0.05, kind="int")
+    C = spl.CSR(_t(p2), _t(c2), _t(v2, torch.float32), (n, m))
+    D = spl.CSR(_t(p3), _t(c3), _t(v3, torch.float32), (n, m))
+    A = spl.spadd3(B, C, D)
+    rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
+    assert np.array_equal(A.pos.cpu().numpy(), rpos)
+    assert np.array_equal(A.crd.cpu().numpy(), rcrd)
+    assert np.array_equal(host64(A.vals), rvals)
