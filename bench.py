@@ -44,6 +44,84 @@ def algorithmic_bytes(n, m, nnz, N, vbytes, dbytes, obytes):
     return spmv, spmm
 
 
+def _rate(ms, nbytes, flops):
+    return {"ms": round(ms, 5), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
+
+
+def measure_other_ops(dev, spl, autotune, torch):
+    """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
+    1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
+    200,000^3 CSF tensor with 1e8 nonzeros.  Median of 10 timed calls after
+    3 warm-up calls, inputs resident in HBM."""
+    from workloads import configs
+    res = {}
+    print("[bench] generating the 1e6-row SpAdd3/SDDMM operands", file=sys.stderr, flush=True)
+    c3 = configs.config3(device=dev)
+    n = c3["n"]
+    K = c3["Cd"].shape[1]
+    ops = [spl.CSR(c3[k]["pos"], c3[k]["crd"], c3[k]["vals"].to(torch.float32), (n, n))
+           for k in "BCD"]
+    B = ops[0]
+    nnzB = B.crd.numel()
+    for name, fdt, variant in (("sddmm_f32", torch.float32, 0), ("sddmm_bf16_valu", torch.bfloat16, 0),
+                               ("sddmm_bf16_mfma", torch.bfloat16, 1)):
+        C = c3["Cd"].to(torch.float32).to(fdt)
+        D = c3["Dd"].to(torch.float32).to(fdt)
+        A = torch.empty(nnzB, dtype=torch.float32, device=dev)
+        s = spl.schedule(variant=variant)
+        ms = autotune.time_call(lambda: spl.sddmm(B, C, D, A, sched=s), reps=10, warmup=3)
+        esz = 2 if fdt == torch.bfloat16 else 4
+        nbytes = 4 * (n + 1) + 8 * nnzB + K * n * esz * 2 + 4 * nnzB
+        res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1))
+        del C, D, A
+    ms = autotune.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
+    out = spl.spadd3(*ops)
+    nnzA = out.crd.numel()
+    nnzs = sum(o.crd.numel() for o in ops)
+    nbytes = (3 * 4 * (n + 1) + 4 * nnzs + 4 * (n + 1)) + \
+             (3 * 4 * (n + 1) + 8 * nnzs + 4 * (n + 1) + 8 * nnzA)
+    res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA)
+    res["spadd3_f32"]["nnz_out"] = nnzA
+    del ops, B, out, c3
+    torch.cuda.empty_cache()
+
+    print("[bench] generating the 1e8-nonzero CSF tensor", file=sys.stderr, flush=True)
+    c4 = configs.config4(device=dev)
+    I, J, Kd = c4["I"], c4["J"], c4["K"]
+    F = c4["crd1"].numel()
+    nnz = c4["crd2"].numel()
+    R = c4["C"].shape[1]
+    B32 = spl.CSF(c4["pos1"], c4["crd1"], c4["pos2"], c4["crd2"], c4["vals"].to(torch.float32),
+                  (I, J, Kd))
+    cv = c4["c"].to(torch.float32)
+    At = torch.empty(F, dtype=torch.float32, device=dev)
+    ms = autotune.time_call(lambda: spl.spttv(B32, cv, At), reps=10, warmup=3)
+    res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+    del At
+    for name, dt in (("mttkrp_f32", torch.float32), ("mttkrp_bf16_f32acc", torch.bfloat16)):
+        Bt = B32.with_vals(B32.vals.to(dt))
+        C = c4["C"].to(torch.float32).to(dt)
+        D = c4["D"].to(torch.float32).to(dt)
+        M = torch.empty(I, R, dtype=torch.float32, device=dev)
+        ms = autotune.time_call(lambda: spl.mttkrp(Bt, C, D, M), reps=10, warmup=3)
+        esz = 2 if dt == torch.bfloat16 else 4
+        nbytes = 4 * (I + 1) + 4 * F + 4 * (F + 1) + (4 + esz) * nnz + esz * (J + Kd) * R + 4 * I * R
+        res[name] = _rate(ms, nbytes, 2 * R * (nnz + F))
+        del Bt, C, D, M
+    B64 = B32.with_vals(c4["vals"])
+    C64 = B32.with_vals(c4["vals2"])
+    a = torch.empty(1, dtype=torch.float64, device=dev)
+    ms = autotune.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
+    res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
+    res["workloads"] = {
+        "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
+        "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",
+    }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +131,8 @@ def main():
                     help="shrink the workload (testing only; the headline uses 1.0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-variants", action="store_true", help="skip variant measurements")
+    ap.add_argument("--no-ops", action="store_true",
+                    help="skip the SDDMM/SpAdd3/SpTTV/SpMTTKRP/inner-product measurements")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--sched-spmv", type=str, default=None,
@@ -234,6 +314,11 @@ def main():
             ceil[name] = {"ms_per_nnz_gathers": round(ms, 5),
                           "GB_s_useful": round(nnz * row_bytes / (ms * 1e-3) / 1e9, 1)}
         out["ceilings"] = ceil
+
+    if not args.profile and not args.no_ops:
+        del B64, B16, D64, D16, A64
+        torch.cuda.empty_cache()
+        out["ops"] = measure_other_ops(dev, spl, autotune, torch)
 
     if not args.profile and not args.no_cpu:
         import oracle

@@ -290,6 +290,48 @@ spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_s
                               const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
                               void *A_vals, const spl_schedule *sched, spl_stream stream);
 
+/* ------------------------------------------------- learned schedule choice */
+
+/* Seven sparsity features of a CSR matrix, computed in one pass over pos and
+ * the first and last coordinate of every row, written as 7 floats to `feat`
+ * (device): log2(rows), log2(nnz + 1), mean row degree, log2(1 + degree
+ * variance), log2(1 + max degree), log2(1 + bandwidth) where bandwidth is
+ * max |col - row| over the first and last entry of each row, and the mean
+ * column span of a non-empty row divided by the column count. */
+spl_status spl_features(spl_context *ctx, const spl_sparse *B, float *feat, void *workspace,
+                        size_t workspace_bytes, spl_stream stream);
+
+/* Parameter count of the schedule-selection network with K outputs
+ * (7 -> 64 -> 64 -> K, ReLU; flat FP32 layout W1[64][7], b1[64], W2[64][64],
+ * b2[64], W3[K][64], b3[K]); 0 for K outside 1..256. */
+int64_t spl_mlp_param_count(int K);
+
+/* Forward pass for `batch` feature rows X (batch x 7, device): Y (batch x K,
+ * device) = network(standardize(X)).  `norm` (device, may be NULL) holds 7
+ * means then 7 inverse standard deviations.  `act` (device, may be NULL)
+ * receives the activations the backward pass needs: 2*64*batch + 7*batch
+ * floats. */
+spl_status spl_mlp_forward(spl_context *ctx, int K, const float *params, const float *X,
+                           const float *norm, int64_t batch, float *Y, float *act,
+                           spl_stream stream);
+
+/* Backward pass of the mean squared error mean((Y - T)^2) over the batch
+ * and the K outputs: gradient w.r.t. every parameter into `grad`
+ * (param_count floats, device) and the loss into `loss` (1 float, device,
+ * may be NULL).  Y and act come from spl_mlp_forward on the same batch; T is
+ * batch x K (device).  Workspace: (128 + K + 1) * batch floats. */
+spl_status spl_mlp_backward(spl_context *ctx, int K, const float *params, int64_t batch,
+                            const float *Y, const float *T, const float *act, float *grad,
+                            float *loss, void *workspace, size_t workspace_bytes,
+                            spl_stream stream);
+
+/* One Adam step (Kingma and Ba, 2015) on n parameters, in place: m and v
+ * are the moment buffers (device, zero before step 1), `step` counts from 1
+ * and sets the bias corrections. */
+spl_status spl_adam_step(spl_context *ctx, int64_t n, float *params, float *m, float *v,
+                         const float *grad, float lr, float beta1, float beta2, float eps,
+                         int step, spl_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,12 @@ SIGNATURES = {
     "spl_spadd3_symbolic": (_I32, [_P, _SP, _SP, _SP, _P, ctypes.POINTER(_I64), _SCH, _P, _SZ,
                                    _P]),
     "spl_spadd3_numeric": (_I32, [_P, _SP, _SP, _SP, _P, _P, _P, _SCH, _P]),
+    "spl_features": (_I32, [_P, _SP, _P, _P, _SZ, _P]),
+    "spl_mlp_param_count": (_I64, [ctypes.c_int]),
+    "spl_mlp_forward": (_I32, [_P, ctypes.c_int, _P, _P, _P, _I64, _P, _P, _P]),
+    "spl_mlp_backward": (_I32, [_P, ctypes.c_int, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "spl_adam_step": (_I32, [_P, _I64, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, ctypes.c_int, _P]),
 }
 
 _lib = None

@@ -1071,4 +1071,81 @@ spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_s
     SPL_GUARD_END
 }
 
+spl_status spl_features(spl_context *ctx, const spl_sparse *B, float *feat, void *workspace,
+                        size_t workspace_bytes, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    if (!feat) return fail(ctx, SPL_ERR_ARG, "NULL feature output");
+    SPL_CHECK(set_device(ctx));
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
+                            static_cast<size_t>(spl::feature_ws_bytes()), &ws));
+    SPL_HIP(spl::launch_features(B->dims[0], B->dims[1], B->pos[1], B->crd[1],
+                                 static_cast<double *>(ws), feat,
+                                 static_cast<hipStream_t>(stream)),
+            "features launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+int64_t spl_mlp_param_count(int K) {
+    if (K < 1 || K > 256) return 0;
+    return spl::mlp_param_count(K);
+}
+
+spl_status spl_mlp_forward(spl_context *ctx, int K, const float *params, const float *X,
+                           const float *norm, int64_t batch, float *Y, float *act,
+                           spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (K < 1 || K > 256) return fail(ctx, SPL_ERR_ARG, "K must be 1..256");
+    if (batch < 0 || batch > (1LL << 31) - 1) return fail(ctx, SPL_ERR_ARG, "bad batch size");
+    if (batch > 0 && (!params || !X || !Y)) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(spl::launch_mlp_forward(K, params, X, norm, batch, Y, act,
+                                    static_cast<hipStream_t>(stream)),
+            "MLP forward launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mlp_backward(spl_context *ctx, int K, const float *params, int64_t batch,
+                            const float *Y, const float *T, const float *act, float *grad,
+                            float *loss, void *workspace, size_t workspace_bytes,
+                            spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (K < 1 || K > 256) return fail(ctx, SPL_ERR_ARG, "K must be 1..256");
+    if (batch < 1 || batch > (1LL << 31) - 1) return fail(ctx, SPL_ERR_ARG, "bad batch size");
+    if (!params || !Y || !T || !act || !grad) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    SPL_CHECK(set_device(ctx));
+    const size_t need = static_cast<size_t>((128 + K + 1) * batch) * sizeof(float);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, need, &ws));
+    float *dZ = static_cast<float *>(ws);
+    float *loss_b = dZ + (128 + K) * batch;
+    SPL_HIP(spl::launch_mlp_backward(K, params, batch, Y, T, act, dZ, loss_b, grad, loss,
+                                     static_cast<hipStream_t>(stream)),
+            "MLP backward launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_adam_step(spl_context *ctx, int64_t n, float *params, float *m, float *v,
+                         const float *grad, float lr, float beta1, float beta2, float eps,
+                         int step, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (n < 0 || step < 1) return fail(ctx, SPL_ERR_ARG, "bad size or step");
+    if (n > 0 && (!params || !m || !v || !grad)) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    if (n == 0) return SPL_OK;
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(spl::launch_adam(n, params, m, v, grad, lr, beta1, beta2, eps, step,
+                             static_cast<hipStream_t>(stream)),
+            "Adam launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
 }  // extern "C"

@@ -83,6 +83,19 @@ hipError_t launch_spadd3_numeric(int vtype, int64_t n, const int32_t *bp, const 
                                  const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
                                  hipStream_t s);
 
+// ---- mlp.hip -------------------------------------------------------------
+int64_t mlp_param_count(int K);
+int64_t feature_ws_bytes();
+hipError_t launch_features(int64_t n, int64_t m, const int32_t *pos, const int32_t *crd,
+                           double *part, float *feat, hipStream_t s);
+hipError_t launch_mlp_forward(int K, const float *P, const float *X, const float *norm,
+                              int64_t B, float *Y, float *act, hipStream_t s);
+hipError_t launch_mlp_backward(int K, const float *P, int64_t B, const float *Y, const float *T,
+                               const float *act, float *dZ, float *loss_b, float *grad,
+                               float *loss, hipStream_t s);
+hipError_t launch_adam(int64_t n, float *P, float *m, float *v, const float *g, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+
 // ---- probe.hip -----------------------------------------------------------
 hipError_t launch_probe(int kind, const void *buf, int64_t bytes, int64_t row_bytes,
                         int64_t count, double *out, int64_t blocks, hipStream_t s);

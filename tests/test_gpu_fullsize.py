@@ -1,0 +1,133 @@
+"""Parity at the full benchmark sizes, on sampled outputs the oracle computes
+one by one: the 2,000,000-row power-law matrix (SpMV, SpMM), the three
+1,000,000-row matrices (SDDMM, SpAdd3) and the 1e8-nonzero CSF tensor
+(SpTTV, SpMTTKRP, inner product).  Inputs are generated on the GPU and
+copied to the host for the oracle; the schedules are the ones the benchmark
+chooses among (its autotuner's candidates)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_util import assert_close, host64, need_gpu
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _spl():
+    need_gpu()
+    import paper_2207_13901_amd as spl
+    from paper_2207_13901_amd import autotune
+    return spl, autotune
+
+
+def _sample_rows(pos, k=1500, seed=0):
+    deg = np.diff(pos)
+    rs = np.random.RandomState(seed)
+    heavy = np.argsort(deg)[-60:]
+    rows = np.unique(np.concatenate([rs.choice(len(deg), k, replace=False), heavy,
+                                     [0, len(deg) - 1]]))
+    return rows
+
+
+@pytest.fixture(scope="module")
+def c2():
+    need_gpu()
+    c = configs.config2(device="cuda")
+    host = dict(pos=c["pos"].cpu().numpy(), crd=c["crd"].cpu().numpy())
+    return c, host
+
+
+def test_config2_spmv_sampled(c2):
+    spl, autotune = _spl()
+    c, h = c2
+    n = c["n"]
+    rows = _sample_rows(h["pos"])
+    for dtype, rtol in ((torch.float32, 1e-5), (torch.float64, 1e-12)):
+        B = spl.CSR(c["pos"], c["crd"], c["vals"].to(dtype), (n, n))
+        x = c["x"].to(dtype)
+        ref, S = oracle.spmv(h["pos"], h["crd"], host64(B.vals), host64(x), rows=rows)
+        for cand in autotune.SPMV_CANDIDATES[4:]:  # skip the slowest row splits
+            y = spl.spmv(B, x, sched=spl.schedule(**cand))
+            assert_close(host64(y[torch.as_tensor(rows, device=y.device)]), ref, S, rtol,
+                         f"spmv {dtype} {cand}")
+
+
+def test_config2_spmm_sampled(c2):
+    spl, autotune = _spl()
+    c, h = c2
+    n = c["n"]
+    rows = _sample_rows(h["pos"], k=400, seed=1)
+    for dtype, rtol in ((torch.float32, 1e-5), (torch.bfloat16, 1e-5), (torch.float64, 1e-12)):
+        B = spl.CSR(c["pos"], c["crd"], c["vals"].to(torch.float32).to(dtype), (n, n))
+        D = c["B"].to(torch.float32).to(dtype)
+        Dh = host64(D)
+        ref, S = oracle.spmm(h["pos"], h["crd"], host64(B.vals), Dh, rows=rows)
+        for cand in autotune.SPMM_CANDIDATES[1:]:
+            A = spl.spmm(B, D, sched=spl.schedule(**cand))
+            got = host64(A[torch.as_tensor(rows, device=A.device)])
+            assert_close(got, ref, S, rtol, f"spmm {dtype} {cand}")
+        del D
+
+
+def test_config3_sddmm_and_spadd3():
+    spl, _ = _spl()
+    c = configs.config3(device="cuda")
+    n = c["n"]
+    Bm = c["B"]
+    hpos, hcrd = Bm["pos"].cpu().numpy(), Bm["crd"].cpu().numpy()
+    B = spl.CSR(Bm["pos"], Bm["crd"], Bm["vals"].to(torch.float32), (n, n))
+    rows = _sample_rows(hpos, k=3000, seed=2)
+    sub_pos = np.concatenate([[0], np.cumsum(np.diff(hpos)[rows])]).astype(np.int32)
+    sel = np.concatenate([np.arange(hpos[r], hpos[r + 1]) for r in rows])
+    for fdt, variant in ((torch.float32, 0), (torch.bfloat16, 0), (torch.bfloat16, 1)):
+        C = c["Cd"].to(torch.float32).to(fdt)
+        D = c["Dd"].to(torch.float32).to(fdt)
+        A = spl.sddmm(B, C, D, sched=spl.schedule(variant=variant))
+        Ch = host64(C[torch.as_tensor(rows, device=C.device)])
+        ref, S = oracle.sddmm(sub_pos, hcrd[sel], host64(B.vals)[sel], Ch, host64(D))
+        assert_close(host64(A)[sel], ref, S, 1e-5, f"sddmm {fdt} variant {variant}")
+        del C, D
+    ops = [spl.CSR(c[k]["pos"], c[k]["crd"], c[k]["vals"].to(torch.float32), (n, n))
+           for k in "BCD"]
+    A = spl.spadd3(*ops)
+    host = [(c[k]["pos"].cpu().numpy(), c[k]["crd"].cpu().numpy(), host64(o.vals))
+            for k, o in zip("BCD", ops)]
+    rpos, rcrd, rvals, rS, rnnz = oracle.spadd3(*host)
+    assert np.array_equal(A.pos.cpu().numpy(), rpos)
+    assert np.array_equal(A.crd.cpu().numpy(), rcrd)
+    assert_close(host64(A.vals), rvals, rS, 1e-5, "spadd3 full size")
+
+
+def test_config4_csf_ops():
+    spl, _ = _spl()
+    c = configs.config4(device="cuda")
+    I, J, K = c["I"], c["J"], c["K"]
+    h = {k: c[k].cpu().numpy() for k in ("pos1", "crd1", "pos2", "crd2")}
+    vals32 = c["vals"].to(torch.float32)
+    B = spl.CSF(c["pos1"], c["crd1"], c["pos2"], c["crd2"], vals32, (I, J, K))
+    cv = c["c"].to(torch.float32)
+    # SpTTV over every fiber (one oracle pass)
+    A = spl.spttv(B, cv)
+    ref, S = oracle.spttv(h["pos1"], h["pos2"], h["crd2"], host64(vals32), host64(cv))
+    assert_close(host64(A), ref, S, 1e-5, "spttv full size")
+    del A, ref, S
+    # MTTKRP on sampled slices, FP32 and BF16
+    rows = _sample_rows(h["pos1"], k=300, seed=3)
+    for dt in (torch.float32, torch.bfloat16):
+        Bt = B.with_vals(vals32.to(dt))
+        C = c["C"].to(torch.float32).to(dt)
+        D = c["D"].to(torch.float32).to(dt)
+        M = spl.mttkrp(Bt, C, D)
+        ref, S = oracle.mttkrp(h["pos1"], h["crd1"], h["pos2"], h["crd2"], host64(Bt.vals),
+                               host64(C), host64(D), rows=rows)
+        assert_close(host64(M[torch.as_tensor(rows, device=M.device)]), ref, S, 1e-5,
+                     f"mttkrp {dt}")
+    # inner product in FP64: uniform[0, 1] values, so no cancellation
+    B64 = B.with_vals(c["vals"])
+    C64 = B.with_vals(c["vals2"])
+    a = spl.inner(B64, C64)
+    ref, S = oracle.inner((h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals"].cpu().numpy()),
+                          (h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals2"].cpu().numpy()))
+    assert abs(float(a.item()) - ref) <= 1e-12 * S
