@@ -97,18 +97,27 @@ def measure_other_ops(dev, spl, autotune, torch):
                   (I, J, Kd))
     cv = c4["c"].to(torch.float32)
     At = torch.empty(F, dtype=torch.float32, device=dev)
-    ms = autotune.time_call(lambda: spl.spttv(B32, cv, At), reps=10, warmup=3)
+    # SpTTV is the SpMV leaf on the fiber level: the same candidate schedules
+    best_t, res_t = autotune.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
+                                    autotune.SPMV_CANDIDATES, reps=5)
+    st = spl.schedule(**best_t)
+    ms = autotune.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
     res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+    res["spttv_f32"]["schedule"] = best_t
     del At
     for name, dt in (("mttkrp_f32", torch.float32), ("mttkrp_bf16_f32acc", torch.bfloat16)):
         Bt = B32.with_vals(B32.vals.to(dt))
         C = c4["C"].to(torch.float32).to(dt)
         D = c4["D"].to(torch.float32).to(dt)
         M = torch.empty(I, R, dtype=torch.float32, device=dev)
-        ms = autotune.time_call(lambda: spl.mttkrp(Bt, C, D, M), reps=10, warmup=3)
+        best_k, _ = autotune.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
+                                    autotune.MTTKRP_CANDIDATES, reps=3)
+        sk = spl.schedule(**best_k)
+        ms = autotune.time_call(lambda: spl.mttkrp(Bt, C, D, M, sched=sk), reps=10, warmup=3)
         esz = 2 if dt == torch.bfloat16 else 4
         nbytes = 4 * (I + 1) + 4 * F + 4 * (F + 1) + (4 + esz) * nnz + esz * (J + Kd) * R + 4 * I * R
         res[name] = _rate(ms, nbytes, 2 * R * (nnz + F))
+        res[name]["schedule"] = best_k
         del Bt, C, D, M
     B64 = B32.with_vals(c4["vals"])
     C64 = B32.with_vals(c4["vals2"])
@@ -201,6 +210,36 @@ def main():
     ws_m = spl.workspace(N.OP_SPMM, B32, N_COLS, sm)
     print(f"[bench] schedules spmv={best_v} spmm={best_m}", file=sys.stderr, flush=True)
 
+    # the learned selector's choice for this matrix (features and network on
+    # the GPU), timed against the exhaustive autotuner's choice
+    learned_out = None
+    if not args.profile and res_v and res_m:
+        from paper_2207_13901_amd import learned
+        learned_out = {}
+        for op, best, res, call in (
+                ("spmv", best_v, res_v, lambda s: spl.spmv(B32, x32, y32, sched=s)),
+                ("spmm", best_m, res_m, lambda s: spl.spmm(B32, D32, A32, sched=s))):
+            path = os.path.join(learned.DATA_DIR, f"selector_{op}.json")
+            if not os.path.exists(path):
+                continue
+            sel = learned.Selector.from_json(json.load(open(path)))
+            choice = sel.choose(B32)
+            sc = spl.schedule(**choice)
+            t_learned = autotune.time_call(lambda: call(sc), reps=10, warmup=3)
+            t_best = autotune.time_call(lambda: call(spl.schedule(**best)), reps=10, warmup=3)
+            learned_out[op] = {"learned_choice": choice, "autotuned_choice": best,
+                               "learned_ms": round(t_learned, 5), "autotuned_ms": round(t_best, 5),
+                               "regret": round(t_learned / t_best - 1.0, 4)}
+        regret_path = os.path.join(learned.DATA_DIR, "regret.json")
+        if os.path.exists(regret_path):
+            rep = json.load(open(regret_path))
+            learned_out["held_out_corpus"] = {
+                op: {"learned_mean_regret": round(rep[op]["learned"]["mean"], 4),
+                     "library_default_mean_regret": round(rep[op]["library_default"]["mean"], 4),
+                     "best_fixed_mean_regret": round(rep[op]["best_fixed_on_train"]["mean"], 4),
+                     "paper_rule_mean_regret": round(rep[op]["paper_rule"]["mean"], 4),
+                     "matrices": rep[op]["held_out_matrices"]} for op in ("spmv", "spmm")}
+
     def step():
         spl.spmv(B32, x32, y32, sched=sv, ws=ws_v)
         spl.spmm(B32, D32, A32, sched=sm, ws=ws_m)
@@ -277,6 +316,9 @@ def main():
         },
     }
 
+    if learned_out is not None:
+        out["learned"] = learned_out
+
     if not args.profile and not args.no_variants and res_v and res_m:
         var = {}
         bv64, bm64 = algorithmic_bytes(n, n, nnz, N_COLS, 8, 8, 8)
@@ -304,15 +346,18 @@ def main():
         big = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB
         ms = autotune.time_call(lambda: spl.probe(0, big), reps=5, warmup=2)
         ceil = {"stream_read_GB_s": round(big.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
+        # nnz random row reads, the gather pattern of one SpMV / SpMM call,
+        # from tables of growing size (L2 = 4 MB per XCD, MALL = 256 MB)
+        for row_bytes, mbs in ((4, (2, 8, 64)), (8, (16,)), (128, (8, 64, 128, 256, 1024)),
+                               (256, (512,))):
+            for mb in mbs:
+                table = big[: mb * (1 << 18)]
+                ms = autotune.time_call(
+                    lambda: spl.probe(1, table, row_bytes=row_bytes, count=nnz), reps=5, warmup=2)
+                ceil[f"gather_{row_bytes}B_rows_from_{mb}MB"] = {
+                    "ms_per_nnz_gathers": round(ms, 5),
+                    "Grows_per_s": round(nnz / (ms * 1e-3) / 1e9, 2)}
         del big
-        for name, table, row_bytes in (("gather_4B_rows_from_8MB", x32, 4),
-                                       ("gather_8B_rows_from_16MB", x64, 8),
-                                       ("gather_128B_rows_from_256MB", D32, 128),
-                                       ("gather_256B_rows_from_512MB", D64, 256)):
-            ms = autotune.time_call(lambda: spl.probe(1, table, row_bytes=row_bytes, count=nnz),
-                                    reps=5, warmup=2)
-            ceil[name] = {"ms_per_nnz_gathers": round(ms, 5),
-                          "GB_s_useful": round(nnz * row_bytes / (ms * 1e-3) / 1e9, 1)}
         out["ceilings"] = ceil
 
     if not args.profile and not args.no_ops:

@@ -28,6 +28,15 @@ SPMM_CANDIDATES: List[Dict] = (
 )
 
 
+MTTKRP_CANDIDATES: List[Dict] = [
+    dict(kind="merge", tile=512, col_tile=32, items_per_lane=16),
+    dict(kind="merge", tile=2048, col_tile=32, items_per_lane=16),
+    dict(kind="merge", tile=256, col_tile=32, items_per_lane=8),
+    dict(kind="nnz", tile=2048, col_tile=32, items_per_lane=16),
+    dict(kind="nnz", tile=512, col_tile=32, items_per_lane=8),
+]
+
+
 def time_call(fn: Callable[[], object], reps: int = 5, warmup: int = 2) -> float:
     """Median milliseconds of fn() over `reps` runs on the current stream."""
     for _ in range(warmup):

@@ -109,15 +109,26 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
                         : Acc(0);
         const int64_t P0 = s_fp[b0], P1 = s_fp[b1];
         const int np = static_cast<int>(P1 - P0);
+        {
+            // every index and value load, then every D-row gather, then the LDS
+            // stores: kPosCap independent gathers in flight per lane
+            int kq[kPosCap];
+            Acc vq[kPosCap], dq[kPosCap];
 #pragma unroll
-        for (int q = 0; q < kPosCap; ++q) {
-            Acc dv = 0;
-            if (q < np && colok) {
-                const int64_t p = P0 + q;
-                dv = widen<Acc>(load_stream(vals + p)) *
-                     widen<Acc>(D[static_cast<int64_t>(load_stream(crd2 + p)) * ldd + col]);
+            for (int q = 0; q < kPosCap; ++q) {
+                kq[q] = 0;
+                vq[q] = 0;
+                if (q < np) {
+                    kq[q] = load_stream(crd2 + P0 + q);
+                    vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+                }
             }
-            s_dv[g][q][lane] = dv;
+#pragma unroll
+            for (int q = 0; q < kPosCap; ++q)
+                dq[q] = (q < np && colok) ? widen<Acc>(D[static_cast<int64_t>(kq[q]) * ldd + col])
+                                          : Acc(0);
+#pragma unroll
+            for (int q = 0; q < kPosCap; ++q) s_dv[g][q][lane] = vq[q] * dq[q];
         }
 
         Acc acc = 0;
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
                 s_head[g][lane] = acc;
                 first = false;
             } else if (colok) {
-                A[(ci + r) * lda + col] = acc;
+                store_stream(A + (ci + r) * lda + col, acc);
             }
             acc = 0;
         };
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
             for (int gg = 0; gg < G; ++gg) {
                 if (s_done[gg] > 0) {
                     const Acc v = c + s_head[gg][lane];
-                    if (colok) A[(ci + s_a0[gg]) * lda + col] = v;
+                    if (colok) store_stream(A + (ci + s_a0[gg]) * lda + col, v);
                     c = s_tail[gg][lane];
                 } else {
                     c += s_tail[gg][lane];

@@ -46,6 +46,13 @@ __device__ __forceinline__ bf16 load_stream(const bf16 *p) {
     return r;
 }
 
+// Non-temporal stores for outputs written exactly once, so that the
+// streamed results do not evict the gathered dense operand from L2/MALL.
+template <typename T>
+__device__ __forceinline__ void store_stream(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // Sum over aligned groups of L lanes (L a power of two <= 64) with xor
 // butterflies; every lane of the group ends with the group total.
 template <int L, typename T>

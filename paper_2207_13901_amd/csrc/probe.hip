@@ -49,13 +49,27 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_probe_gather(const float *__restrict__ table,
                                                          int64_t rows, int64_t count,
                                                          double *__restrict__ out) {
+    // each lane group keeps kInFlight independent row reads outstanding
+    constexpr int kInFlight = 8;
     float acc = 0.f;
     const int lane = threadIdx.x % W;
     const int64_t groups = static_cast<int64_t>(gridDim.x) * (kBlock / W);
-    for (int64_t q = static_cast<int64_t>(blockIdx.x) * (kBlock / W) + threadIdx.x / W; q < count;
-         q += groups) {
-        const int64_t r = static_cast<int64_t>(mix64(static_cast<uint64_t>(q)) % static_cast<uint64_t>(rows));
-        acc += table[r * W + lane];
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kBlock / W) + threadIdx.x / W;
+    // rows used: the largest power of two <= rows, so the index is a mask
+    // (a 64-bit modulo would make the probe compute-bound)
+    uint64_t mask = 1;
+    while (mask * 2 <= static_cast<uint64_t>(rows)) mask *= 2;
+    mask -= 1;
+    for (int64_t q0 = g0 * kInFlight; q0 < count; q0 += groups * kInFlight) {
+        float v[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            const int64_t q = q0 + u;
+            const int64_t r = static_cast<int64_t>(mix64(static_cast<uint64_t>(q)) & mask);
+            v[u] = q < count ? table[r * W + lane] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) acc += v[u];
     }
     block_store_sum(acc, out);
 }

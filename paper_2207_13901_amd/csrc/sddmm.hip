@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_valu(
             a1 = group_sum<32>(a1);
             a2 = group_sum<32>(a2);
             if (lane == 0) {
-                out[p] = static_cast<V>(widen<Acc>(load_stream(bv + p)) * a1);
-                if (has2) out[p2] = static_cast<V>(widen<Acc>(load_stream(bv + p2)) * a2);
+                store_stream(out + p, static_cast<V>(widen<Acc>(load_stream(bv + p)) * a1));
+                if (has2) store_stream(out + p2, static_cast<V>(widen<Acc>(load_stream(bv + p2)) * a2));
             }
         }
         ci = ei;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_mfma(
             if (live && kg == r / 4) {
                 const int e = r % 4;
                 const float d = e == 0 ? acc[0] : e == 1 ? acc[1] : e == 2 ? acc[2] : acc[3];
-                out[cp + k] = load_stream(bv + cp + k) * d;
+                store_stream(out + cp + k, load_stream(bv + cp + k) * d);
             }
         }
         ci = ei;

@@ -70,15 +70,38 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
     apos[i + 1] = merge3<false, float>(m, i, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
+// Numeric phase.  The 256 rows of a workgroup own one contiguous run of the
+// output, [apos[r0], apos[r0 + 256]).  When it fits in LDS, every lane
+// merges its row into LDS and the workgroup then writes the run with
+// coalesced stores; a longer run is written directly by the lanes.
+constexpr int kFillCap = 3072;
+
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const V *bv,
                                                         const V *cv, const V *dv,
                                                         const int32_t *apos, int32_t *acrd,
                                                         V *aval) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int64_t o = apos[i];
-    merge3<true, V>(m, i, bv, cv, dv, acrd + o, aval + o);
+    __shared__ int32_t s_crd[kFillCap];
+    __shared__ V s_val[kFillCap];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int64_t i = r0 + threadIdx.x;
+    const int64_t base = apos[r0];
+    const int64_t total = apos[r1] - base;
+    if (total <= kFillCap) {
+        if (i < n) {
+            const int64_t o = apos[i] - base;
+            merge3<true, V>(m, i, bv, cv, dv, s_crd + o, s_val + o);
+        }
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < total; k += kBlock) {
+            store_stream(acrd + base + k, s_crd[k]);
+            store_stream(aval + base + k, s_val[k]);
+        }
+    } else if (i < n) {
+        const int64_t o = apos[i];
+        merge3<true, V>(m, i, bv, cv, dv, acrd + o, aval + o);
+    }
 }
 
 // Block sums of x[0..n) in tiles of kScanTile.

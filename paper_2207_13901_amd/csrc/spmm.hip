@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_row(int64_t n, int64_t N,
                 for (int kk = 0; kk < 8; ++kk) acc += vv[kk] * bv[kk];
             }
         }
-        if (colok) Out[row * ldo + col] = narrow<OT>(acc);
+        if (colok) store_stream(Out + row * ldo + col, narrow<OT>(acc));
     }
 }
 
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
                 s_head[g][lane] = acc;
                 first = false;
             } else if (colok) {
-                Out[(ci + r) * ldo + col] = narrow<OT>(acc);
+                store_stream(Out + (ci + r) * ldo + col, narrow<OT>(acc));
             }
             acc = 0;
         };
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
             for (int gg = 0; gg < G; ++gg) {
                 if (s_done[gg] > 0) {
                     const Acc v = c + s_head[gg][lane];
-                    if (colok) Out[(ci + s_a0[gg]) * ldo + col] = narrow<OT>(v);
+                    if (colok) store_stream(Out + (ci + s_a0[gg]) * ldo + col, narrow<OT>(v));
                     c = s_tail[gg][lane];
                 } else {
                     c += s_tail[gg][lane];

@@ -56,7 +56,58 @@ __global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *_
         acc += acc2;
     }
     acc = group_sum<L>(acc);
-    if (row < n && lane == 0) y[row] = static_cast<V>(acc);
+    if (row < n && lane == 0) store_stream(y + row, static_cast<V>(acc));
+}
+
+// Row split with one lane per row and kRows rows per lane (rows
+// r0 + lane + 256 k): every step issues the next position of all of the
+// lane's rows at once, so short rows (fibers of a CSF tensor) keep kRows
+// independent gathers in flight instead of one.
+template <typename V, int kRows>
+__global__ __launch_bounds__(kBlock) void k_spmv_row_multi(int64_t n, const int32_t *__restrict__ pos,
+                                                           const int32_t *__restrict__ crd,
+                                                           const V *__restrict__ vals,
+                                                           const V *__restrict__ x,
+                                                           V *__restrict__ y) {
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock * kRows + threadIdx.x;
+    int p[kRows], e[kRows];
+    double acc[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int64_t r = r0 + static_cast<int64_t>(k) * kBlock;
+        p[k] = r < n ? pos[r] : 0;
+        e[k] = r < n ? pos[r + 1] : 0;
+        acc[k] = 0.0;
+    }
+    for (;;) {
+        bool any = false;
+        int c[kRows];
+        V v[kRows], xv[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            if (p[k] < e[k]) {
+                any = true;
+                c[k] = load_stream(crd + p[k]);
+                v[k] = load_stream(vals + p[k]);
+            }
+        }
+        if (!any) break;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k)
+            if (p[k] < e[k]) xv[k] = x[c[k]];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            if (p[k] < e[k]) {
+                acc[k] += to_f64(v[k]) * to_f64(xv[k]);
+                ++p[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int64_t r = r0 + static_cast<int64_t>(k) * kBlock;
+        if (r < n) store_stream(y + r, static_cast<V>(acc[k]));
+    }
 }
 
 // Inclusive segmented sum across the 256 lanes of a workgroup.  Lanes are
@@ -174,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
                 s_open = v;
         }
         __syncthreads();
-        for (int k = tid; k < nr; k += kBlock) y[ci + k] = static_cast<V>(s_out[k]);
+        for (int k = tid; k < nr; k += kBlock) store_stream(y + ci + k, static_cast<V>(s_out[k]));
         open = s_open;
         ci = ei;
         cp = ep;
@@ -193,7 +244,7 @@ hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int
         return hipGetLastError();
     };
     switch (lanes) {
-    case 1: return go(k_spmv_row<1, V>, 256);
+    case 1: return go(k_spmv_row_multi<V, 4>, 1024);
     case 2: return go(k_spmv_row<2, V>, 128);
     case 4: return go(k_spmv_row<4, V>, 64);
     case 8: return go(k_spmv_row<8, V>, 32);

@@ -42,6 +42,14 @@ SPMM_CANDIDATES: List[Dict] = [
 ]
 SPMM_COLS = 32
 
+# What SPL_SCHED_DEFAULT resolves to for these operands (merge split, SpMV:
+# 8 items per lane and one 2048-item chunk per tile; SpMM with 32 columns:
+# col_tile 32, 16 items per group, four 128-item chunks per tile).
+LIBRARY_DEFAULT = {
+    "spmv": dict(kind="merge", tile=2048, items_per_lane=8),
+    "spmm": dict(kind="merge", tile=512, col_tile=32, items_per_lane=16),
+}
+
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
 
@@ -190,7 +198,9 @@ def evaluate(sel: Selector, X: np.ndarray, times: np.ndarray, train_times: np.nd
     cands = candidates(sel.op)
     # the best single fixed candidate, chosen on the training set
     fixed = int(np.argmin([np.mean(train_times[:, k] / train_times.min(1)) for k in range(K)]))
-    default = next(k for k, c in enumerate(cands) if c["kind"] == "merge")
+    # the schedule the library resolves SPL_SCHED_DEFAULT to
+    lib_default = LIBRARY_DEFAULT[sel.op]
+    default = next(k for k, c in enumerate(cands) if c == lib_default)
     rule_kind = "row" if sel.op == "spmv" else "nnz"
     rule = min((k for k, c in enumerate(cands) if c["kind"] == rule_kind),
                key=lambda k: np.mean(train_times[:, k] / train_times.min(1)))
