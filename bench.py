@@ -34,6 +34,52 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 N_COLS = 32
+# HBM traffic of the SpMM leaf measured with hardware counters (FETCH_SIZE,
+# WRITE_SIZE, each scaled against a plain 1 GiB device copy); used only while
+# the kernel sources are the ones the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_leaf_traffic_powerlaw2M.txt")
+SPMM_SOURCES = [os.path.join(ROOT, "paper_2207_13901_amd", "csrc", f)
+                for f in ("spmm.hip", "device.hpp")]
+
+
+def sources_digest(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(schedule):
+    """Counter-measured HBM bytes per SpMM leaf launch, or None when the
+    record is missing, was taken on other kernel sources or on another
+    schedule."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    try:
+        if rec.get("sources_digest") != sources_digest(SPMM_SOURCES):
+            return None
+        if json.loads(rec["schedule"]) != schedule:
+            return None
+        return int(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def spmm_kernel_name(sched):
+    """Leaf kernel a SpMM schedule dispatches (FP32, col_tile 32)."""
+    kind = sched.get("kind", "merge")
+    if kind == "row":
+        return "k_spmm_row"
+    if kind == "nnz":
+        return "k_spmm_tiles"
+    return "k_spmm_wave" if sched.get("col_tile", 32) >= 32 else "k_spmm_pipe"
 
 
 def algorithmic_bytes(n, m, nnz, N, vbytes, dbytes, obytes):
@@ -50,10 +96,12 @@ def _rate(ms, nbytes, flops):
             "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
 
 
-def measure_other_ops(dev, spl, autotune, torch):
+def measure_other_ops(dev, spl, autotune, torch, fixed=None):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
-    200,000^3 CSF tensor with 1e8 nonzeros.  Median of 10 timed calls after
+    200,000^3 CSF tensor with 1e8 nonzeros.  SpTTV and SpMTTKRP run with the
+    autotuned schedule unless `fixed` gives one ({"spttv": {...},
+    "mttkrp": {...}}).  Median of 10 timed calls after
     3 warm-up calls, inputs resident in HBM."""
     from workloads import configs
     res = {}
@@ -98,7 +146,11 @@ def measure_other_ops(dev, spl, autotune, torch):
     cv = c4["c"].to(torch.float32)
     At = torch.empty(F, dtype=torch.float32, device=dev)
     # SpTTV is the SpMV leaf on the fiber level: the same candidate schedules
-    best_t, res_t = autotune.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
+    fixed = fixed or {}
+    if "spttv" in fixed:
+        best_t = fixed["spttv"]
+    else:
+        best_t, _ = autotune.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
                                     autotune.SPMV_CANDIDATES, reps=5)
     st = spl.schedule(**best_t)
     ms = autotune.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
@@ -110,8 +162,11 @@ def measure_other_ops(dev, spl, autotune, torch):
         C = c4["C"].to(torch.float32).to(dt)
         D = c4["D"].to(torch.float32).to(dt)
         M = torch.empty(I, R, dtype=torch.float32, device=dev)
-        best_k, _ = autotune.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
-                                    autotune.MTTKRP_CANDIDATES, reps=3)
+        if "mttkrp" in fixed:
+            best_k = fixed["mttkrp"]
+        else:
+            best_k, _ = autotune.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
+                                        autotune.MTTKRP_CANDIDATES, reps=3)
         sk = spl.schedule(**best_k)
         ms = autotune.time_call(lambda: spl.mttkrp(Bt, C, D, M, sched=sk), reps=10, warmup=3)
         esz = 2 if dt == torch.bfloat16 else 4
@@ -148,6 +203,10 @@ def main():
                     help="JSON schedule for SpMV instead of autotuning")
     ap.add_argument("--sched-spmm", type=str, default=None,
                     help="JSON schedule for SpMM instead of autotuning")
+    ap.add_argument("--sched", action="append", default=[], metavar="OP=JSON",
+                    help="fixed schedule for spttv or mttkrp (repeatable)")
+    ap.add_argument("--ops-only", action="store_true",
+                    help="only the SDDMM/SpAdd3/SpTTV/SpMTTKRP/inner-product measurements")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a 1 GiB device copy first (counter scale reference)")
     args = ap.parse_args()
@@ -166,6 +225,14 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    fixed = {}
+    for item in args.sched:
+        op, js = item.split("=", 1)
+        fixed[op] = json.loads(js)
+    if args.ops_only:
+        print(json.dumps({"ops": measure_other_ops(dev, spl, autotune, torch, fixed)}),
+              flush=True)
+        return
     t0 = time.time()
     c2 = configs.config2(device=dev, scale=args.scale, N=N_COLS)
     torch.cuda.synchronize()
@@ -289,13 +356,13 @@ def main():
             "schedule_spmv": best_v, "schedule_spmm": best_m,
         },
         "roofline": {
-            "kernel": "SpMM leaf (k_spmm_tiles / k_spmm_row), FP32",
+            "kernel": f"SpMM leaf ({spmm_kernel_name(best_m)}), FP32",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": counted_traffic(best_m),
             "algorithmic_bytes_per_launch": bytes_m32,
             "avg_launch_ms": round(spmm_ms, 5),
             "launches": lm,
@@ -363,7 +430,7 @@ def main():
     if not args.profile and not args.no_ops:
         del B64, B16, D64, D16, A64
         torch.cuda.empty_cache()
-        out["ops"] = measure_other_ops(dev, spl, autotune, torch)
+        out["ops"] = measure_other_ops(dev, spl, autotune, torch, fixed)
 
     if not args.profile and not args.no_cpu:
         import oracle
@@ -390,6 +457,8 @@ def main():
                        f"rows 0..{rows_m} ({int(pos[rows_m])} nnz, {t3 - t2:.2f}s); "
                        "single-threaded long-double C loops"),
         }
+    if args.profile:
+        out["sources_digest"] = sources_digest(SPMM_SOURCES)
     print(json.dumps(out), flush=True)
 
 

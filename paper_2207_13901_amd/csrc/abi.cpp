@@ -298,6 +298,8 @@ Pieces pieces_for(const Plan &p, int64_t rows, int64_t nnz, int64_t chunk) {
 }
 
 int64_t spmv_chunk(const Plan &p) { return 256 * p.items; }
+// Merged items per leaf chunk: lane groups of one workgroup times the items
+// each group walks.
 int64_t spmm_chunk(const Plan &p) { return (256 / p.col_tile) * p.items; }
 
 size_t tiled_ws(const Pieces &q, int64_t ncols, size_t elem) {
@@ -809,9 +811,9 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMM, s);
-    SPL_HIP(spl::launch_spmm_tiles(B->vtype, A->dtype, p.col_tile, p.items, n, N, B->pos[1],
-                                   B->crd[1], B->vals, C->data, C->ld, A->data, A->ld, cv.tiles,
-                                   q.stride, cv.carry, s),
+    SPL_HIP(spl::launch_spmm_tiles(B->vtype, p.col_tile, p.items, n, N, B->pos[1], B->crd[1],
+                                   B->vals, C->data, C->ld, A->data, A->ld, cv.tiles, q.stride,
+                                   /*exact_chunks=*/p.kind == SPL_MERGE, cv.carry, s),
             "SpMM tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmm_fixup(B->vtype, n, N, cv.tiles, q.stride, cv.carry, A->data, A->ld,

@@ -42,11 +42,13 @@ hipError_t launch_spmv_fixup(int dtype, int64_t n, const Tiles &t, int64_t strid
 hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_t N,
                            const int32_t *pos, const int32_t *crd, const void *vals,
                            const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
-hipError_t launch_spmm_tiles(int vtype, int otype, int col_tile, int items, int64_t n,
-                             int64_t N, const int32_t *pos, const int32_t *crd,
-                             const void *vals, const void *B, int64_t ldb, void *C,
-                             int64_t ldc, const Tiles &t, int64_t stride, void *carry,
-                             hipStream_t s);
+// exact_chunks: every piece of `t` holds at most one leaf chunk
+// ((256 / col_tile) * items merged items), as the merge split is cut here;
+// the leaf then pipelines its staging loads (k_spmm_pipe).
+hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int64_t n, int64_t N,
+                             const int32_t *pos, const int32_t *crd, const void *vals,
+                             const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
+                             int64_t stride, bool exact_chunks, void *carry, hipStream_t s);
 hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, int64_t stride,
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 

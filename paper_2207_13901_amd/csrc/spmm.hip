@@ -23,6 +23,9 @@
 //    combined across groups in order by group 0 (G steps), and the row open
 //    at the tile end is written to the tile's carry vector.  k_carry_fixup
 //    (carry.hpp) adds carries into their rows in a fixed order.  Deterministic, no atomics.
+//
+//  * k_spmm_pipe: the merge-split form of k_spmm_tiles, with the staging
+//    loads of the next chunk software-pipelined behind the current walk.
 #include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
@@ -176,6 +179,153 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
     if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * N + col] = open;
 }
 
+// Merge-split pieces are exactly one chunk each, so every chunk's bounds
+// are known in advance and the staging can be software-pipelined: while a
+// workgroup gathers and walks chunk c (LDS buffer c % 2), its lanes already
+// hold in registers the row ends, coordinates and values of chunk c + 1,
+// loaded before chunk c's gathers were issued, and the bounds of chunk c + 2
+// one iteration earlier still.  After the walk they are stored to the other
+// LDS buffer, so the loads of the next chunk never sit on the critical path.
+// The walk, the cross-group pass and the carries are those of k_spmm_tiles.
+template <int W, int ITEMS, typename V, typename BT, typename OT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_spmm_pipe(
+    int64_t n, int64_t N, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
+    int64_t ldo, const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos,
+    int64_t npieces, int64_t stride, Acc *__restrict__ carry) {
+    constexpr int G = kBlock / W;
+    constexpr int kChunk = G * ITEMS;
+    constexpr int kPer = (kChunk + kBlock - 1) / kBlock;
+    __shared__ int32_t s_end[2][kChunk];
+    __shared__ int32_t s_crd[2][kChunk];
+    __shared__ Acc s_val[2][kChunk];
+    __shared__ Acc s_head[G][W];
+    __shared__ Acc s_tail[G][W];
+    __shared__ int s_done[G];
+    __shared__ int s_a0[G];
+
+    const int tid = threadIdx.x;
+    const int g = tid / W, lane = tid % W;
+    const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
+    const bool colok = col < N;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
+    auto bound_i = [&](int64_t c) { return static_cast<int64_t>(trow[c < pend ? c : pend]); };
+    auto bound_p = [&](int64_t c) { return static_cast<int64_t>(tpos[c < pend ? c : pend]); };
+
+    int r_end[kPer], r_crd[kPer];
+    Acc r_val[kPer];
+    // issue the loads of the chunk [(fi, fp), (ei, ep)) into registers
+    auto fetch = [&](int64_t fi, int64_t fp, int nr, int np) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < nr) r_end[j] = pos[fi + 1 + k];
+            if (k < np) {
+                r_crd[j] = load_stream(crd + fp + k);
+                r_val[j] = widen<Acc>(load_stream(vals + fp + k));
+            }
+        }
+    };
+    auto stash = [&](int buf, int nr, int np) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < nr) s_end[buf][k] = r_end[j];
+            if (k < np) {
+                s_crd[buf][k] = r_crd[j];
+                s_val[buf][k] = r_val[j];
+            }
+        }
+    };
+
+    // bounds of the current chunk (ci, cp)-(ei, ep) and of the one after it
+    int64_t ci = bound_i(p0), cp = bound_p(p0);
+    int64_t ei = bound_i(p0 + 1), ep = bound_p(p0 + 1);
+    int64_t ni = bound_i(p0 + 2), np2 = bound_p(p0 + 2);
+    int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
+    fetch(ci, cp, nr, np);
+    stash(0, nr, np);
+    Acc open = 0;
+    int buf = 0;
+    for (int64_t c = p0; c < pend; ++c) {
+        __syncthreads();  // buffer `buf` holds chunk c; the previous pass is done
+        const bool more = c + 1 < pend;
+        const int nnr = static_cast<int>(ni - ei), nnp = static_cast<int>(np2 - ep);
+        const int64_t fi = bound_i(c + 3), fp = bound_p(c + 3);  // for the next iteration
+        if (more) fetch(ei, ep, nnr, nnp);
+
+        const int total = nr + np;
+        const int d0 = min(g * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        const int32_t *send = s_end[buf];
+        auto end_at = [&](int64_t m) { return send[m]; };
+        const int a0 = static_cast<int>(merge_search(d0, nr, np, cp, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, np, cp, end_at));
+        const int b0 = d0 - a0, b1 = d1 - a1;
+        Acc pv[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            pv[k] = 0;
+            if (b0 + k < b1 && colok)
+                pv[k] = s_val[buf][b0 + k] *
+                        widen<Acc>(Bd[static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col]);
+        }
+        Acc acc = 0;
+        int a = a0;
+        bool first = true;
+        auto finish = [&](int r) {
+            if (first) {
+                s_head[g][lane] = acc;
+                first = false;
+            } else if (colok) {
+                store_stream(Out + (ci + r) * ldo + col, narrow<OT>(acc));
+            }
+            acc = 0;
+        };
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (b0 + k < b1) {
+                while (a < a1 && send[a] <= cp + b0 + k) finish(a++);
+                acc += pv[k];
+            }
+        }
+        while (a < a1) finish(a++);
+        s_tail[g][lane] = acc;
+        if (lane == 0) {
+            s_done[g] = a1 - a0;
+            s_a0[g] = a0;
+        }
+        __syncthreads();
+        if (g == 0) {
+            Acc cc = open;
+            for (int gg = 0; gg < G; ++gg) {
+                if (s_done[gg] > 0) {
+                    const Acc v = cc + s_head[gg][lane];
+                    if (colok) store_stream(Out + (ci + s_a0[gg]) * ldo + col, narrow<OT>(v));
+                    cc = s_tail[gg][lane];
+                } else {
+                    cc += s_tail[gg][lane];
+                }
+            }
+            open = cc;
+        }
+        if (more) stash(buf ^ 1, nnr, nnp);
+        ci = ei;
+        cp = ep;
+        ei = ni;
+        ep = np2;
+        ni = fi;
+        np2 = fp;
+        nr = nnr;
+        np = nnp;
+        buf ^= 1;
+    }
+    if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * N + col] = open;
+}
+
+// Order LDS accesses of the lanes of one wave (no workgroup barrier).
+
 template <typename V, typename BT, typename OT, typename Acc>
 struct SpmmTypes {
     static hipError_t row(int W, int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
@@ -200,15 +350,17 @@ struct SpmmTypes {
     template <int W, int ITEMS>
     static hipError_t tiles_w(int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
                               const void *vals, const void *Bd, int64_t ldb, void *Out,
-                              int64_t ldo, const Tiles &t, int64_t stride, void *carry,
-                              hipStream_t s) {
-        dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)),
-                  static_cast<unsigned>((N + W - 1) / W));
+                              int64_t ldo, const Tiles &t, int64_t stride, bool exact,
+                              void *carry, hipStream_t s) {
+        const int64_t tiles = ceil_div(t.ntiles, stride);
+        // pieces of exactly one chunk (merge split): the pipelined leaf
+        dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>((N + W - 1) / W));
         if (grid.y == 0) return hipSuccess;
-        k_spmm_tiles<W, ITEMS, V, BT, OT, Acc><<<grid, kBlock, 0, s>>>(
-            n, N, pos, crd, static_cast<const V *>(vals), static_cast<const BT *>(Bd), ldb,
-            static_cast<OT *>(Out), ldo, t.row, t.pos, t.ntiles, stride,
-            static_cast<Acc *>(carry));
+        auto kern = exact ? k_spmm_pipe<W, ITEMS, V, BT, OT, Acc>
+                          : k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>;
+        kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
+                                     static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out), ldo,
+                                     t.row, t.pos, t.ntiles, stride, static_cast<Acc *>(carry));
         return hipGetLastError();
     }
 
@@ -222,14 +374,16 @@ struct SpmmTypes {
 
     static hipError_t tiles(int W, int items, int64_t n, int64_t N, const int32_t *pos,
                             const int32_t *crd, const void *vals, const void *Bd, int64_t ldb,
-                            void *Out, int64_t ldo, const Tiles &t, int64_t stride, void *carry,
-                            hipStream_t s) {
-#define SPL_SPMM_ITEMS(Wv)                                                                      \
-    if (items <= 8)                                                                             \
-        return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);    \
-    if (items <= 16)                                                                            \
-        return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);   \
-    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, carry, s);
+                            void *Out, int64_t ldo, const Tiles &t, int64_t stride, bool exact,
+                            void *carry, hipStream_t s) {
+#define SPL_SPMM_ITEMS(Wv)                                                                    \
+    if (items <= 8)                                                                           \
+        return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact,      \
+                              carry, s);                                                      \
+    if (items <= 16)                                                                          \
+        return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact,     \
+                               carry, s);                                                     \
+    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s);
         switch (W) {
         case 8: SPL_SPMM_ITEMS(8)
         case 16: SPL_SPMM_ITEMS(16)
@@ -263,21 +417,21 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
                                                     ldo, s);
 }
 
-hipError_t launch_spmm_tiles(int vtype, int otype, int col_tile, int items, int64_t n,
-                             int64_t N, const int32_t *pos, const int32_t *crd,
-                             const void *vals, const void *Bd, int64_t ldb, void *Out,
-                             int64_t ldo, const Tiles &t, int64_t stride, void *carry,
-                             hipStream_t s) {
-    (void)otype;
+hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int64_t n, int64_t N,
+                             const int32_t *pos, const int32_t *crd, const void *vals,
+                             const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
+                             int64_t stride, bool exact_chunks, void *carry, hipStream_t s) {
     if (vtype == SPL_F64)
         return SpmmTypes<double, double, double, double>::tiles(col_tile, items, n, N, pos, crd,
                                                                 vals, Bd, ldb, Out, ldo, t, stride,
-                                                                carry, s);
+                                                                exact_chunks, carry, s);
     if (vtype == SPL_F32)
         return SpmmTypes<float, float, float, float>::tiles(col_tile, items, n, N, pos, crd, vals,
-                                                            Bd, ldb, Out, ldo, t, stride, carry, s);
+                                                            Bd, ldb, Out, ldo, t, stride,
+                                                            exact_chunks, carry, s);
     return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, n, N, pos, crd, vals, Bd,
-                                                      ldb, Out, ldo, t, stride, carry, s);
+                                                      ldb, Out, ldo, t, stride, exact_chunks,
+                                                      carry, s);
 }
 
 }  // namespace spl

@@ -22,7 +22,9 @@ TTV_SCHEDULES = [dict(kind="default"), dict(kind="row", lanes_per_row=2),
 MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=32, items_per_lane=8),
                     dict(kind="nnz", tile=300), dict(kind="nnz", tile=4096, col_tile=16),
                     dict(kind="row", tile=3), dict(kind="merge", tile=5000, col_tile=64,
-                                                   items_per_lane=16)]
+                                                   items_per_lane=16),
+                    dict(kind="merge", tile=32, col_tile=32, items_per_lane=16),
+                    dict(kind="merge", tile=1, col_tile=64, items_per_lane=8)]
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
                    dict(kind="merge", tile=512)]
 
