@@ -424,6 +424,14 @@ def main():
                 ceil[f"gather_{row_bytes}B_rows_from_{mb}MB"] = {
                     "ms_per_nnz_gathers": round(ms, 5),
                     "Grows_per_s": round(nnz / (ms * 1e-3) / 1e9, 2)}
+        # the same gathers with 16-byte lanes (a quarter of the load instructions)
+        for row_bytes, mb in ((64, 128), (128, 256)):
+            table = big[: mb * (1 << 18)]
+            ms = autotune.time_call(
+                lambda: spl.probe(2, table, row_bytes=row_bytes, count=nnz), reps=5, warmup=2)
+            ceil[f"gather_{row_bytes}B_rows_16B_lanes_from_{mb}MB"] = {
+                "ms_per_nnz_gathers": round(ms, 5),
+                "Grows_per_s": round(nnz / (ms * 1e-3) / 1e9, 2)}
         del big
         out["ceilings"] = ceil
 

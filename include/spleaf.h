@@ -201,6 +201,8 @@ spl_status spl_timing_read(spl_context *ctx, spl_op op, int64_t *launches, doubl
  *   kind 1: read `count` rows of `row_bytes` (4, 8, 32, 64, 128 or 256) at
  *           pseudo-random row indices of the table `buf` of `bytes` bytes:
  *           the ceiling for random dense-operand gathers.
+ *   kind 2: as kind 1 with 16-byte loads per lane (row_bytes 16, 64, 128
+ *           or 256).
  * `out` (device) receives one double per workgroup (`blocks` of them, at
  * least 1); `buf` must be 16-byte aligned. */
 spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,

@@ -278,8 +278,9 @@ def timing_read(op: int, ctx: Optional[Context] = None):
 def probe(kind: int, buf: torch.Tensor, row_bytes: int = 128, count: int = 0,
           blocks: int = 4096, ctx: Optional[Context] = None) -> torch.Tensor:
     """Memory-system probe (kind 0: stream-read `buf`; kind 1: `count`
-    random `row_bytes` reads from table `buf`).  Returns the per-workgroup
-    partial sums (device)."""
+    random `row_bytes` reads from table `buf`, 4-byte lanes; kind 2: the
+    same with 16-byte lanes).  Returns the per-workgroup partial sums
+    (device)."""
     ctx, stream = _ctx_stream(buf, ctx)
     out = torch.empty(blocks, dtype=torch.float64, device=buf.device)
     nbytes = buf.numel() * buf.element_size()

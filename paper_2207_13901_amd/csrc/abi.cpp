@@ -721,6 +721,10 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
             row_bytes != 128 && row_bytes != 256)
             return fail(ctx, SPL_ERR_ARG, "row_bytes must be 4, 8, 32, 64, 128 or 256");
         if (bytes < row_bytes || count < 0) return fail(ctx, SPL_ERR_ARG, "bad table or count");
+    } else if (kind == 2) {
+        if (row_bytes != 16 && row_bytes != 64 && row_bytes != 128 && row_bytes != 256)
+            return fail(ctx, SPL_ERR_ARG, "row_bytes must be 16, 64, 128 or 256");
+        if (bytes < row_bytes || count < 0) return fail(ctx, SPL_ERR_ARG, "bad table or count");
     } else {
         return fail(ctx, SPL_ERR_ARG, "unknown probe kind %d", kind);
     }

@@ -4,7 +4,8 @@
 //  - k_probe_gather: reads `count` rows of `row_bytes` bytes at pseudo-random
 //    row indices of a table (a SplitMix64 hash of the request number), the
 //    ceiling for the random dense-operand gathers of SpMV/SpMM/MTTKRP/SDDMM
-//    when the table does not fit in the caches.
+//    when the table does not fit in the caches;
+//  - k_probe_gather_vec: the same gathers with 16-byte lanes.
 // Both reduce what they read into one double per workgroup so nothing is
 // optimized away.
 #include "device.hpp"
@@ -74,6 +75,35 @@ __global__ __launch_bounds__(kBlock) void k_probe_gather(const float *__restrict
     block_store_sum(acc, out);
 }
 
+// As k_probe_gather with 16-byte lanes: W lanes read one row of W * 16
+// bytes (the same rows per step as W * 4 four-byte lanes, in a quarter of
+// the load instructions).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_probe_gather_vec(const f32x4 *__restrict__ table,
+                                                             int64_t rows, int64_t count,
+                                                             double *__restrict__ out) {
+    constexpr int kInFlight = 8;
+    float acc = 0.f;
+    const int lane = threadIdx.x % W;
+    const int64_t groups = static_cast<int64_t>(gridDim.x) * (kBlock / W);
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kBlock / W) + threadIdx.x / W;
+    uint64_t mask = 1;
+    while (mask * 2 <= static_cast<uint64_t>(rows)) mask *= 2;
+    mask -= 1;
+    for (int64_t q0 = g0 * kInFlight; q0 < count; q0 += groups * kInFlight) {
+        f32x4 v[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            const int64_t q = q0 + u;
+            const int64_t r = static_cast<int64_t>(mix64(static_cast<uint64_t>(q)) & mask);
+            v[u] = q < count ? table[r * W + lane] : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    block_store_sum(acc, out);
+}
+
 }  // namespace
 
 hipError_t launch_probe(int kind, const void *buf, int64_t bytes, int64_t row_bytes,
@@ -81,6 +111,16 @@ hipError_t launch_probe(int kind, const void *buf, int64_t bytes, int64_t row_by
     dim3 grid(static_cast<unsigned>(blocks));
     if (kind == 0) {
         k_probe_stream<<<grid, kBlock, 0, s>>>(static_cast<const f32x4 *>(buf), bytes / 16, out);
+        return hipGetLastError();
+    }
+    if (kind == 2) {
+        const f32x4 *t4 = static_cast<const f32x4 *>(buf);
+        switch (row_bytes) {
+        case 16: k_probe_gather_vec<1><<<grid, kBlock, 0, s>>>(t4, bytes / 16, count, out); break;
+        case 64: k_probe_gather_vec<4><<<grid, kBlock, 0, s>>>(t4, bytes / 64, count, out); break;
+        case 256: k_probe_gather_vec<16><<<grid, kBlock, 0, s>>>(t4, bytes / 256, count, out); break;
+        default: k_probe_gather_vec<8><<<grid, kBlock, 0, s>>>(t4, bytes / 128, count, out); break;
+        }
         return hipGetLastError();
     }
     const float *t = static_cast<const float *>(buf);

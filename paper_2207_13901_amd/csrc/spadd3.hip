@@ -10,7 +10,10 @@
 // One lane per row merges the three sorted coordinate lists; values are
 // summed in operand order B, C, D over the operands present (a cancellation
 // to zero keeps its coordinate).  The scan is three passes: per-workgroup
-// totals, one workgroup scanning the totals, per-workgroup rescan.
+// totals, one workgroup scanning the totals, per-workgroup rescan.  The
+// numeric phase stages the output in LDS so that its stores are coalesced:
+// one lane per row storing straight to HBM keeps far more partly written
+// lines open than the L2 holds.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -24,57 +27,75 @@ struct Csr3 {
     const int32_t *bp, *bc, *cp, *cc, *dp, *dc;
 };
 
-template <bool kNumeric, typename V>
-__device__ __forceinline__ int32_t merge3(const Csr3 &m, int64_t i, const V *bv, const V *cv,
-                                          const V *dv, int32_t *ocrd, V *oval) {
-    int32_t a = m.bp[i], ae = m.bp[i + 1];
-    int32_t b = m.cp[i], be = m.cp[i + 1];
-    int32_t d = m.dp[i], de = m.dp[i + 1];
-    int32_t k = 0;
-    constexpr int32_t kInf = 0x7fffffff;
-    int32_t xa = a < ae ? m.bc[a] : kInf;
-    int32_t xb = b < be ? m.cc[b] : kInf;
-    int32_t xd = d < de ? m.dc[d] : kInf;
-    for (;;) {
+// Three-way merge of one row's sorted coordinate lists, resumable: next()
+// yields the union's coordinates in increasing order; with values, the sum
+// over the operands present in operand order B, C, D.
+struct Merge3 {
+    static constexpr int32_t kInf = 0x7fffffff;
+    int32_t a, ae, b, be, d, de, xa, xb, xd;
+
+    __device__ __forceinline__ Merge3(const Csr3 &m, int64_t i) {
+        a = m.bp[i];
+        ae = m.bp[i + 1];
+        b = m.cp[i];
+        be = m.cp[i + 1];
+        d = m.dp[i];
+        de = m.dp[i + 1];
+        xa = a < ae ? m.bc[a] : kInf;
+        xb = b < be ? m.cc[b] : kInf;
+        xd = d < de ? m.dc[d] : kInf;
+    }
+
+    __device__ __forceinline__ bool done() const { return min(xa, min(xb, xd)) == kInf; }
+
+    // Advance past the smallest remaining coordinate c; returns c.
+    template <bool kValues, typename V>
+    __device__ __forceinline__ int32_t next(const Csr3 &m, const V *bv, const V *cv, const V *dv,
+                                            V &sum) {
         const int32_t c = min(xa, min(xb, xd));
-        if (c == kInf) break;
-        V sum = 0;
+        V s = 0;
         if (xa == c) {
-            if (kNumeric) sum = bv[a];
+            if (kValues) s = bv[a];
             ++a;
             xa = a < ae ? m.bc[a] : kInf;
         }
         if (xb == c) {
-            if (kNumeric) sum = sum + cv[b];
+            if (kValues) s = s + cv[b];
             ++b;
             xb = b < be ? m.cc[b] : kInf;
         }
         if (xd == c) {
-            if (kNumeric) sum = sum + dv[d];
+            if (kValues) s = s + dv[d];
             ++d;
             xd = d < de ? m.dc[d] : kInf;
         }
-        if (kNumeric) {
-            ocrd[k] = c;
-            oval[k] = sum;
-        }
-        ++k;
+        sum = s;
+        return c;
     }
-    return k;
-}
+};
 
 __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int32_t *apos) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i == 0) apos[0] = 0;
     if (i >= n) return;
-    apos[i + 1] = merge3<false, float>(m, i, nullptr, nullptr, nullptr, nullptr, nullptr);
+    Merge3 mg(m, i);
+    int32_t k = 0;
+    float unused;
+    while (!mg.done()) {
+        mg.next<false, float>(m, nullptr, nullptr, nullptr, unused);
+        ++k;
+    }
+    apos[i + 1] = k;
 }
 
 // Numeric phase.  The 256 rows of a workgroup own one contiguous run of the
-// output, [apos[r0], apos[r0 + 256]).  When it fits in LDS, every lane
-// merges its row into LDS and the workgroup then writes the run with
-// coalesced stores; a longer run is written directly by the lanes.
-constexpr int kFillCap = 3072;
+// output, [apos[r0], apos[r0 + 256]), written in windows of kFillCap
+// entries: in each window every lane continues its row's merge from where
+// it stopped, emitting into LDS the entries whose output index falls in the
+// window, and the workgroup then writes the window with coalesced stores.
+// Each row is merged once whatever its length; only one row's lane works
+// in the windows a long row fills alone.
+constexpr int kFillCap = 4096;
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const V *bv,
@@ -88,19 +109,24 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const
     const int64_t i = r0 + threadIdx.x;
     const int64_t base = apos[r0];
     const int64_t total = apos[r1] - base;
-    if (total <= kFillCap) {
-        if (i < n) {
-            const int64_t o = apos[i] - base;
-            merge3<true, V>(m, i, bv, cv, dv, s_crd + o, s_val + o);
+    const bool mine = i < n;
+    int64_t k = mine ? apos[i] - base : 0;
+    const int64_t hi = mine ? apos[i + 1] - base : 0;
+    Merge3 mg(m, mine ? i : r0);
+    for (int64_t w = 0; w < total; w += kFillCap) {
+        const int64_t we = w + kFillCap < total ? w + kFillCap : total;
+        for (; k < hi && k < we; ++k) {
+            V sum;
+            const int32_t c = mg.next<true, V>(m, bv, cv, dv, sum);
+            s_crd[k - w] = c;
+            s_val[k - w] = sum;
         }
         __syncthreads();
-        for (int64_t k = threadIdx.x; k < total; k += kBlock) {
-            store_stream(acrd + base + k, s_crd[k]);
-            store_stream(aval + base + k, s_val[k]);
+        for (int64_t q = threadIdx.x; q < we - w; q += kBlock) {
+            store_stream(acrd + base + w + q, s_crd[q]);
+            store_stream(aval + base + w + q, s_val[q]);
         }
-    } else if (i < n) {
-        const int64_t o = apos[i];
-        merge3<true, V>(m, i, bv, cv, dv, acrd + o, aval + o);
+        __syncthreads();
     }
 }
 

@@ -231,3 +231,22 @@ def test_spadd3_invariants_and_errors():
     assert np.array_equal(A.pos.cpu().numpy(), rpos)
     assert np.array_equal(A.crd.cpu().numpy(), rcrd)
     assert np.array_equal(host64(A.vals), rvals)
+
+
+def test_spadd3_long_rows_span_output_windows():
+    # rows whose union alone fills several LDS output windows, next to short
+    # and empty rows in the same workgroup and in the next one
+    spl = _spl()
+    rs = np.random.RandomState(11)
+    n, m = 700, 9000
+    pos, crd, vals = tiny.csr(rs, n, m, 0.002, empty_rows={0, 255, 256}, full_rows={5, 300},
+                              kind="int")
+    p2, c2, v2 = tiny.csr(rs, n, m, 0.3, empty_rows={5}, full_rows={254}, kind="int")
+    p3, c3, v3 = tiny.csr(rs, n, m, 0.001, full_rows={699}, kind="int")
+    ops = [spl.CSR(_t(p), _t(c), _t(v, torch.float32), (n, m))
+           for p, c, v in ((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))]
+    A = spl.spadd3(*ops)
+    rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
+    assert np.array_equal(A.pos.cpu().numpy(), rpos)
+    assert np.array_equal(A.crd.cpu().numpy(), rcrd)
+    assert np.array_equal(host64(A.vals), rvals)
