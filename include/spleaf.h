@@ -222,7 +222,14 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
 /* SpMM  A(i,j) = B(i,k) * C(k,j)   (Sec. VI-A).
  * B CSR n x m; C dense m x N; A dense n x N.  dtypes (vals, C, A): all F64;
  * all F32; or vals and C BF16 with A F32 (F32 accumulation).  Schedules:
- * ROW, NNZ, MERGE (default MERGE); col_tile 8..64 columns per lane group. */
+ * ROW, NNZ, MERGE (default MERGE); col_tile 8..64 columns per lane group.
+ * sched->variant (MERGE): 0 = each lane reads and writes 4 F32, 2 F64 or 4
+ * BF16 consecutive columns with one vector access when N, C->ld, A->ld and
+ * the C and A pointers are multiples of that, col_tile leaves 8 to 32
+ * lanes per group and items_per_lane is 8 or 16 (otherwise one column per
+ * lane); 1 = one column per lane.
+ * The workspace query returns the one-column-per-lane size, enough for
+ * both. */
 spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                     spl_dense *A, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);

@@ -120,6 +120,8 @@ struct Plan {
     int64_t tile = 0;
     int items = 0;
     int col_tile = 0;
+    int variant = 0;
+    int vec = 1;  // SpMM: dense columns per lane
 };
 
 int lanes_for_mean(double mean) {
@@ -166,6 +168,9 @@ spl_status resolve_spmm(spl_context *ctx, const spl_sparse *B, int64_t N, const 
         return fail(ctx, SPL_ERR_ARG, "SpMM items_per_lane must be 8, 16 or 32");
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 256 / ct : 4 * (256 / ct) * p.items);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
+    if (s->variant != 0 && s->variant != 1)
+        return fail(ctx, SPL_ERR_ARG, "SpMM variant must be 0 (default) or 1 (4-byte lanes)");
+    p.variant = s->variant;
     return SPL_OK;
 }
 
@@ -300,7 +305,25 @@ Pieces pieces_for(const Plan &p, int64_t rows, int64_t nnz, int64_t chunk) {
 int64_t spmv_chunk(const Plan &p) { return 256 * p.items; }
 // Merged items per leaf chunk: lane groups of one workgroup times the items
 // each group walks.
-int64_t spmm_chunk(const Plan &p) { return (256 / p.col_tile) * p.items; }
+int64_t spmm_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.items; }
+
+size_t dtype_bytes(int dt) { return dt == SPL_F64 ? 8 : dt == SPL_F32 ? 4 : 2; }
+
+// Vector lanes for the merge-split SpMM leaf (variant 0): each lane reads
+// and writes spl::spmm_vec_width columns with one vector access, when the
+// columns, leading dimensions and pointers allow it and a lane group still
+// has 8 to 32 lanes and walks 8 or 16 items; otherwise one column per lane.
+int spmm_vec(const Plan &p, int vtype, const spl_dense *C, const spl_dense *A) {
+    if (p.kind != SPL_MERGE || p.variant != 0 || p.items > 16) return 1;
+    const int v = spl::spmm_vec_width(vtype);
+    const int64_t lanes = p.col_tile / v;
+    const int64_t N = C->dims[1];
+    const size_t cb = v * dtype_bytes(C->dtype), ab = v * dtype_bytes(A->dtype);
+    const bool ok = lanes >= 8 && lanes <= 32 && N % v == 0 && C->ld % v == 0 &&
+                    A->ld % v == 0 && reinterpret_cast<uintptr_t>(C->data) % cb == 0 &&
+                    reinterpret_cast<uintptr_t>(A->data) % ab == 0;
+    return ok ? v : 1;
+}
 
 size_t tiled_ws(const Pieces &q, int64_t ncols, size_t elem) {
     return 2 * align_up(static_cast<size_t>(q.count + 1) * 4) +
@@ -808,6 +831,8 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
         tm.stop();
         return SPL_OK;
     }
+    // the workspace query assumed one column per lane: the larger size
+    p.vec = spmm_vec(p, B->vtype, C, A);
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmm_ws(B, N, p), &ws));
     const Pieces q = pieces_for(p, n, B->nnz, spmm_chunk(p));
@@ -815,7 +840,7 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMM, s);
-    SPL_HIP(spl::launch_spmm_tiles(B->vtype, p.col_tile, p.items, n, N, B->pos[1], B->crd[1],
+    SPL_HIP(spl::launch_spmm_tiles(B->vtype, p.col_tile, p.items, p.vec, n, N, B->pos[1], B->crd[1],
                                    B->vals, C->data, C->ld, A->data, A->ld, cv.tiles, q.stride,
                                    /*exact_chunks=*/p.kind == SPL_MERGE, cv.carry, s),
             "SpMM tile launch");

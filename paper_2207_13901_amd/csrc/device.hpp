@@ -53,6 +53,85 @@ __device__ __forceinline__ void store_stream(T *p, T v) {
     __builtin_nontemporal_store(v, p);
 }
 
+// Rows of a dense operand read and written VEC consecutive elements per lane
+// (VEC > 1: one vector access of VEC elements, 16 bytes except for 4 BF16;
+// the address must be aligned to the access size).
+typedef float vf32x4 __attribute__((ext_vector_type(4)));
+typedef double vf64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t vu32x4 __attribute__((ext_vector_type(4)));
+
+template <int VEC, typename Acc>
+__device__ __forceinline__ void load_row(const float *p, Acc (&o)[VEC]) {
+    if constexpr (VEC == 1) {
+        o[0] = *p;
+    } else {
+        static_assert(VEC == 4, "FP32 rows: 1 or 4 per lane");
+        const vf32x4 v = *reinterpret_cast<const vf32x4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+}
+template <int VEC, typename Acc>
+__device__ __forceinline__ void load_row(const double *p, Acc (&o)[VEC]) {
+    if constexpr (VEC == 1) {
+        o[0] = *p;
+    } else {
+        static_assert(VEC == 2, "FP64 rows: 1 or 2 per lane");
+        const vf64x2 v = *reinterpret_cast<const vf64x2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+}
+template <int VEC, typename Acc>
+__device__ __forceinline__ void load_row(const bf16 *p, Acc (&o)[VEC]) {
+    if constexpr (VEC == 1) {
+        o[0] = to_f32(*p);
+    } else if constexpr (VEC == 4) {
+        typedef uint32_t vu32x2 __attribute__((ext_vector_type(2)));
+        const vu32x2 v = *reinterpret_cast<const vu32x2 *>(p);  // 8-byte access
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            o[2 * k] = __uint_as_float(v[k] << 16);
+            o[2 * k + 1] = __uint_as_float(v[k] & 0xffff0000u);
+        }
+    } else {
+        static_assert(VEC == 8, "BF16 rows: 1, 4 or 8 per lane");
+        // element 2k in the low half of word k (little-endian)
+        const vu32x4 v = *reinterpret_cast<const vu32x4 *>(p);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            o[2 * k] = __uint_as_float(v[k] << 16);
+            o[2 * k + 1] = __uint_as_float(v[k] & 0xffff0000u);
+        }
+    }
+}
+
+template <int VEC, typename Acc>
+__device__ __forceinline__ void store_row(float *p, const Acc (&a)[VEC]) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(static_cast<float>(a[0]), p);
+    } else {
+#pragma unroll
+        for (int q = 0; q < VEC; q += 4) {
+            vf32x4 v = {static_cast<float>(a[q]), static_cast<float>(a[q + 1]),
+                        static_cast<float>(a[q + 2]), static_cast<float>(a[q + 3])};
+            __builtin_nontemporal_store(v, reinterpret_cast<vf32x4 *>(p + q));
+        }
+    }
+}
+template <int VEC, typename Acc>
+__device__ __forceinline__ void store_row(double *p, const Acc (&a)[VEC]) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(static_cast<double>(a[0]), p);
+    } else {
+        static_assert(VEC == 2, "FP64 rows: 1 or 2 per lane");
+        vf64x2 v = {static_cast<double>(a[0]), static_cast<double>(a[1])};
+        __builtin_nontemporal_store(v, reinterpret_cast<vf64x2 *>(p));
+    }
+}
+
 // Sum over aligned groups of L lanes (L a power of two <= 64) with xor
 // butterflies; every lane of the group ends with the group total.
 template <int L, typename T>

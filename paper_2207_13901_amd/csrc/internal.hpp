@@ -43,9 +43,13 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
                            const int32_t *pos, const int32_t *crd, const void *vals,
                            const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
 // exact_chunks: every piece of `t` holds at most one leaf chunk
-// ((256 / col_tile) * items merged items), as the merge split is cut here;
-// the leaf then pipelines its staging loads (k_spmm_pipe).
-hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int64_t n, int64_t N,
+// ((256 / lanes) * items merged items, lanes = col_tile / vec), as the merge
+// split is cut here; the leaf then pipelines its staging loads (k_spmm_pipe).
+// vec: 1, or spmm_vec_width(vtype) columns per lane (merge split only; N,
+// the leading dimensions and both dense pointers aligned to it, and
+// col_tile / vec in {8, 16, 32}).
+int spmm_vec_width(int vtype);
+hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                              const int32_t *pos, const int32_t *crd, const void *vals,
                              const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
                              int64_t stride, bool exact_chunks, void *carry, hipStream_t s);

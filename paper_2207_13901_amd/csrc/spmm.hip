@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
 // one iteration earlier still.  After the walk they are stored to the other
 // LDS buffer, so the loads of the next chunk never sit on the critical path.
 // The walk, the cross-group pass and the carries are those of k_spmm_tiles.
-template <int W, int ITEMS, typename V, typename BT, typename OT, typename Acc>
+template <int W, int ITEMS, int VEC, typename V, typename BT, typename OT, typename Acc>
 __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     int64_t n, int64_t N, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
@@ -199,15 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     __shared__ int32_t s_end[2][kChunk];
     __shared__ int32_t s_crd[2][kChunk];
     __shared__ Acc s_val[2][kChunk];
-    __shared__ Acc s_head[G][W];
-    __shared__ Acc s_tail[G][W];
+    __shared__ Acc s_head[G][W * VEC];
+    __shared__ Acc s_tail[G][W * VEC];
     __shared__ int s_done[G];
     __shared__ int s_a0[G];
 
     const int tid = threadIdx.x;
     const int g = tid / W, lane = tid % W;
-    const int64_t col = static_cast<int64_t>(blockIdx.y) * W + lane;
-    const bool colok = col < N;
+    // this lane's columns: col0 .. col0 + VEC - 1 (N is a multiple of VEC)
+    const int64_t col0 = (static_cast<int64_t>(blockIdx.y) * W + lane) * VEC;
+    const bool colok = col0 < N;
     const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
     const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
     auto bound_i = [&](int64_t c) { return static_cast<int64_t>(trow[c < pend ? c : pend]); };
@@ -246,7 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
     fetch(ci, cp, nr, np);
     stash(0, nr, np);
-    Acc open = 0;
+    Acc open[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) open[v] = 0;
     int buf = 0;
     for (int64_t c = p0; c < pend; ++c) {
         __syncthreads();  // buffer `buf` holds chunk c; the previous pass is done
@@ -263,52 +266,63 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         const int a0 = static_cast<int>(merge_search(d0, nr, np, cp, end_at));
         const int a1 = static_cast<int>(merge_search(d1, nr, np, cp, end_at));
         const int b0 = d0 - a0, b1 = d1 - a1;
-        Acc pv[ITEMS];
+        // every gather of the group's positions is issued before any is used
+        Acc pv[ITEMS][VEC];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            pv[k] = 0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) pv[k][v] = 0;
             if (b0 + k < b1 && colok)
-                pv[k] = s_val[buf][b0 + k] *
-                        widen<Acc>(Bd[static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col]);
+                load_row<VEC>(Bd + static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col0, pv[k]);
         }
-        Acc acc = 0;
+        Acc acc[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = 0;
         int a = a0;
         bool first = true;
         auto finish = [&](int r) {
             if (first) {
-                s_head[g][lane] = acc;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) s_head[g][lane * VEC + v] = acc[v];
                 first = false;
             } else if (colok) {
-                store_stream(Out + (ci + r) * ldo + col, narrow<OT>(acc));
+                store_row<VEC>(Out + (ci + r) * ldo + col0, acc);
             }
-            acc = 0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = 0;
         };
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             if (b0 + k < b1) {
                 while (a < a1 && send[a] <= cp + b0 + k) finish(a++);
-                acc += pv[k];
+                const Acc sv = s_val[buf][b0 + k];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += sv * pv[k][v];
             }
         }
         while (a < a1) finish(a++);
-        s_tail[g][lane] = acc;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s_tail[g][lane * VEC + v] = acc[v];
         if (lane == 0) {
             s_done[g] = a1 - a0;
             s_a0[g] = a0;
         }
         __syncthreads();
         if (g == 0) {
-            Acc cc = open;
             for (int gg = 0; gg < G; ++gg) {
                 if (s_done[gg] > 0) {
-                    const Acc v = cc + s_head[gg][lane];
-                    if (colok) store_stream(Out + (ci + s_a0[gg]) * ldo + col, narrow<OT>(v));
-                    cc = s_tail[gg][lane];
+                    Acc out[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        out[v] = open[v] + s_head[gg][lane * VEC + v];
+                        open[v] = s_tail[gg][lane * VEC + v];
+                    }
+                    if (colok) store_row<VEC>(Out + (ci + s_a0[gg]) * ldo + col0, out);
                 } else {
-                    cc += s_tail[gg][lane];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) open[v] += s_tail[gg][lane * VEC + v];
                 }
             }
-            open = cc;
         }
         if (more) stash(buf ^ 1, nnr, nnp);
         ci = ei;
@@ -321,10 +335,18 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         np = nnp;
         buf ^= 1;
     }
-    if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * N + col] = open;
+    if (g == 0 && colok) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) carry[static_cast<int64_t>(blockIdx.x) * N + col0 + v] = open[v];
+    }
 }
 
-// Order LDS accesses of the lanes of one wave (no workgroup barrier).
+
+// Columns per lane of the vector-lane leaf: one 16-byte access for FP32 and
+// FP64 rows, one 8-byte access for BF16 rows (so 32 BF16 columns still take
+// a group of 8 lanes).
+template <typename BT>
+constexpr int kSpmmVec = sizeof(BT) == 2 ? 4 : 16 / static_cast<int>(sizeof(BT));
 
 template <typename V, typename BT, typename OT, typename Acc>
 struct SpmmTypes {
@@ -347,16 +369,16 @@ struct SpmmTypes {
         }
     }
 
-    template <int W, int ITEMS>
+    template <int W, int ITEMS, int VEC>
     static hipError_t tiles_w(int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
                               const void *vals, const void *Bd, int64_t ldb, void *Out,
                               int64_t ldo, const Tiles &t, int64_t stride, bool exact,
                               void *carry, hipStream_t s) {
         const int64_t tiles = ceil_div(t.ntiles, stride);
-        // pieces of exactly one chunk (merge split): the pipelined leaf
-        dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>((N + W - 1) / W));
+        dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(ceil_div(N, W * VEC)));
         if (grid.y == 0) return hipSuccess;
-        auto kern = exact ? k_spmm_pipe<W, ITEMS, V, BT, OT, Acc>
+        // pieces of exactly one chunk (merge split): the pipelined leaf
+        auto kern = exact ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc>
                           : k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>;
         kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
                                      static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out), ldo,
@@ -372,25 +394,38 @@ struct SpmmTypes {
                                            static_cast<OT *>(Out), ldo, s);
     }
 
-    static hipError_t tiles(int W, int items, int64_t n, int64_t N, const int32_t *pos,
-                            const int32_t *crd, const void *vals, const void *Bd, int64_t ldb,
-                            void *Out, int64_t ldo, const Tiles &t, int64_t stride, bool exact,
-                            void *carry, hipStream_t s) {
+    // col_tile columns per lane group; vec > 1 (merge split only): vec
+    // columns per lane, so col_tile / vec lanes per group
+    static hipError_t tiles(int col_tile, int items, int vec, int64_t n, int64_t N,
+                            const int32_t *pos, const int32_t *crd, const void *vals,
+                            const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
+                            int64_t stride, bool exact, void *carry, hipStream_t s) {
+#define SPL_SPMM_ARGS n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s
+        if (vec > 1) {
+            constexpr int VEC = kSpmmVec<BT>;
+            if (vec != VEC || !exact || (items != 8 && items != 16)) return hipErrorInvalidValue;
+            switch (col_tile / VEC) {
+            case 8: return items <= 8 ? tiles_w<8, 8, VEC>(SPL_SPMM_ARGS)
+                                      : tiles_w<8, 16, VEC>(SPL_SPMM_ARGS);
+            case 16: return items <= 8 ? tiles_w<16, 8, VEC>(SPL_SPMM_ARGS)
+                                       : tiles_w<16, 16, VEC>(SPL_SPMM_ARGS);
+            case 32: return items <= 8 ? tiles_w<32, 8, VEC>(SPL_SPMM_ARGS)
+                                       : tiles_w<32, 16, VEC>(SPL_SPMM_ARGS);
+            default: return hipErrorInvalidValue;
+            }
+        }
 #define SPL_SPMM_ITEMS(Wv)                                                                    \
-    if (items <= 8)                                                                           \
-        return tiles_w<Wv, 8>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact,      \
-                              carry, s);                                                      \
-    if (items <= 16)                                                                          \
-        return tiles_w<Wv, 16>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact,     \
-                               carry, s);                                                     \
-    return tiles_w<Wv, 32>(n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s);
-        switch (W) {
+    if (items <= 8) return tiles_w<Wv, 8, 1>(SPL_SPMM_ARGS);                                  \
+    if (items <= 16) return tiles_w<Wv, 16, 1>(SPL_SPMM_ARGS);                                \
+    return tiles_w<Wv, 32, 1>(SPL_SPMM_ARGS);
+        switch (col_tile) {
         case 8: SPL_SPMM_ITEMS(8)
         case 16: SPL_SPMM_ITEMS(16)
         case 64: SPL_SPMM_ITEMS(64)
         default: SPL_SPMM_ITEMS(32)
         }
 #undef SPL_SPMM_ITEMS
+#undef SPL_SPMM_ARGS
     }
 };
 
@@ -417,20 +452,25 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
                                                     ldo, s);
 }
 
-hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int64_t n, int64_t N,
+int spmm_vec_width(int vtype) {
+    return vtype == SPL_F64 ? kSpmmVec<double> : vtype == SPL_F32 ? kSpmmVec<float>
+                                                                  : kSpmmVec<bf16>;
+}
+
+hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                              const int32_t *pos, const int32_t *crd, const void *vals,
                              const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
                              int64_t stride, bool exact_chunks, void *carry, hipStream_t s) {
     if (vtype == SPL_F64)
-        return SpmmTypes<double, double, double, double>::tiles(col_tile, items, n, N, pos, crd,
-                                                                vals, Bd, ldb, Out, ldo, t, stride,
-                                                                exact_chunks, carry, s);
+        return SpmmTypes<double, double, double, double>::tiles(col_tile, items, vec, n, N, pos,
+                                                                crd, vals, Bd, ldb, Out, ldo, t,
+                                                                stride, exact_chunks, carry, s);
     if (vtype == SPL_F32)
-        return SpmmTypes<float, float, float, float>::tiles(col_tile, items, n, N, pos, crd, vals,
-                                                            Bd, ldb, Out, ldo, t, stride,
+        return SpmmTypes<float, float, float, float>::tiles(col_tile, items, vec, n, N, pos, crd,
+                                                            vals, Bd, ldb, Out, ldo, t, stride,
                                                             exact_chunks, carry, s);
-    return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, n, N, pos, crd, vals, Bd,
-                                                      ldb, Out, ldo, t, stride, exact_chunks,
+    return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, vec, n, N, pos, crd, vals,
+                                                      Bd, ldb, Out, ldo, t, stride, exact_chunks,
                                                       carry, s);
 }
 

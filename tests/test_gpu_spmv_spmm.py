@@ -32,6 +32,11 @@ SCHEDULES_SPMM = [
     dict(kind="merge", tile=128, col_tile=32, items_per_lane=16),
     dict(kind="merge", tile=2000, col_tile=64, items_per_lane=32),
     dict(kind="default"),
+    # vector lanes (aligned operands) with 8 items and one chunk per tile,
+    # 16 lanes per group; and the one-column-per-lane leaf forced
+    dict(kind="merge", tile=64, col_tile=32, items_per_lane=8),
+    dict(kind="merge", tile=4096, col_tile=64, items_per_lane=16),
+    dict(kind="merge", tile=512, col_tile=32, items_per_lane=16, variant=1),
 ]
 
 
