@@ -251,7 +251,12 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * accumulation.  Schedules: MERGE (default; equal runs of the merged slice
  * ends and fibers), NNZ (blocks of `tile` positions snapped to fiber starts:
  * the fused non-zero partition), ROW (blocks of `tile` slices); col_tile 16,
- * 32 or 64 rank columns per lane group. */
+ * 32 or 64 rank columns per lane group.  sched->variant: 0 = each lane reads
+ * and writes 4 consecutive rank columns with one vector access when R,
+ * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
+ * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 8
+ * (otherwise one column per lane); 1 = one column per lane.  The workspace query returns the
+ * one-column-per-lane size, enough for both. */
 spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                       const spl_dense *D, spl_dense *A, const spl_schedule *sched,
                       void *workspace, size_t workspace_bytes, spl_stream stream);
@@ -271,9 +276,10 @@ spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
  * (Sec. V-B): A is the vector of B->nnz output values (A.pos = B.pos,
  * A.crd = B.crd).  dtypes (vals, C, D, A): all F64; all F32; or
  * (F32, BF16, BF16, F32) with F32 accumulation.  sched->variant: 0 = vector
- * ALU dot products (default), 1 = matrix cores (BF16 factors only, K a
- * multiple of 32, ld a multiple of 8, 16-byte aligned factors).  Schedules:
- * MERGE (default), NNZ, ROW. */
+ * ALU dot products (default; 16-byte factor accesses when K and both ld are
+ * multiples of 2 F64, 4 F32 or 8 BF16 and the factors are 16-byte aligned),
+ * 1 = matrix cores (BF16 factors only, K a multiple of 32, ld a multiple of
+ * 8, 16-byte aligned factors).  Schedules: MERGE (default), NNZ, ROW. */
 spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                      const spl_dense *D, spl_dense *A, const spl_schedule *sched,
                      void *workspace, size_t workspace_bytes, spl_stream stream);

@@ -30,8 +30,10 @@ SPMM_CANDIDATES: List[Dict] = (
 
 MTTKRP_CANDIDATES: List[Dict] = [
     dict(kind="merge", tile=512, col_tile=32, items_per_lane=16),
-    dict(kind="merge", tile=2048, col_tile=32, items_per_lane=16),
     dict(kind="merge", tile=256, col_tile=32, items_per_lane=8),
+    dict(kind="merge", tile=1024, col_tile=32, items_per_lane=8),
+    dict(kind="merge", tile=4096, col_tile=32, items_per_lane=8),
+    dict(kind="merge", tile=512, col_tile=64, items_per_lane=8),
     dict(kind="nnz", tile=2048, col_tile=32, items_per_lane=16),
     dict(kind="nnz", tile=512, col_tile=32, items_per_lane=8),
 ]

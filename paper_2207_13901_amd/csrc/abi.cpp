@@ -375,10 +375,28 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     const int64_t chunk = (256 / ct) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
+    if (s->variant != 0 && s->variant != 1)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP variant must be 0 (default) or 1 (4-byte lanes)");
+    p.variant = s->variant;
     return SPL_OK;
 }
 
-int64_t mttkrp_chunk(const Plan &p) { return (256 / p.col_tile) * p.items; }
+int64_t mttkrp_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.items; }
+
+// Vector lanes for the MTTKRP leaf (variant 0): 4 rank columns per lane when
+// R, the leading dimensions and the pointers allow it, col_tile is 32 or 64
+// and items_per_lane 8; otherwise one column per lane.
+int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_dense *A) {
+    constexpr int v = 4;
+    if (p.variant != 0 || p.items != 8 || (p.col_tile != 32 && p.col_tile != 64)) return 1;
+    const int64_t R = C->dims[1];
+    const size_t fb = v * dtype_bytes(C->dtype);
+    const bool ok = R % v == 0 && C->ld % v == 0 && D->ld % v == 0 && A->ld % v == 0 &&
+                    reinterpret_cast<uintptr_t>(C->data) % fb == 0 &&
+                    reinterpret_cast<uintptr_t>(D->data) % fb == 0 &&
+                    reinterpret_cast<uintptr_t>(A->data) % 16 == 0;
+    return ok ? v : 1;
+}
 
 // MTTKRP pieces live in (slice, fiber) coordinates.
 Pieces mttkrp_pieces(const spl_sparse *B, const Plan &p) {
@@ -918,6 +936,8 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t I = B->dims[0];
     if (I == 0 || R == 0) return SPL_OK;
+    // the workspace query assumed one column per lane: the larger size
+    p.vec = mttkrp_vec(p, C, D, A);
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, mttkrp_ws(B, R, p), &ws));
     const Pieces q = mttkrp_pieces(B, p);
@@ -930,7 +950,7 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
         SPL_HIP(spl::launch_tile_bounds(p.kind, I, B->pos[1], B->nfibers, q.size, cv.tiles, s),
                 "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
-    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.col_tile, p.items, I, R, B->pos[1], B->crd[1],
+    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.col_tile, p.items, p.vec, I, R, B->pos[1], B->crd[1],
                                      B->pos[2], B->crd[2], B->vals, C->data, C->ld, D->data,
                                      D->ld, static_cast<float *>(A->data), A->ld, cv.tiles,
                                      q.stride, static_cast<float *>(cv.carry), s),
@@ -1019,8 +1039,18 @@ spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     Carved cv = carve(ws, q.count);
     SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
+    // vector lanes for the VALU variant when K, the leading dimensions and
+    // the factor pointers allow 16-byte accesses
+    int vec_lanes = 0;
+    if (variant == 0) {
+        const int v = spl::sddmm_vec_width(C->dtype);
+        if (K % v == 0 && C->ld % v == 0 && D->ld % v == 0 &&
+            reinterpret_cast<uintptr_t>(C->data) % 16 == 0 &&
+            reinterpret_cast<uintptr_t>(D->data) % 16 == 0)
+            vec_lanes = K / v >= 32 ? 32 : K / v >= 16 ? 16 : 8;
+    }
     LeafTimer tm(ctx, SPL_OP_SDDMM, s);
-    SPL_HIP(spl::launch_sddmm(B->vtype, C->dtype, variant, K, B->pos[1], B->crd[1], B->vals,
+    SPL_HIP(spl::launch_sddmm(B->vtype, C->dtype, variant, vec_lanes, K, B->pos[1], B->crd[1], B->vals,
                               C->data, C->ld, D->data, D->ld, A->data, cv.tiles, q.stride, s),
             "SDDMM launch");
     tm.stop();

@@ -19,12 +19,18 @@
 // fibers: t = sum over the fiber's positions, acc += C(j_f,:) * t, and a
 // slice end writes acc (first finished slice and the open one go through
 // the cross-group pass and the tile carry exactly as the SpMM rows do).
+//
+// k_mttkrp_vec: the same leaf with 4 rank columns per lane (one vector access
+// per row), the D products and C rows kept in registers.
 #include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace spl {
 namespace {
+
+// Rank columns per lane of k_mttkrp_vec (16-byte FP32, 8-byte BF16 rows).
+constexpr int kMttkrpVec = 4;
 
 __device__ __forceinline__ int64_t finished_at(const int32_t *pos, int64_t rows, int64_t p) {
     int64_t lo = 0, hi = rows;
@@ -190,6 +196,181 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
     if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * R + col] = open;
 }
 
+// k_mttkrp_vec: k_mttkrp_tiles with VEC rank columns per lane, so that one
+// lane group of W = col_tile / VEC lanes reads a C or D row with W vector
+// accesses.  The D rows of the group's first kPosCap positions stay in
+// registers and the C rows of its fibers go to a per-group LDS slab (each
+// lane reads back only what it wrote, so no barrier): the group walks its
+// positions in order, closing a fiber when the walk passes the fiber's end
+// (acc += C(j_f, :) * t, the C row read from the slab) and finishing every
+// slice that ends before the fiber it is about to close.
+template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
+    int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
+    const int32_t *__restrict__ pos2, const int32_t *__restrict__ crd2,
+    const V *__restrict__ vals, const FT *__restrict__ C, int64_t ldc,
+    const FT *__restrict__ D, int64_t ldd, float *__restrict__ A, int64_t lda,
+    const int32_t *__restrict__ tslice, const int32_t *__restrict__ tfib, int64_t npieces,
+    int64_t stride, Acc *__restrict__ carry) {
+    constexpr int G = kBlock / W;
+    constexpr int kChunk = G * ITEMS;
+    constexpr int kPosCap = ITEMS + ITEMS / 2;  // keeps 3 waves per SIMD
+    __shared__ int32_t s_end[kChunk];
+    __shared__ int32_t s_j[kChunk];
+    __shared__ int32_t s_fp[kChunk + 1];
+    __shared__ Acc s_c[G][ITEMS][W * VEC];  // C rows of each group's fibers
+    __shared__ Acc s_head[G][W * VEC];
+    __shared__ Acc s_tail[G][W * VEC];
+    __shared__ int s_done[G];
+    __shared__ int s_a0[G];
+    __shared__ int64_t s_next[2];
+
+    const int tid = threadIdx.x;
+    const int g = tid / W, lane = tid % W;
+    // this lane's rank columns: col0 .. col0 + VEC - 1 (R is a multiple of VEC)
+    const int64_t col0 = (static_cast<int64_t>(blockIdx.y) * W + lane) * VEC;
+    const bool colok = col0 < R;
+    int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
+    int64_t ci = tslice[piece], cf = tfib[piece];
+    Acc open[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) open[v] = 0;
+
+    while (piece < piece_end) {
+        const int64_t next = chunk_end(pos1, tslice, tfib, piece, ci, cf, kChunk, s_next);
+        const int64_t ei = s_next[0], ef = s_next[1];
+        piece = next;
+        const int nr = static_cast<int>(ei - ci), nf = static_cast<int>(ef - cf);
+        for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
+        for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
+        for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+        __syncthreads();
+
+        const int total = nr + nf;
+        const int d0 = min(g * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        auto end_at = [&](int64_t m) { return s_end[m]; };
+        const int a0 = static_cast<int>(merge_search(d0, nr, nf, cf, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, nf, cf, end_at));
+        const int b0 = d0 - a0, b1 = d1 - a1;
+        const int64_t P0 = s_fp[b0];
+        const int np = static_cast<int>(s_fp[b1] - P0);
+
+        // every C-row and D-row gather of the group before any is used
+        Acc cv[ITEMS][VEC];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) cv[k][v] = 0;
+            if (b0 + k < b1 && colok)
+                load_row<VEC>(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0, cv[k]);
+        }
+        int kq[kPosCap];
+        Acc vq[kPosCap];
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+            kq[q] = 0;
+            vq[q] = 0;
+            if (q < np) {
+                kq[q] = load_stream(crd2 + P0 + q);
+                vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+            }
+        }
+        Acc dv[kPosCap][VEC];
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) dv[q][v] = 0;
+            if (q < np && colok)
+                load_row<VEC>(D + static_cast<int64_t>(kq[q]) * ldd + col0, dv[q]);
+        }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s_c[g][k][lane * VEC + v] = cv[k][v];
+        }
+
+        Acc acc[VEC], t[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = t[v] = 0;
+        int a = a0, f = b0;
+        bool first = true;
+        auto finish = [&](int r) {
+            if (first) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) s_head[g][lane * VEC + v] = acc[v];
+                first = false;
+            } else if (colok) {
+                store_row<VEC>(A + (ci + r) * lda + col0, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = 0;
+        };
+        auto close_fiber = [&]() {
+            while (a < a1 && s_end[a] <= cf + f) finish(a++);
+            const Acc *crow = &s_c[g][f - b0][lane * VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                acc[v] += crow[v] * t[v];
+                t[v] = 0;
+            }
+            ++f;
+        };
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+            if (q < np) {
+                while (P0 + q >= s_fp[f + 1]) close_fiber();
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) t[v] += vq[q] * dv[q][v];
+            }
+        }
+        for (int q = kPosCap; q < np; ++q) {  // positions past the register cap
+            while (P0 + q >= s_fp[f + 1]) close_fiber();
+            if (colok) {
+                Acc d[VEC];
+                load_row<VEC>(D + static_cast<int64_t>(load_stream(crd2 + P0 + q)) * ldd + col0, d);
+                const Acc vv = widen<Acc>(load_stream(vals + P0 + q));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) t[v] += vv * d[v];
+            }
+        }
+        while (f < b1) close_fiber();
+        while (a < a1) finish(a++);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s_tail[g][lane * VEC + v] = acc[v];
+        if (lane == 0) {
+            s_done[g] = a1 - a0;
+            s_a0[g] = a0;
+        }
+        __syncthreads();
+
+        if (g == 0) {
+            for (int gg = 0; gg < G; ++gg) {
+                if (s_done[gg] > 0) {
+                    Acc out[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        out[v] = open[v] + s_head[gg][lane * VEC + v];
+                        open[v] = s_tail[gg][lane * VEC + v];
+                    }
+                    if (colok) store_row<VEC>(A + (ci + s_a0[gg]) * lda + col0, out);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) open[v] += s_tail[gg][lane * VEC + v];
+                }
+            }
+        }
+        ci = ei;
+        cf = ef;
+        __syncthreads();
+    }
+    if (g == 0 && colok) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) carry[static_cast<int64_t>(blockIdx.x) * R + col0 + v] = open[v];
+    }
+}
+
 // Inner product of two value arrays on one pattern: per-workgroup FP64
 // partial sums over a fixed grid-stride assignment, then one workgroup adds
 // the partials in a fixed tree.  Bitwise reproducible for a fixed grid.
@@ -232,22 +413,30 @@ __global__ __launch_bounds__(kBlock) void k_inner_final(int64_t nparts,
 }
 
 template <typename V, typename FT>
-hipError_t mttkrp_types(int W, int items, int64_t I, int64_t R, const int32_t *pos1,
-                        const int32_t *crd1, const int32_t *pos2, const int32_t *crd2,
-                        const void *vals, const void *C, int64_t ldc, const void *D, int64_t ldd,
-                        float *A, int64_t lda, const Tiles &t, int64_t stride, float *carry,
-                        hipStream_t s) {
-    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)), static_cast<unsigned>(ceil_div(R, W)));
+hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
+                        const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
+                        const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
+                        const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
+                        int64_t stride, float *carry, hipStream_t s) {
+    const int lanes = col_tile / vec;
+    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)),
+              static_cast<unsigned>(ceil_div(R, col_tile)));
     auto go = [&](auto kern) {
         kern<<<grid, kBlock, 0, s>>>(I, R, pos1, crd1, pos2, crd2, static_cast<const V *>(vals),
                                      static_cast<const FT *>(C), ldc, static_cast<const FT *>(D),
                                      ldd, A, lda, t.row, t.pos, t.ntiles, stride, carry);
         return hipGetLastError();
     };
-    if (W == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
-                                   : go(k_mttkrp_tiles<16, 16, V, FT, float>);
-    if (W == 64) return items <= 8 ? go(k_mttkrp_tiles<64, 8, V, FT, float>)
-                                   : go(k_mttkrp_tiles<64, 16, V, FT, float>);
+    if (vec > 1) {
+        if (vec != kMttkrpVec || items != 8) return hipErrorInvalidValue;
+        if (lanes == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVec, V, FT, float>);
+        if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float>);
+        return hipErrorInvalidValue;
+    }
+    if (col_tile == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
+                                          : go(k_mttkrp_tiles<16, 16, V, FT, float>);
+    if (col_tile == 64) return items <= 8 ? go(k_mttkrp_tiles<64, 8, V, FT, float>)
+                                          : go(k_mttkrp_tiles<64, 16, V, FT, float>);
     return items <= 8 ? go(k_mttkrp_tiles<32, 8, V, FT, float>)
                       : go(k_mttkrp_tiles<32, 16, V, FT, float>);
 }
@@ -261,16 +450,16 @@ hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, cons
     return hipGetLastError();
 }
 
-hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int64_t I, int64_t R,
+hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int vec, int64_t I, int64_t R,
                                const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
                                const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
                                const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
                                int64_t stride, float *carry, hipStream_t s) {
     if (vtype == SPL_F32)
-        return mttkrp_types<float, float>(col_tile, items, I, R, pos1, crd1, pos2, crd2, vals, C,
-                                          ldc, D, ldd, A, lda, t, stride, carry, s);
-    return mttkrp_types<bf16, bf16>(col_tile, items, I, R, pos1, crd1, pos2, crd2, vals, C, ldc, D,
-                                    ldd, A, lda, t, stride, carry, s);
+        return mttkrp_types<float, float>(col_tile, items, vec, I, R, pos1, crd1, pos2, crd2, vals,
+                                          C, ldc, D, ldd, A, lda, t, stride, carry, s);
+    return mttkrp_types<bf16, bf16>(col_tile, items, vec, I, R, pos1, crd1, pos2, crd2, vals, C,
+                                    ldc, D, ldd, A, lda, t, stride, carry, s);
 }
 
 hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t stride,

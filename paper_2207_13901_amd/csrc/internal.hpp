@@ -60,7 +60,10 @@ hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, in
 // Fiber-aligned non-zero split of a CSF tensor: t.row = slice, t.pos = fiber.
 hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
                                  int64_t nnz, int64_t T, const Tiles &t, hipStream_t s);
-hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int64_t I, int64_t R,
+// vec: 1, or 4 rank columns per lane (R, ldc, ldd, lda multiples of 4, C and D
+// aligned to 4 elements and A to 16 bytes, col_tile / 4 in {8, 16}, items
+// 8).
+hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int vec, int64_t I, int64_t R,
                                const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
                                const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
                                const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
@@ -72,10 +75,15 @@ hipError_t launch_inner(int vtype, int64_t nnz, const void *a, const void *b, do
 
 // ---- sddmm.hip -----------------------------------------------------------
 int64_t sddmm_chunk();
-hipError_t launch_sddmm(int vtype, int ftype, int variant, int64_t K, const int32_t *pos,
-                        const int32_t *crd, const void *bv, const void *C, int64_t ldc,
-                        const void *D, int64_t ldd, void *out, const Tiles &t, int64_t stride,
-                        hipStream_t s);
+// Factor elements per 16-byte access (2 F64, 4 F32, 8 BF16).
+int sddmm_vec_width(int ftype);
+// vec_lanes (variant 0): 0 = one element per lane access; 8, 16 or 32 =
+// lanes per position reading sddmm_vec_width(ftype) elements each (K, ldc,
+// ldd multiples of it, factors 16-byte aligned).
+hipError_t launch_sddmm(int vtype, int ftype, int variant, int vec_lanes, int64_t K,
+                        const int32_t *pos, const int32_t *crd, const void *bv, const void *C,
+                        int64_t ldc, const void *D, int64_t ldd, void *out, const Tiles &t,
+                        int64_t stride, hipStream_t s);
 
 // ---- spadd3.hip ----------------------------------------------------------
 int64_t spadd3_scan_tiles(int64_t n);

@@ -11,6 +11,8 @@
 //    C(i,k) D(j,k) for k = l, l+32, ... (every row access is coalesced), then
 //    a 32-lane butterfly.  FP64, FP32, or BF16 factors with FP32
 //    accumulation.
+//  * k_sddmm_vec: the same with vector lanes (16-byte factor accesses) and
+//    8, 16 or 32 lanes per position, four positions per lane group in flight.
 //  * k_sddmm_mfma: BF16 factors on the matrix cores.  A wave takes 16
 //    positions; v_mfma_f32_16x16x32_bf16 multiplies the 16 gathered C rows
 //    (as A, 16 x 32 per step) by the 16 gathered D rows (as B, 32 x 16) and
@@ -94,6 +96,75 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_valu(
     }
 }
 
+// k_sddmm_valu with vector lanes: a group of L lanes per position, each lane
+// reading VEC consecutive k of the C and D rows with one vector access
+// (K, ldc, ldd multiples of VEC, factors aligned), P positions per group in
+// flight; then an L-lane butterfly.
+template <typename V, typename FT, typename Acc, int CHUNK, int L, int VEC, int P>
+__global__ __launch_bounds__(kBlock) void k_sddmm_vec(
+    int64_t K, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ bv, const FT *__restrict__ C, int64_t ldc, const FT *__restrict__ D,
+    int64_t ldd, V *__restrict__ out, const int32_t *__restrict__ trow,
+    const int32_t *__restrict__ tpos, int64_t npieces, int64_t stride) {
+    __shared__ int32_t s_end[CHUNK];
+    __shared__ int32_t s_row[CHUNK];
+    __shared__ int64_t s_next[2];
+    constexpr int kGroups = kBlock / L;
+    const int grp = threadIdx.x / L, lane = threadIdx.x % L;
+    int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
+    int64_t ci = trow[piece], cp = tpos[piece];
+    while (piece < piece_end) {
+        piece = chunk_end(pos, trow, tpos, piece, ci, cp, CHUNK, s_next);
+        const int64_t ei = s_next[0], ep = s_next[1];
+        const int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
+        chunk_rows(pos, ci, cp, nr, np, s_end, s_row);
+        for (int k = grp; k < np; k += P * kGroups) {
+            const FT *crow[P];
+            const FT *drow[P];
+            bool live[P];
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int ku = k + u * kGroups;
+                live[u] = ku < np;
+                const int kk = live[u] ? ku : k;  // dead slots reread a live position
+                crow[u] = C + static_cast<int64_t>(s_row[kk]) * ldc;
+                drow[u] = D + static_cast<int64_t>(load_stream(crd + cp + kk)) * ldd;
+            }
+            Acc a[P];
+#pragma unroll
+            for (int u = 0; u < P; ++u) a[u] = 0;
+            for (int64_t k0 = static_cast<int64_t>(lane) * VEC; k0 < K; k0 += L * VEC) {
+                Acc cr[P][VEC], dr[P][VEC];
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    load_row<VEC>(crow[u] + k0, cr[u]);
+                    load_row<VEC>(drow[u] + k0, dr[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) a[u] += cr[u][v] * dr[u][v];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < P; ++u) a[u] = group_sum<L>(a[u]);
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    if (live[u]) {
+                        const int64_t p = cp + k + u * kGroups;
+                        store_stream(out + p, static_cast<V>(widen<Acc>(load_stream(bv + p)) * a[u]));
+                    }
+                }
+            }
+        }
+        ci = ei;
+        cp = ep;
+        __syncthreads();
+    }
+}
+
 // BF16 factors, FP32 values and output, K a multiple of 32.
 template <int CHUNK>
 __global__ __launch_bounds__(kBlock) void k_sddmm_mfma(
@@ -150,11 +221,42 @@ constexpr int kSddmmChunk = 512;
 
 int64_t sddmm_chunk() { return kSddmmChunk; }
 
-hipError_t launch_sddmm(int vtype, int ftype, int variant, int64_t K, const int32_t *pos,
-                        const int32_t *crd, const void *bv, const void *C, int64_t ldc,
-                        const void *D, int64_t ldd, void *out, const Tiles &t, int64_t stride,
-                        hipStream_t s) {
+int sddmm_vec_width(int ftype) { return ftype == SPL_F64 ? 2 : ftype == SPL_F32 ? 4 : 8; }
+
+namespace {
+template <typename V, typename FT, int VEC>
+hipError_t sddmm_vec(int lanes, dim3 grid, int64_t K, const int32_t *pos, const int32_t *crd,
+                     const void *bv, const void *C, int64_t ldc, const void *D, int64_t ldd,
+                     void *out, const Tiles &t, int64_t stride, hipStream_t s) {
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, s>>>(K, pos, crd, static_cast<const V *>(bv),
+                                     static_cast<const FT *>(C), ldc, static_cast<const FT *>(D),
+                                     ldd, static_cast<V *>(out), t.row, t.pos, t.ntiles, stride);
+        return hipGetLastError();
+    };
+    using Acc = V;  // FP64 or FP32 accumulation, as the values
+    if (lanes == 32) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 32, VEC, 4>);
+    if (lanes == 16) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 16, VEC, 4>);
+    if (lanes == 8) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 8, VEC, 4>);
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_sddmm(int vtype, int ftype, int variant, int vec_lanes, int64_t K,
+                        const int32_t *pos, const int32_t *crd, const void *bv, const void *C,
+                        int64_t ldc, const void *D, int64_t ldd, void *out, const Tiles &t,
+                        int64_t stride, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
+    if (variant == 0 && vec_lanes > 0) {
+        if (ftype == SPL_BF16)
+            return sddmm_vec<float, bf16, 8>(vec_lanes, grid, K, pos, crd, bv, C, ldc, D, ldd,
+                                             out, t, stride, s);
+        if (vtype == SPL_F64)
+            return sddmm_vec<double, double, 2>(vec_lanes, grid, K, pos, crd, bv, C, ldc, D, ldd,
+                                                out, t, stride, s);
+        return sddmm_vec<float, float, 4>(vec_lanes, grid, K, pos, crd, bv, C, ldc, D, ldd, out,
+                                          t, stride, s);
+    }
     if (ftype == SPL_BF16 && variant == 1) {
         k_sddmm_mfma<kSddmmChunk><<<grid, kBlock, 0, s>>>(
             K, pos, crd, static_cast<const float *>(bv), static_cast<const bf16 *>(C), ldc,

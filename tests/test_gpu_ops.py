@@ -24,7 +24,9 @@ MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=
                     dict(kind="row", tile=3), dict(kind="merge", tile=5000, col_tile=64,
                                                    items_per_lane=16),
                     dict(kind="merge", tile=32, col_tile=32, items_per_lane=16),
-                    dict(kind="merge", tile=1, col_tile=64, items_per_lane=8)]
+                    dict(kind="merge", tile=1, col_tile=64, items_per_lane=8),
+                    dict(kind="nnz", tile=700, col_tile=32, items_per_lane=8),
+                    dict(kind="merge", tile=512, col_tile=32, items_per_lane=8, variant=1)]
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
                    dict(kind="merge", tile=512)]
 
@@ -172,6 +174,17 @@ def test_sddmm_edge_cases():
         ref, S = oracle.sddmm(pos, crd, host64(B.vals), host64(C), host64(D))
         A = spl.sddmm(B, C, D, sched=spl.schedule(variant=variant))
         assert_close(host64(A), ref, S, 1e-5, f"K={K} variant={variant}")
+    # factors whose leading dimension rules out 16-byte accesses (one element
+    # per lane access), and a short FP64 K on the vector-lane path
+    Cw = _t(rs.uniform(-1, 1, (200, 41)), torch.float32)[:, :40]
+    Dw = _t(rs.uniform(-1, 1, (150, 41)), torch.float32)[:, :40]
+    ref, S = oracle.sddmm(pos, crd, host64(B.vals), host64(Cw), host64(Dw))
+    assert_close(host64(spl.sddmm(B, Cw, Dw)), ref, S, 1e-5, "strided factors")
+    B64 = spl.CSR(B.pos, B.crd, B.vals.to(torch.float64), (200, 150))
+    C6 = _t(rs.uniform(-1, 1, (200, 6)), torch.float64)
+    D6 = _t(rs.uniform(-1, 1, (150, 6)), torch.float64)
+    ref, S = oracle.sddmm(pos, crd, host64(B64.vals), host64(C6), host64(D6))
+    assert_close(host64(spl.sddmm(B64, C6, D6)), ref, S, 1e-12, "K=6 FP64")
     with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
         spl.sddmm(B, _t(rs.uniform(-1, 1, (200, 40)), torch.bfloat16),
                   _t(rs.uniform(-1, 1, (150, 40)), torch.bfloat16),
