@@ -225,6 +225,14 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        # plain copy of 1 GiB: 1 GiB read + 1 GiB written per dispatch
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     fixed = {}
     for item in args.sched:
         op, js = item.split("=", 1)
@@ -250,15 +258,6 @@ def main():
     y32, y64 = torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float64, device=dev)
     A32 = torch.empty(n, N_COLS, dtype=torch.float32, device=dev)
     A64 = torch.empty(n, N_COLS, dtype=torch.float64, device=dev)
-
-    if args.calibrate:
-        # plain copy of 1 GiB: 1 GiB read + 1 GiB written per dispatch
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     # -- exhaustive schedule search (untimed) ---------------------------------
     reps = 3 if args.profile else 5
