@@ -53,8 +53,10 @@ def sources_digest(paths):
 
 def counted_traffic(schedule):
     """Counter-measured HBM bytes per SpMM leaf launch, or None when the
-    record is missing, was taken on other kernel sources or on another
-    schedule."""
+    record is missing, was taken on other kernel sources or with another
+    leaf kernel (kind, col_tile, items_per_lane, variant; the merge tile only
+    sets how many chunks a workgroup walks, so it changes the carries, a few
+    KB, not the leaf's traffic)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -65,7 +67,9 @@ def counted_traffic(schedule):
     try:
         if rec.get("sources_digest") != sources_digest(SPMM_SOURCES):
             return None
-        if json.loads(rec["schedule"]) != schedule:
+        keys = ("kind", "col_tile", "items_per_lane", "variant")
+        rs = json.loads(rec["schedule"])
+        if any(rs.get(k, 0) != schedule.get(k, 0) for k in keys):
             return None
         return int(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -73,13 +77,15 @@ def counted_traffic(schedule):
 
 
 def spmm_kernel_name(sched):
-    """Leaf kernel a SpMM schedule dispatches (FP32, col_tile 32)."""
+    """Leaf kernel a SpMM schedule dispatches for the FP32 N=32 operands."""
     kind = sched.get("kind", "merge")
     if kind == "row":
         return "k_spmm_row"
     if kind == "nnz":
         return "k_spmm_tiles"
-    return "k_spmm_wave" if sched.get("col_tile", 32) >= 32 else "k_spmm_pipe"
+    vec = (sched.get("variant", 0) == 0 and sched.get("items_per_lane", 16) <= 16 and
+           sched.get("col_tile", 32) >= 32)
+    return "k_spmm_pipe, 4 columns per lane" if vec else "k_spmm_pipe"
 
 
 def algorithmic_bytes(n, m, nnz, N, vbytes, dbytes, obytes):

@@ -809,7 +809,8 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, n, B->pos[1], B->crd[1], B->vals, c->data,
-                                   a->data, cv.tiles, q.stride, static_cast<double *>(cv.carry), s),
+                                   a->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
+                                   static_cast<double *>(cv.carry), s),
             "SpMV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
@@ -903,7 +904,8 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPTTV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, F, v.pos[1], v.crd[1], B->vals, c->data,
-                                   A->data, cv.tiles, q.stride, static_cast<double *>(cv.carry), s),
+                                   A->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
+                                   static_cast<double *>(cv.carry), s),
             "SpTTV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, F, cv.tiles, q.stride,

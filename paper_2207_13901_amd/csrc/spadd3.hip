@@ -11,9 +11,11 @@
 // summed in operand order B, C, D over the operands present (a cancellation
 // to zero keeps its coordinate).  The scan is three passes: per-workgroup
 // totals, one workgroup scanning the totals, per-workgroup rescan.  The
-// numeric phase stages the output in LDS so that its stores are coalesced:
-// one lane per row storing straight to HBM keeps far more partly written
-// lines open than the L2 holds.
+// symbolic phase copies the workgroup's input coordinates to LDS with
+// coalesced loads first, and the numeric phase stages the output in LDS so
+// that its stores are coalesced: one lane per row reading or storing
+// straight to HBM keeps far more partly used lines open than the caches
+// hold.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -27,6 +29,14 @@ struct Csr3 {
     const int32_t *bp, *bc, *cp, *cc, *dp, *dc;
 };
 
+// Where a workgroup reads the three operands' coordinates from: the
+// operands themselves, or an LDS copy of the workgroup's ranges (element q
+// of operand X at x[q - ox]).
+struct Crd3 {
+    const int32_t *b, *c, *d;
+    int32_t ob, oc, od;
+};
+
 // Three-way merge of one row's sorted coordinate lists, resumable: next()
 // yields the union's coordinates in increasing order; with values, the sum
 // over the operands present in operand order B, C, D.
@@ -34,55 +44,78 @@ struct Merge3 {
     static constexpr int32_t kInf = 0x7fffffff;
     int32_t a, ae, b, be, d, de, xa, xb, xd;
 
-    __device__ __forceinline__ Merge3(const Csr3 &m, int64_t i) {
+    __device__ __forceinline__ Merge3(const Csr3 &m, const Crd3 &x, int64_t i) {
         a = m.bp[i];
         ae = m.bp[i + 1];
         b = m.cp[i];
         be = m.cp[i + 1];
         d = m.dp[i];
         de = m.dp[i + 1];
-        xa = a < ae ? m.bc[a] : kInf;
-        xb = b < be ? m.cc[b] : kInf;
-        xd = d < de ? m.dc[d] : kInf;
+        xa = a < ae ? x.b[a - x.ob] : kInf;
+        xb = b < be ? x.c[b - x.oc] : kInf;
+        xd = d < de ? x.d[d - x.od] : kInf;
     }
 
     __device__ __forceinline__ bool done() const { return min(xa, min(xb, xd)) == kInf; }
 
     // Advance past the smallest remaining coordinate c; returns c.
     template <bool kValues, typename V>
-    __device__ __forceinline__ int32_t next(const Csr3 &m, const V *bv, const V *cv, const V *dv,
+    __device__ __forceinline__ int32_t next(const Crd3 &x, const V *bv, const V *cv, const V *dv,
                                             V &sum) {
         const int32_t c = min(xa, min(xb, xd));
         V s = 0;
         if (xa == c) {
             if (kValues) s = bv[a];
             ++a;
-            xa = a < ae ? m.bc[a] : kInf;
+            xa = a < ae ? x.b[a - x.ob] : kInf;
         }
         if (xb == c) {
             if (kValues) s = s + cv[b];
             ++b;
-            xb = b < be ? m.cc[b] : kInf;
+            xb = b < be ? x.c[b - x.oc] : kInf;
         }
         if (xd == c) {
             if (kValues) s = s + dv[d];
             ++d;
-            xd = d < de ? m.dc[d] : kInf;
+            xd = d < de ? x.d[d - x.od] : kInf;
         }
         sum = s;
         return c;
     }
 };
 
+// Coordinates of the workgroup's rows [r0, r1) per operand staged in LDS.
+// One lane per row reading its row straight from HBM keeps a few lines per
+// lane open at once, more than the L1 and L2 hold, so lines are fetched
+// several times; the coalesced copy reads each once.  When an operand's run
+// exceeds kStageCap the workgroup reads the operands directly.
+constexpr int kStageCap = 2560;
+
+__device__ __forceinline__ Crd3 stage_crd(const Csr3 &m, int64_t r0, int64_t r1,
+                                          int32_t (*s_x)[kStageCap]) {
+    const int32_t b0 = m.bp[r0], c0 = m.cp[r0], d0 = m.dp[r0];
+    const int32_t nb = m.bp[r1] - b0, nc = m.cp[r1] - c0, nd = m.dp[r1] - d0;
+    if (nb > kStageCap || nc > kStageCap || nd > kStageCap) return Crd3{m.bc, m.cc, m.dc, 0, 0, 0};
+    for (int k = threadIdx.x; k < nb; k += kBlock) s_x[0][k] = m.bc[b0 + k];
+    for (int k = threadIdx.x; k < nc; k += kBlock) s_x[1][k] = m.cc[c0 + k];
+    for (int k = threadIdx.x; k < nd; k += kBlock) s_x[2][k] = m.dc[d0 + k];
+    __syncthreads();
+    return Crd3{s_x[0], s_x[1], s_x[2], b0, c0, d0};
+}
+
 __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int32_t *apos) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    __shared__ int32_t s_x[3][kStageCap];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int64_t i = r0 + threadIdx.x;
+    const Crd3 x = stage_crd(m, r0, r1, s_x);
     if (i == 0) apos[0] = 0;
     if (i >= n) return;
-    Merge3 mg(m, i);
+    Merge3 mg(m, x, i);
     int32_t k = 0;
     float unused;
     while (!mg.done()) {
-        mg.next<false, float>(m, nullptr, nullptr, nullptr, unused);
+        mg.next<false, float>(x, nullptr, nullptr, nullptr, unused);
         ++k;
     }
     apos[i + 1] = k;
@@ -94,7 +127,9 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
 // it stopped, emitting into LDS the entries whose output index falls in the
 // window, and the workgroup then writes the window with coalesced stores.
 // Each row is merged once whatever its length; only one row's lane works
-// in the windows a long row fills alone.
+// in the windows a long row fills alone.  The inputs are read directly:
+// staging them as well would halve the workgroups per CU, which costs more
+// than the repeated line fetches it saves.
 constexpr int kFillCap = 4096;
 
 template <typename V>
@@ -107,17 +142,18 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
     const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
     const int64_t i = r0 + threadIdx.x;
+    const Crd3 x{m.bc, m.cc, m.dc, 0, 0, 0};
     const int64_t base = apos[r0];
     const int64_t total = apos[r1] - base;
     const bool mine = i < n;
     int64_t k = mine ? apos[i] - base : 0;
     const int64_t hi = mine ? apos[i + 1] - base : 0;
-    Merge3 mg(m, mine ? i : r0);
+    Merge3 mg(m, x, mine ? i : r0);
     for (int64_t w = 0; w < total; w += kFillCap) {
         const int64_t we = w + kFillCap < total ? w + kFillCap : total;
         for (; k < hi && k < we; ++k) {
             V sum;
-            const int32_t c = mg.next<true, V>(m, bv, cv, dv, sum);
+            const int32_t c = mg.next<true, V>(x, bv, cv, dv, sum);
             s_crd[k - w] = c;
             s_val[k - w] = sum;
         }

@@ -25,6 +25,9 @@
 //    non-zero algorithm of Sec. II-D requires.  No floating-point atomics,
 //    so results are bitwise reproducible.
 //
+//  * k_spmv_pipe: the merge-split form of k_spmv_tiles with its staging
+//    software-pipelined two chunks deep.
+//
 // Accumulation is in double for both double and float data (a float output
 // is rounded once from the double sum, then once more if a carry lands on it).
 #include "carry.hpp"
@@ -234,6 +237,134 @@ __global__ __launch_bounds__(kBlock) void k_spmv_tiles(
     if (tid == 0) carry[blockIdx.x] = open;
 }
 
+// Merge-split pieces are exactly one chunk each, so the chunk bounds are
+// known ahead and the staging is software-pipelined two chunks deep: while
+// a workgroup walks chunk c (LDS buffer c % 2), the x gathers of chunk c + 1
+// and the crd/vals/row-end loads of chunk c + 2 are in flight in registers;
+// after the walk, chunk c + 1's products go to the other buffer, its gathers
+// having had a whole iteration to land.  The walk, the segmented scan and
+// the carry are those of k_spmv_tiles.
+template <typename V, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_spmv_pipe(
+    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
+    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
+    int64_t stride, double *__restrict__ carry) {
+    constexpr int kChunk = kBlock * ITEMS;
+    __shared__ double s_prod[2][kChunk];
+    __shared__ int32_t s_end[2][kChunk];
+    __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
+    __shared__ double s_last_val[kBlock / kWave];
+    __shared__ double s_open;
+
+    const int tid = threadIdx.x;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
+    auto bound_i = [&](int64_t c) { return static_cast<int64_t>(trow[c < pend ? c : pend]); };
+    auto bound_p = [&](int64_t c) { return static_cast<int64_t>(tpos[c < pend ? c : pend]); };
+
+    // stage 2: loads of a chunk; stage 1: its x gathers
+    int e2[ITEMS], k2[ITEMS], e1[ITEMS];
+    V v2[ITEMS], v1[ITEMS], x1[ITEMS];
+    auto load = [&](int64_t bi, int64_t bp, int nr, int np) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < nr) e2[j] = pos[bi + 1 + k];
+            if (k < np) {
+                k2[j] = load_stream(crd + bp + k);
+                v2[j] = load_stream(vals + bp + k);
+            }
+        }
+    };
+    auto gather = [&](int np) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            e1[j] = e2[j];
+            v1[j] = v2[j];
+            if (tid + j * kBlock < np) x1[j] = x[k2[j]];
+        }
+    };
+    auto stash = [&](int buf, int nr, int np) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < nr) s_end[buf][k] = e1[j];
+            if (k < np) s_prod[buf][k] = to_f64(v1[j]) * to_f64(x1[j]);
+        }
+    };
+
+    // bounds of chunks c .. c + 3 as (b*0 .. b*3)
+    int64_t bi0 = bound_i(p0), bp0 = bound_p(p0);
+    int64_t bi1 = bound_i(p0 + 1), bp1 = bound_p(p0 + 1);
+    int64_t bi2 = bound_i(p0 + 2), bp2 = bound_p(p0 + 2);
+    int64_t bi3 = bound_i(p0 + 3), bp3 = bound_p(p0 + 3);
+    // prologue: chunk p0 into buffer 0, chunk p0 + 1 gathering, p0 + 2 loading
+    load(bi0, bp0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0));
+    gather(static_cast<int>(bp1 - bp0));
+    stash(0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0));
+    load(bi1, bp1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1));
+    gather(static_cast<int>(bp2 - bp1));
+    load(bi2, bp2, static_cast<int>(bi3 - bi2), static_cast<int>(bp3 - bp2));
+
+    double open = 0.0;  // partial sum of the row open at the chunk start
+    int buf = 0;
+    for (int64_t c = p0; c < pend; ++c) {
+        const int64_t bi4 = bound_i(c + 4), bp4 = bound_p(c + 4);
+        __syncthreads();  // buffer `buf` holds chunk c
+        const int nr = static_cast<int>(bi1 - bi0), np = static_cast<int>(bp1 - bp0);
+        const int total = nr + np;
+        const int d0 = min(tid * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        const int32_t *send = s_end[buf];
+        const double *sprod = s_prod[buf];
+        // finished rows' sums go to the idle product buffer until written out
+        double *s_out = s_prod[buf ^ 1];
+        int a = static_cast<int>(merge_search(d0, nr, np, bp0, [&](int64_t m) { return send[m]; }));
+        int b = d0 - a;
+        double acc = tid == 0 ? open : 0.0;
+#pragma unroll
+        for (int s = 0; s < ITEMS; ++s) {
+            if (d0 + s < d1) {
+                if (a < nr && send[a] <= bp0 + b) {
+                    s_out[a] = acc;  // row a finished by this lane
+                    acc = 0.0;
+                    ++a;
+                } else {
+                    acc += sprod[b];
+                    ++b;
+                }
+            }
+        }
+        double v = block_segmented_scan(acc, a, s_first_key, s_last_key, s_last_val);
+        int next_key = __shfl_down(a, 1);
+        const int lane = tid & (kWave - 1), wave = tid / kWave;
+        if (lane == kWave - 1) next_key = wave + 1 < kBlock / kWave ? s_first_key[wave + 1] : -1;
+        if (next_key != a) {
+            if (a < nr)
+                s_out[a] += v;
+            else
+                s_open = v;
+        }
+        __syncthreads();
+        for (int k = tid; k < nr; k += kBlock) store_stream(y + bi0 + k, static_cast<V>(s_out[k]));
+        open = s_open;
+        __syncthreads();  // the row sums are out of the buffer the stash refills
+        // chunk c + 1 to the other buffer; c + 2 starts gathering, c + 3 loading
+        if (c + 1 < pend) {
+            stash(buf ^ 1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1));
+            gather(static_cast<int>(bp3 - bp2));
+            if (c + 3 < pend) load(bi3, bp3, static_cast<int>(bi4 - bi3), static_cast<int>(bp4 - bp3));
+        }
+        bi0 = bi1; bp0 = bp1;
+        bi1 = bi2; bp1 = bp2;
+        bi2 = bi3; bp2 = bp3;
+        bi3 = bi4; bp3 = bp4;
+        buf ^= 1;
+    }
+    if (tid == 0) carry[blockIdx.x] = open;
+}
+
 template <typename V>
 hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int32_t *crd,
                              const V *vals, const V *x, V *y, hipStream_t s) {
@@ -257,8 +388,17 @@ hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int
 template <typename V>
 hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const int32_t *crd,
                                const V *vals, const V *x, V *y, const Tiles &t, int64_t stride,
-                               double *carry, hipStream_t s) {
+                               bool exact, double *carry, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
+    if (exact) {
+        if (items <= 4)
+            k_spmv_pipe<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        else
+            k_spmv_pipe<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        return hipGetLastError();
+    }
     if (items <= 4)
         k_spmv_tiles<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
                                                     t.ntiles, stride, carry);
@@ -296,14 +436,16 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
 
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
-                             const Tiles &t, int64_t stride, double *carry, hipStream_t s) {
+                             const Tiles &t, int64_t stride, bool exact_chunks, double *carry,
+                             hipStream_t s) {
     if (dtype == SPL_F64)
         return spmv_tiles_dispatch<double>(items, n, pos, crd, static_cast<const double *>(vals),
                                            static_cast<const double *>(x),
-                                           static_cast<double *>(y), t, stride, carry, s);
+                                           static_cast<double *>(y), t, stride, exact_chunks,
+                                           carry, s);
     return spmv_tiles_dispatch<float>(items, n, pos, crd, static_cast<const float *>(vals),
                                       static_cast<const float *>(x), static_cast<float *>(y), t,
-                                      stride, carry, s);
+                                      stride, exact_chunks, carry, s);
 }
 
 }  // namespace spl
