@@ -369,10 +369,12 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     if (ct != 16 && ct != 32 && ct != 64)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP col_tile must be 16, 32 or 64");
     p.col_tile = ct;
-    p.items = s->items_per_lane ? s->items_per_lane : 16;
+    p.items = s->items_per_lane ? s->items_per_lane : 8;
     if (p.items != 8 && p.items != 16)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 8 or 16");
-    const int64_t chunk = (256 / ct) * p.items;
+    // four leaf chunks per workgroup by default (vector-lane chunks when
+    // the operands allow them: col_tile 32 or 64 with 8 items)
+    const int64_t chunk = (256 / (p.items == 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
     if (s->variant != 0 && s->variant != 1)

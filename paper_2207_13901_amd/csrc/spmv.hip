@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pipe(
     const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
     int64_t stride, double *__restrict__ carry) {
     constexpr int kChunk = kBlock * ITEMS;
-    __shared__ double s_prod[2][kChunk];
+    __shared__ double s_prod[2][kChunk + 1];  // + a spare slot for the walk
     __shared__ int32_t s_end[2][kChunk];
     __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
     __shared__ double s_last_val[kBlock / kWave];
@@ -323,18 +323,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pipe(
         int a = static_cast<int>(merge_search(d0, nr, np, bp0, [&](int64_t m) { return send[m]; }));
         int b = d0 - a;
         double acc = tid == 0 ? open : 0.0;
+        // Branch-free walk (selects instead of divergent branches, whose
+        // exec-mask bookkeeping dominated the instruction count for short
+        // rows): each step reads the next row end and product at clamped
+        // indices and either finishes row a (its sum to s_out[a], else to the
+        // spare slot) or adds position b.
 #pragma unroll
         for (int s = 0; s < ITEMS; ++s) {
-            if (d0 + s < d1) {
-                if (a < nr && send[a] <= bp0 + b) {
-                    s_out[a] = acc;  // row a finished by this lane
-                    acc = 0.0;
-                    ++a;
-                } else {
-                    acc += sprod[b];
-                    ++b;
-                }
-            }
+            const bool in = d0 + s < d1;
+            const int32_t e = send[a < kChunk ? a : kChunk - 1];
+            const double pv = sprod[b < kChunk ? b : kChunk - 1];
+            const bool fin = in && a < nr && e <= bp0 + b;
+            const bool add = in && !fin;
+            s_out[fin ? a : kChunk] = acc;
+            acc = fin ? 0.0 : (add ? acc + pv : acc);
+            a += fin ? 1 : 0;
+            b += add ? 1 : 0;
         }
         double v = block_segmented_scan(acc, a, s_first_key, s_last_key, s_last_val);
         int next_key = __shfl_down(a, 1);

@@ -18,7 +18,8 @@ from workloads import configs
 pytestmark = pytest.mark.gpu
 
 TTV_SCHEDULES = [dict(kind="default"), dict(kind="row", lanes_per_row=2),
-                 dict(kind="nnz", tile=500), dict(kind="merge", tile=4096, items_per_lane=4)]
+                 dict(kind="nnz", tile=500), dict(kind="merge", tile=4096, items_per_lane=4),
+                 dict(kind="merge", tile=20000, items_per_lane=8)]
 MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=32, items_per_lane=8),
                     dict(kind="nnz", tile=300), dict(kind="nnz", tile=4096, col_tile=16),
                     dict(kind="row", tile=3), dict(kind="merge", tile=5000, col_tile=64,
@@ -26,6 +27,7 @@ MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=
                     dict(kind="merge", tile=32, col_tile=32, items_per_lane=16),
                     dict(kind="merge", tile=1, col_tile=64, items_per_lane=8),
                     dict(kind="nnz", tile=700, col_tile=32, items_per_lane=8),
+                    dict(kind="merge", tile=2048, col_tile=32, items_per_lane=8),
                     dict(kind="merge", tile=512, col_tile=32, items_per_lane=8, variant=1)]
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
                    dict(kind="merge", tile=512)]

@@ -24,6 +24,8 @@ SCHEDULES_SPMV = [
     dict(kind="nnz", tile=5000, items_per_lane=8),
     dict(kind="merge", tile=1024, items_per_lane=4), dict(kind="merge", tile=2048),
     dict(kind="merge", tile=777), dict(kind="default"),
+    # several chunks per workgroup: the pipelined leaf's steady state
+    dict(kind="merge", tile=8192, items_per_lane=4), dict(kind="merge", tile=6000, items_per_lane=8),
 ]
 SCHEDULES_SPMM = [
     dict(kind="row", col_tile=32), dict(kind="row", col_tile=8),
