@@ -21,7 +21,7 @@
 // the cross-group pass and the tile carry exactly as the SpMM rows do).
 //
 // k_mttkrp_vec: the same leaf with 4 rank columns per lane (one vector access
-// per row).
+// per row), the D products and C rows kept in registers.
 #include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
@@ -196,162 +196,18 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
     if (g == 0 && colok) carry[static_cast<int64_t>(blockIdx.x) * R + col] = open;
 }
 
-// Vector-lane MTTKRP: k_mttkrp_tiles with VEC rank columns per lane, so that
-// one lane group of W = col_tile / VEC lanes reads a C or D row with W vector
+// k_mttkrp_vec: k_mttkrp_tiles with VEC rank columns per lane, so that one
+// lane group of W = col_tile / VEC lanes reads a C or D row with W vector
 // accesses.  The D rows of the group's first kPosCap positions stay in
 // registers and the C rows of its fibers go to a per-group LDS slab (each
 // lane reads back only what it wrote, so no barrier): the group walks its
 // positions in order, closing a fiber when the walk passes the fiber's end
 // (acc += C(j_f, :) * t, the C row read from the slab) and finishing every
-// slice that ends before the fiber it is about to close.  (A select chain
-// over registers for the C rows is turned by the compiler into an indexed
-// private array in scratch memory.)
-template <int W, int ITEMS, int VEC, typename Acc>
-struct MttkrpVecShared {
-    static constexpr int G = kBlock / W;
-    Acc c[G][ITEMS][W * VEC];  // C rows of each group's fibers
-    Acc head[G][W * VEC];
-    Acc tail[G][W * VEC];
-    int done[G];
-    int a0[G];
-};
-
-// One chunk [(ci, cf), (ci + nr, cf + nf)) whose slice ends, fiber
-// coordinates and fiber starts are in LDS (s_end, s_j, s_fp); `open` (group
-// 0) carries the partial of slice ci in and the partial of the slice left
-// open out.  Contains one workgroup barrier; the caller separates chunks by
-// another.
-template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
-__device__ __forceinline__ void mttkrp_vec_chunk(
-    int64_t R, int64_t col0, const int32_t *__restrict__ crd2, const V *__restrict__ vals,
-    const FT *__restrict__ C, int64_t ldc, const FT *__restrict__ D, int64_t ldd,
-    float *__restrict__ A, int64_t lda, int64_t ci, int64_t cf, int nr, int nf,
-    const int32_t *s_end, const int32_t *s_j, const int32_t *s_fp,
-    MttkrpVecShared<W, ITEMS, VEC, Acc> &sh, Acc (&open)[VEC]) {
-    constexpr int G = kBlock / W;
-    constexpr int kPosCap = ITEMS + ITEMS / 2;  // keeps 3 waves per SIMD
-    const int g = threadIdx.x / W, lane = threadIdx.x % W;
-    const bool colok = col0 < R;
-    const int total = nr + nf;
-    const int d0 = min(g * ITEMS, total);
-    const int d1 = min(d0 + ITEMS, total);
-    auto end_at = [&](int64_t m) { return s_end[m]; };
-    const int a0 = static_cast<int>(merge_search(d0, nr, nf, cf, end_at));
-    const int a1 = static_cast<int>(merge_search(d1, nr, nf, cf, end_at));
-    const int b0 = d0 - a0, b1 = d1 - a1;
-    const int64_t P0 = s_fp[b0];
-    const int np = static_cast<int>(s_fp[b1] - P0);
-
-    // every C-row and D-row gather of the group before any is used
-    Acc cv[ITEMS][VEC];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) cv[k][v] = 0;
-        if (b0 + k < b1 && colok)
-            load_row<VEC>(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0, cv[k]);
-    }
-    int kq[kPosCap];
-    Acc vq[kPosCap];
-#pragma unroll
-    for (int q = 0; q < kPosCap; ++q) {
-        kq[q] = 0;
-        vq[q] = 0;
-        if (q < np) {
-            kq[q] = load_stream(crd2 + P0 + q);
-            vq[q] = widen<Acc>(load_stream(vals + P0 + q));
-        }
-    }
-    Acc dv[kPosCap][VEC];
-#pragma unroll
-    for (int q = 0; q < kPosCap; ++q) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) dv[q][v] = 0;
-        if (q < np && colok) load_row<VEC>(D + static_cast<int64_t>(kq[q]) * ldd + col0, dv[q]);
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) sh.c[g][k][lane * VEC + v] = cv[k][v];
-    }
-
-    Acc acc[VEC], t[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] = t[v] = 0;
-    int a = a0, f = b0;
-    bool first = true;
-    auto finish = [&](int r) {
-        if (first) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) sh.head[g][lane * VEC + v] = acc[v];
-            first = false;
-        } else if (colok) {
-            store_row<VEC>(A + (ci + r) * lda + col0, acc);
-        }
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = 0;
-    };
-    auto close_fiber = [&]() {
-        while (a < a1 && s_end[a] <= cf + f) finish(a++);
-        const Acc *crow = &sh.c[g][f - b0][lane * VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            acc[v] += crow[v] * t[v];
-            t[v] = 0;
-        }
-        ++f;
-    };
-#pragma unroll
-    for (int q = 0; q < kPosCap; ++q) {
-        if (q < np) {
-            while (P0 + q >= s_fp[f + 1]) close_fiber();
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) t[v] += vq[q] * dv[q][v];
-        }
-    }
-    for (int q = kPosCap; q < np; ++q) {  // positions past the register cap
-        while (P0 + q >= s_fp[f + 1]) close_fiber();
-        if (colok) {
-            Acc d[VEC];
-            load_row<VEC>(D + static_cast<int64_t>(load_stream(crd2 + P0 + q)) * ldd + col0, d);
-            const Acc vv = widen<Acc>(load_stream(vals + P0 + q));
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) t[v] += vv * d[v];
-        }
-    }
-    while (f < b1) close_fiber();
-    while (a < a1) finish(a++);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) sh.tail[g][lane * VEC + v] = acc[v];
-    if (lane == 0) {
-        sh.done[g] = a1 - a0;
-        sh.a0[g] = a0;
-    }
-    __syncthreads();
-
-    if (g == 0) {
-        for (int gg = 0; gg < G; ++gg) {
-            if (sh.done[gg] > 0) {
-                Acc out[VEC];
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    out[v] = open[v] + sh.head[gg][lane * VEC + v];
-                    open[v] = sh.tail[gg][lane * VEC + v];
-                }
-                if (colok) store_row<VEC>(A + (ci + sh.a0[gg]) * lda + col0, out);
-            } else {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) open[v] += sh.tail[gg][lane * VEC + v];
-            }
-        }
-    }
-}
-
-// Any pieces (chunk ends found by a merge-path search when a piece holds
-// more than one chunk).  A software-pipelined form for merge-split pieces,
-// prefetching the next chunk's slice ends, fibers and fiber starts behind
-// the current walk, measured slower (6.3 ms against 5.7 ms on the 1e8-nnz
-// tensor), so there is none.
+// slice that ends before the fiber it is about to close.  (Two variants
+// measured slower on the 1e8-nonzero tensor and are not kept: prefetching
+// the next chunk's slice ends, fibers and fiber starts behind the current
+// walk, 6.3 ms against 5.7 ms, and the same walk factored into a device
+// function with the LDS slabs in one struct, 6.4 ms.)
 template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
@@ -362,16 +218,22 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t stride, Acc *__restrict__ carry) {
     constexpr int G = kBlock / W;
     constexpr int kChunk = G * ITEMS;
+    constexpr int kPosCap = ITEMS + ITEMS / 2;  // keeps 3 waves per SIMD
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];
-    __shared__ MttkrpVecShared<W, ITEMS, VEC, Acc> sh;
+    __shared__ Acc s_c[G][ITEMS][W * VEC];  // C rows of each group's fibers
+    __shared__ Acc s_head[G][W * VEC];
+    __shared__ Acc s_tail[G][W * VEC];
+    __shared__ int s_done[G];
+    __shared__ int s_a0[G];
     __shared__ int64_t s_next[2];
 
     const int tid = threadIdx.x;
     const int g = tid / W, lane = tid % W;
     // this lane's rank columns: col0 .. col0 + VEC - 1 (R is a multiple of VEC)
     const int64_t col0 = (static_cast<int64_t>(blockIdx.y) * W + lane) * VEC;
+    const bool colok = col0 < R;
     int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
     const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
     int64_t ci = tslice[piece], cf = tfib[piece];
@@ -388,13 +250,126 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
         for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
         __syncthreads();
-        mttkrp_vec_chunk<W, ITEMS, VEC, V, FT, Acc>(R, col0, crd2, vals, C, ldc, D, ldd, A, lda,
-                                                    ci, cf, nr, nf, s_end, s_j, s_fp, sh, open);
+
+        const int total = nr + nf;
+        const int d0 = min(g * ITEMS, total);
+        const int d1 = min(d0 + ITEMS, total);
+        auto end_at = [&](int64_t m) { return s_end[m]; };
+        const int a0 = static_cast<int>(merge_search(d0, nr, nf, cf, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, nf, cf, end_at));
+        const int b0 = d0 - a0, b1 = d1 - a1;
+        const int64_t P0 = s_fp[b0];
+        const int np = static_cast<int>(s_fp[b1] - P0);
+
+        // every C-row and D-row gather of the group before any is used
+        Acc cv[ITEMS][VEC];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) cv[k][v] = 0;
+            if (b0 + k < b1 && colok)
+                load_row<VEC>(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0, cv[k]);
+        }
+        int kq[kPosCap];
+        Acc vq[kPosCap];
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+            kq[q] = 0;
+            vq[q] = 0;
+            if (q < np) {
+                kq[q] = load_stream(crd2 + P0 + q);
+                vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+            }
+        }
+        Acc dv[kPosCap][VEC];
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) dv[q][v] = 0;
+            if (q < np && colok)
+                load_row<VEC>(D + static_cast<int64_t>(kq[q]) * ldd + col0, dv[q]);
+        }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s_c[g][k][lane * VEC + v] = cv[k][v];
+        }
+
+        Acc acc[VEC], t[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = t[v] = 0;
+        int a = a0, f = b0;
+        bool first = true;
+        auto finish = [&](int r) {
+            if (first) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) s_head[g][lane * VEC + v] = acc[v];
+                first = false;
+            } else if (colok) {
+                store_row<VEC>(A + (ci + r) * lda + col0, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = 0;
+        };
+        auto close_fiber = [&]() {
+            while (a < a1 && s_end[a] <= cf + f) finish(a++);
+            const Acc *crow = &s_c[g][f - b0][lane * VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                acc[v] += crow[v] * t[v];
+                t[v] = 0;
+            }
+            ++f;
+        };
+#pragma unroll
+        for (int q = 0; q < kPosCap; ++q) {
+            if (q < np) {
+                while (P0 + q >= s_fp[f + 1]) close_fiber();
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) t[v] += vq[q] * dv[q][v];
+            }
+        }
+        for (int q = kPosCap; q < np; ++q) {  // positions past the register cap
+            while (P0 + q >= s_fp[f + 1]) close_fiber();
+            if (colok) {
+                Acc d[VEC];
+                load_row<VEC>(D + static_cast<int64_t>(load_stream(crd2 + P0 + q)) * ldd + col0, d);
+                const Acc vv = widen<Acc>(load_stream(vals + P0 + q));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) t[v] += vv * d[v];
+            }
+        }
+        while (f < b1) close_fiber();
+        while (a < a1) finish(a++);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) s_tail[g][lane * VEC + v] = acc[v];
+        if (lane == 0) {
+            s_done[g] = a1 - a0;
+            s_a0[g] = a0;
+        }
+        __syncthreads();
+
+        if (g == 0) {
+            for (int gg = 0; gg < G; ++gg) {
+                if (s_done[gg] > 0) {
+                    Acc out[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        out[v] = open[v] + s_head[gg][lane * VEC + v];
+                        open[v] = s_tail[gg][lane * VEC + v];
+                    }
+                    if (colok) store_row<VEC>(A + (ci + s_a0[gg]) * lda + col0, out);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) open[v] += s_tail[gg][lane * VEC + v];
+                }
+            }
+        }
         ci = ei;
         cf = ef;
         __syncthreads();
     }
-    if (g == 0 && col0 < R) {
+    if (g == 0 && colok) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) carry[static_cast<int64_t>(blockIdx.x) * R + col0 + v] = open[v];
     }
