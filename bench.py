@@ -102,7 +102,7 @@ def _rate(ms, nbytes, flops):
             "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
 
 
-def measure_other_ops(dev, spl, autotune, torch, fixed=None):
+def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
     200,000^3 CSF tensor with 1e8 nonzeros.  SpTTV and SpMTTKRP run with the
@@ -125,12 +125,12 @@ def measure_other_ops(dev, spl, autotune, torch, fixed=None):
         D = c3["Dd"].to(torch.float32).to(fdt)
         A = torch.empty(nnzB, dtype=torch.float32, device=dev)
         s = spl.schedule(variant=variant)
-        ms = autotune.time_call(lambda: spl.sddmm(B, C, D, A, sched=s), reps=10, warmup=3)
+        ms = tuning.time_call(lambda: spl.sddmm(B, C, D, A, sched=s), reps=10, warmup=3)
         esz = 2 if fdt == torch.bfloat16 else 4
         nbytes = 4 * (n + 1) + 8 * nnzB + K * n * esz * 2 + 4 * nnzB
         res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1))
         del C, D, A
-    ms = autotune.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
+    ms = tuning.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
     out = spl.spadd3(*ops)
     nnzA = out.crd.numel()
     nnzs = sum(o.crd.numel() for o in ops)
@@ -156,10 +156,10 @@ def measure_other_ops(dev, spl, autotune, torch, fixed=None):
     if "spttv" in fixed:
         best_t = fixed["spttv"]
     else:
-        best_t, _ = autotune.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
-                                    autotune.SPMV_CANDIDATES, reps=5)
+        best_t, _ = tuning.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
+                                    tuning.SPMV_CANDIDATES, reps=5)
     st = spl.schedule(**best_t)
-    ms = autotune.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
+    ms = tuning.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
     res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
     res["spttv_f32"]["schedule"] = best_t
     del At
@@ -171,10 +171,10 @@ def measure_other_ops(dev, spl, autotune, torch, fixed=None):
         if "mttkrp" in fixed:
             best_k = fixed["mttkrp"]
         else:
-            best_k, _ = autotune.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
-                                        autotune.MTTKRP_CANDIDATES, reps=3)
+            best_k, _ = tuning.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
+                                        tuning.MTTKRP_CANDIDATES, reps=3)
         sk = spl.schedule(**best_k)
-        ms = autotune.time_call(lambda: spl.mttkrp(Bt, C, D, M, sched=sk), reps=10, warmup=3)
+        ms = tuning.time_call(lambda: spl.mttkrp(Bt, C, D, M, sched=sk), reps=10, warmup=3)
         esz = 2 if dt == torch.bfloat16 else 4
         nbytes = 4 * (I + 1) + 4 * F + 4 * (F + 1) + (4 + esz) * nnz + esz * (J + Kd) * R + 4 * I * R
         res[name] = _rate(ms, nbytes, 2 * R * (nnz + F))
@@ -183,7 +183,7 @@ def measure_other_ops(dev, spl, autotune, torch, fixed=None):
     B64 = B32.with_vals(c4["vals"])
     C64 = B32.with_vals(c4["vals2"])
     a = torch.empty(1, dtype=torch.float64, device=dev)
-    ms = autotune.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
+    ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
     res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
@@ -225,7 +225,7 @@ def main():
     import torch
 
     import paper_2207_13901_amd as spl
-    from paper_2207_13901_amd import autotune
+    from paper_2207_13901_amd import tuning
     from paper_2207_13901_amd import _native as N
     from workloads import configs
 
@@ -244,7 +244,7 @@ def main():
         op, js = item.split("=", 1)
         fixed[op] = json.loads(js)
     if args.ops_only:
-        print(json.dumps({"ops": measure_other_ops(dev, spl, autotune, torch, fixed)}),
+        print(json.dumps({"ops": measure_other_ops(dev, spl, tuning, torch, fixed)}),
               flush=True)
         return
     t0 = time.time()
@@ -270,13 +270,13 @@ def main():
     if args.sched_spmv:
         best_v, res_v = json.loads(args.sched_spmv), []
     else:
-        best_v, res_v = autotune.search(lambda s: (lambda: spl.spmv(B32, x32, y32, sched=s)),
-                                        autotune.SPMV_CANDIDATES, reps=reps)
+        best_v, res_v = tuning.search(lambda s: (lambda: spl.spmv(B32, x32, y32, sched=s)),
+                                        tuning.SPMV_CANDIDATES, reps=reps)
     if args.sched_spmm:
         best_m, res_m = json.loads(args.sched_spmm), []
     else:
-        best_m, res_m = autotune.search(lambda s: (lambda: spl.spmm(B32, D32, A32, sched=s)),
-                                        autotune.SPMM_CANDIDATES, reps=reps)
+        best_m, res_m = tuning.search(lambda s: (lambda: spl.spmm(B32, D32, A32, sched=s)),
+                                        tuning.SPMM_CANDIDATES, reps=reps)
     sv, sm = spl.schedule(**best_v), spl.schedule(**best_m)
     ws_v = spl.workspace(N.OP_SPMV, B32, 1, sv)
     ws_m = spl.workspace(N.OP_SPMM, B32, N_COLS, sm)
@@ -297,8 +297,8 @@ def main():
             sel = learned.Selector.from_json(json.load(open(path)))
             choice = sel.choose(B32)
             sc = spl.schedule(**choice)
-            t_learned = autotune.time_call(lambda: call(sc), reps=10, warmup=3)
-            t_best = autotune.time_call(lambda: call(spl.schedule(**best)), reps=10, warmup=3)
+            t_learned = tuning.time_call(lambda: call(sc), reps=10, warmup=3)
+            t_best = tuning.time_call(lambda: call(spl.schedule(**best)), reps=10, warmup=3)
             learned_out[op] = {"learned_choice": choice, "autotuned_choice": best,
                                "learned_ms": round(t_learned, 5), "autotuned_ms": round(t_best, 5),
                                "regret": round(t_learned / t_best - 1.0, 4)}
@@ -400,7 +400,7 @@ def main():
             ("spmm_f64", lambda: spl.spmm(B64, D64, A64, sched=sm), bm64, 2 * nnz * N_COLS),
             ("spmm_bf16_f32acc", lambda: spl.spmm(B16, D16, A32, sched=sm), bm16, 2 * nnz * N_COLS),
         ):
-            ms = autotune.time_call(fn, reps=10, warmup=3)
+            ms = tuning.time_call(fn, reps=10, warmup=3)
             var[name] = {"ms": round(ms, 5), "GFLOP_s": round(fl / (ms * 1e-3) / 1e9, 2),
                          "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -416,7 +416,7 @@ def main():
     if not args.profile and not args.no_variants:
         # memory-system ceilings the leaves run against
         big = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB
-        ms = autotune.time_call(lambda: spl.probe(0, big), reps=5, warmup=2)
+        ms = tuning.time_call(lambda: spl.probe(0, big), reps=5, warmup=2)
         ceil = {"stream_read_GB_s": round(big.numel() * 4 / (ms * 1e-3) / 1e9, 1)}
         # nnz random row reads, the gather pattern of one SpMV / SpMM call,
         # from tables of growing size (L2 = 4 MB per XCD, MALL = 256 MB)
@@ -424,7 +424,7 @@ def main():
                                (256, (512,))):
             for mb in mbs:
                 table = big[: mb * (1 << 18)]
-                ms = autotune.time_call(
+                ms = tuning.time_call(
                     lambda: spl.probe(1, table, row_bytes=row_bytes, count=nnz), reps=5, warmup=2)
                 ceil[f"gather_{row_bytes}B_rows_from_{mb}MB"] = {
                     "ms_per_nnz_gathers": round(ms, 5),
@@ -432,7 +432,7 @@ def main():
         # the same gathers with 16-byte lanes (a quarter of the load instructions)
         for row_bytes, mb in ((64, 128), (128, 256)):
             table = big[: mb * (1 << 18)]
-            ms = autotune.time_call(
+            ms = tuning.time_call(
                 lambda: spl.probe(2, table, row_bytes=row_bytes, count=nnz), reps=5, warmup=2)
             ceil[f"gather_{row_bytes}B_rows_16B_lanes_from_{mb}MB"] = {
                 "ms_per_nnz_gathers": round(ms, 5),
@@ -443,7 +443,7 @@ def main():
     if not args.profile and not args.no_ops:
         del B64, B16, D64, D16, A64
         torch.cuda.empty_cache()
-        out["ops"] = measure_other_ops(dev, spl, autotune, torch, fixed)
+        out["ops"] = measure_other_ops(dev, spl, tuning, torch, fixed)
 
     if not args.profile and not args.no_cpu:
         import oracle

@@ -72,7 +72,12 @@ typedef enum spl_sched_kind {
     SPL_SCHED_DEFAULT = 0, /* library choice (merge split)                    */
     SPL_ROW = 1,   /* universe partition of rows, image to positions          */
     SPL_NNZ = 2,   /* non-zero partition of fused positions, rows by preimage */
-    SPL_MERGE = 3  /* equal split of the merged (row ends + positions) list   */
+    SPL_MERGE = 3, /* equal split of the merged (row ends + positions) list   */
+    /* SpMV and SpMM only (see spl_mlp_predict and spl_autotune): */
+    SPL_SCHED_LEARNED = 4,  /* the context's selector picks one of its
+                               candidates from the matrix's features          */
+    SPL_SCHED_AUTOTUNE = 5  /* every candidate is timed on this call's
+                               operands and the fastest one runs              */
 } spl_sched_kind;
 
 typedef enum spl_op {
@@ -214,7 +219,10 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
 /* SpMV  a(i) = B(i,j) * c(j)   (Sec. VI-A; the leaf of Fig. 8b).
  * B CSR n x m; c vector m; a vector n.  dtypes: vals, c, a all F64, or all
  * F32 (products and sums in F64, rounded once per output).  Schedules: ROW,
- * NNZ, MERGE (default MERGE). */
+ * NNZ, MERGE (default MERGE), and SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE
+ * (resolved first to one of the candidates, which synchronizes on
+ * `stream`; a caller workspace must then fit every candidate, as
+ * spl_workspace_query returns for those kinds). */
 spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
                     spl_dense *a, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);
@@ -229,7 +237,7 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * lanes per group and items_per_lane is 8 or 16 (otherwise one column per
  * lane); 1 = one column per lane.
  * The workspace query returns the one-column-per-lane size, enough for
- * both. */
+ * both.  SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE as for spl_spmv. */
 spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                     spl_dense *A, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);
@@ -346,6 +354,57 @@ spl_status spl_mlp_backward(spl_context *ctx, int K, const float *params, int64_
 spl_status spl_adam_step(spl_context *ctx, int64_t n, float *params, float *m, float *v,
                          const float *grad, float lr, float beta1, float beta2, float eps,
                          int step, spl_stream stream);
+
+/* ------------------------------------------------- schedule selection */
+
+/* Exhaustive autotuning, the selector's fallback and its ground truth.
+ * Times every candidate schedule of `op` (SPL_OP_SPMV: X = c, Y = a;
+ * SPL_OP_SPMM: X = C, Y = A; operands as for spl_spmv / spl_spmm) on
+ * `stream` with HIP events: one untimed call, then `reps` (1..100) timed
+ * calls, median.  `candidates` (host, `ncand` of them, kinds SPL_ROW,
+ * SPL_NNZ or SPL_MERGE) may be NULL with ncand = 0 for the library's list
+ * (12 SpMV, 9 SpMM schedules).  Writes the fastest candidate to *best (host)
+ * and, if times_ms is not NULL, every median in milliseconds (host, one per
+ * candidate).  Y is overwritten.  Synchronizes on `stream`.  The calls use
+ * the context's own workspace. */
+spl_status spl_autotune(spl_context *ctx, spl_op op, const spl_sparse *B, const spl_dense *X,
+                        spl_dense *Y, const spl_schedule *candidates, int ncand, int reps,
+                        spl_schedule *best, float *times_ms, spl_stream stream);
+
+/* Install a trained schedule selector for `op` (SPL_OP_SPMV or SPL_OP_SPMM)
+ * in the context, which keeps its own device copy: K candidate schedules
+ * (host; kinds SPL_ROW, SPL_NNZ, SPL_MERGE), the network parameters (host,
+ * spl_mlp_param_count(K) floats, layout of spl_mlp_forward) and the feature
+ * standardization (host, 7 means then 7 inverse standard deviations; NULL
+ * for none).  Resets the training state of spl_mlp_train_step.  Replaces
+ * any selector installed for `op`. */
+spl_status spl_mlp_load(spl_context *ctx, spl_op op, int K, const spl_schedule *candidates,
+                        const float *params, const float *norm);
+
+/* Copy the selector installed for `op` out of the context (after all work
+ * on the device has finished): *K always; then, where not NULL and cap >= K,
+ * the candidates, the parameters and the standardization (host buffers of
+ * cap schedules, spl_mlp_param_count(K) floats and 14 floats).
+ * SPL_ERR_UNSUPPORTED if none is installed. */
+spl_status spl_mlp_save(spl_context *ctx, spl_op op, int *K, int cap, spl_schedule *candidates,
+                        float *params, float *norm);
+
+/* The installed selector's choice for B: the 7 features (spl_features) and
+ * the network's K predictions on the device, the candidate with the
+ * smallest prediction (first on ties) to *out (host).  Synchronizes on
+ * `stream`.  SPL_ERR_UNSUPPORTED if no selector is installed for `op`.
+ * This is what SPL_SCHED_LEARNED runs. */
+spl_status spl_mlp_predict(spl_context *ctx, spl_op op, const spl_sparse *B, spl_schedule *out,
+                           spl_stream stream);
+
+/* One training step of the installed selector on a batch: X (device,
+ * batch x 7 raw features), T (device, batch x K targets); forward, mean
+ * squared error backward and one Adam step (beta1 0.9, beta2 0.999, eps
+ * 1e-8, learning rate lr) on the context's parameters and moments, all on
+ * `stream`; the batch loss before the step to *loss (device, may be NULL).
+ * Uses the context's workspace. */
+spl_status spl_mlp_train_step(spl_context *ctx, spl_op op, const float *X, const float *T,
+                              int64_t batch, float lr, float *loss, spl_stream stream);
 
 #ifdef __cplusplus
 }

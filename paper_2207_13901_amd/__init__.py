@@ -15,6 +15,7 @@ import ctypes
 from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import _native as N
@@ -24,11 +25,14 @@ __all__ = [
     "CSR", "CSF", "Context", "schedule", "spmv", "spmm", "tile_bounds",
     "validate", "op_parse", "op_tin", "workspace_query", "workspace", "SpleafError",
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
-    "spadd3",
+    "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
+    "schedule_dict",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
-_KIND = {"default": N.SCHED_DEFAULT, "row": N.ROW, "nnz": N.NNZ, "merge": N.MERGE}
+_KIND = {"default": N.SCHED_DEFAULT, "row": N.ROW, "nnz": N.NNZ, "merge": N.MERGE,
+         "learned": N.SCHED_LEARNED, "autotune": N.SCHED_AUTOTUNE}
+_KIND_NAME = {v: k for k, v in _KIND.items()}
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -372,3 +376,100 @@ def spadd3(B: CSR, C: CSR, D: CSR, sched=None, ctx: Optional[Context] = None) ->
                                          _ptr(avals), _sched_ptr(sched), stream),
               "spl_spadd3_numeric")
     return CSR(apos, acrd, avals, B.shape)
+
+
+# ------------------------------------------------------- schedule selection
+
+_SCHED_FIELDS = ("lanes_per_row", "tile", "items_per_lane", "col_tile", "variant")
+
+
+def schedule_dict(s: N.SplSchedule) -> dict:
+    """A spl_schedule as the keyword dict `schedule()` takes (zero fields
+    left out)."""
+    d = {"kind": _KIND_NAME.get(s.kind, int(s.kind))}
+    for f in _SCHED_FIELDS:
+        v = int(getattr(s, f))
+        if v:
+            d[f] = v
+    return d
+
+
+def _sched_array(cands):
+    arr = (N.SplSchedule * len(cands))()
+    for i, c in enumerate(cands):
+        arr[i] = c if isinstance(c, N.SplSchedule) else schedule(**c)
+    return arr
+
+
+def _selector_op(op) -> int:
+    return {"spmv": N.OP_SPMV, "spmm": N.OP_SPMM}.get(op, op)
+
+
+def autotune(op, B: CSR, X: torch.Tensor, Y: torch.Tensor, candidates=None, reps: int = 3,
+             ctx: Optional[Context] = None):
+    """spl_autotune: time every candidate (dicts or spl_schedule; None for
+    the library's list) on these operands; returns (best dict, [ms, ...])."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    op = _selector_op(op)
+    s = B.struct()
+    arr = _sched_array(candidates) if candidates is not None else None
+    n = len(arr) if arr is not None else 0
+    times = (ctypes.c_float * max(n, 16))()
+    best = N.SplSchedule()
+    ctx.check(ctx.lib.spl_autotune(ctx.h, op, ctypes.byref(s), ctypes.byref(_dense(X)),
+                                   ctypes.byref(_dense(Y)), arr, n, reps, ctypes.byref(best),
+                                   times, stream), "spl_autotune")
+    count = n if n else (12 if op == N.OP_SPMV else 9)
+    return schedule_dict(best), [float(times[i]) for i in range(count)]
+
+
+def mlp_load(op, candidates, params, norm=None, ctx: Optional[Context] = None) -> None:
+    """spl_mlp_load: install a selector (host parameters and 7 means + 7
+    inverse standard deviations) in the context."""
+    ctx = ctx or Context.get()
+    arr = _sched_array(candidates)
+    P = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    nrm = None if norm is None else np.ascontiguousarray(np.asarray(norm, dtype=np.float32))
+    ctx.check(ctx.lib.spl_mlp_load(ctx.h, _selector_op(op), len(arr), arr,
+                                   P.ctypes.data, None if nrm is None else nrm.ctypes.data),
+              "spl_mlp_load")
+
+
+def mlp_save(op, ctx: Optional[Context] = None):
+    """spl_mlp_save: (candidate dicts, parameters, standardization) of the
+    installed selector, as numpy arrays."""
+    ctx = ctx or Context.get()
+    op = _selector_op(op)
+    K = ctypes.c_int()
+    ctx.check(ctx.lib.spl_mlp_save(ctx.h, op, ctypes.byref(K), 0, None, None, None),
+              "spl_mlp_save")
+    arr = (N.SplSchedule * K.value)()
+    P = np.empty(int(ctx.lib.spl_mlp_param_count(K.value)), dtype=np.float32)
+    nrm = np.empty(14, dtype=np.float32)
+    ctx.check(ctx.lib.spl_mlp_save(ctx.h, op, ctypes.byref(K), K.value, arr, P.ctypes.data,
+                                   nrm.ctypes.data), "spl_mlp_save")
+    return [schedule_dict(a) for a in arr], P, nrm
+
+
+def mlp_predict(op, B: CSR, ctx: Optional[Context] = None) -> dict:
+    """spl_mlp_predict: the installed selector's schedule for B."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    out = N.SplSchedule()
+    s = B.struct()
+    ctx.check(ctx.lib.spl_mlp_predict(ctx.h, _selector_op(op), ctypes.byref(s),
+                                      ctypes.byref(out), stream), "spl_mlp_predict")
+    return schedule_dict(out)
+
+
+def mlp_train_step(op, X: torch.Tensor, T: torch.Tensor, lr: float,
+                   loss: Optional[torch.Tensor] = None, ctx: Optional[Context] = None):
+    """spl_mlp_train_step on a batch (X: batch x 7 raw features, T: batch x K,
+    float32 on the GPU); returns the device loss tensor (loss before the
+    step)."""
+    ctx, stream = _ctx_stream(X, ctx)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    ctx.check(ctx.lib.spl_mlp_train_step(ctx.h, _selector_op(op), X.data_ptr(), T.data_ptr(),
+                                         X.shape[0], lr, loss.data_ptr(), stream),
+              "spl_mlp_train_step")
+    return loss

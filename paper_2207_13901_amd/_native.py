@@ -16,7 +16,7 @@ OK, ERR_ARG, ERR_FORMAT, ERR_SHAPE, ERR_DTYPE, ERR_UNSUPPORTED, ERR_WORKSPACE, \
     ERR_NOMEM, ERR_HIP, ERR_INVALID = range(10)
 F64, F32, BF16 = 0, 1, 2
 DENSE, COMPRESSED = 0, 1
-SCHED_DEFAULT, ROW, NNZ, MERGE = 0, 1, 2, 3
+SCHED_DEFAULT, ROW, NNZ, MERGE, SCHED_LEARNED, SCHED_AUTOTUNE = 0, 1, 2, 3, 4, 5
 OP_SPMV, OP_SPMM, OP_SPADD3, OP_SDDMM, OP_SPTTV, OP_MTTKRP, OP_INNER = range(7)
 
 
@@ -93,6 +93,12 @@ SIGNATURES = {
     "spl_mlp_backward": (_I32, [_P, ctypes.c_int, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "spl_adam_step": (_I32, [_P, _I64, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                              ctypes.c_float, ctypes.c_float, ctypes.c_int, _P]),
+    "spl_autotune": (_I32, [_P, _I32, _SP, _DP, _DP, _SCH, ctypes.c_int, ctypes.c_int, _SCH,
+                            _P, _P]),
+    "spl_mlp_load": (_I32, [_P, _I32, ctypes.c_int, _SCH, _P, _P]),
+    "spl_mlp_save": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _SCH, _P, _P]),
+    "spl_mlp_predict": (_I32, [_P, _I32, _SP, _SCH, _P]),
+    "spl_mlp_train_step": (_I32, [_P, _I32, _P, _P, _I64, ctypes.c_float, _P, _P]),
 }
 
 _lib = None

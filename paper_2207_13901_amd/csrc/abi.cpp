@@ -29,6 +29,19 @@ struct spl_context {
     bool timing = false;
     std::vector<Mark> marks;
     std::vector<hipEvent_t> spare;
+    // installed schedule selectors (spl_mlp_*), [0] SpMV, [1] SpMM
+    struct Selector {
+        int K = 0;
+        std::vector<spl_schedule> cands;
+        int64_t nparams = 0;
+        float *params = nullptr;   // device, the network
+        float *norm = nullptr;     // device, 7 means + 7 inverse standard deviations
+        float *m = nullptr;        // device, Adam moments
+        float *v = nullptr;
+        float *scratch = nullptr;  // device, 8 features + K predictions
+        int step = 0;
+    };
+    Selector sel[2];
 };
 
 namespace {
@@ -501,6 +514,94 @@ const char *const kTin[7] = {
     "a=B(i,j,k)*C(i,j,k)",
 };
 
+spl_schedule make_sched(int kind, int lanes, int tile, int items, int col_tile) {
+    spl_schedule s{};
+    s.kind = kind;
+    s.lanes_per_row = lanes;
+    s.tile = tile;
+    s.items_per_lane = items;
+    s.col_tile = col_tile;
+    return s;
+}
+
+// The library's candidate lists for spl_autotune and SPL_SCHED_AUTOTUNE:
+// SpMV row splits of 1..64 lanes, non-zero splits of 1024..4096 positions
+// and two merge splits; SpMM row split and non-zero/merge splits at 32
+// columns per lane group.
+const std::vector<spl_schedule> &default_candidates(spl_op op) {
+    static const std::vector<spl_schedule> spmv = [] {
+        std::vector<spl_schedule> v;
+        for (int L : {1, 2, 4, 8, 16, 32, 64}) v.push_back(make_sched(SPL_ROW, L, 0, 0, 0));
+        for (int T : {1024, 2048, 4096}) v.push_back(make_sched(SPL_NNZ, 0, T, 8, 0));
+        v.push_back(make_sched(SPL_MERGE, 0, 1024, 4, 0));
+        v.push_back(make_sched(SPL_MERGE, 0, 2048, 8, 0));
+        return v;
+    }();
+    static const std::vector<spl_schedule> spmm = [] {
+        std::vector<spl_schedule> v;
+        v.push_back(make_sched(SPL_ROW, 0, 0, 0, 32));
+        for (int T : {256, 1024}) v.push_back(make_sched(SPL_NNZ, 0, T, 16, 32));
+        for (int it : {8, 16, 32})
+            for (int k : {1, 4}) v.push_back(make_sched(SPL_MERGE, 0, 8 * it * k, it, 32));
+        return v;
+    }();
+    return op == SPL_OP_SPMV ? spmv : spmm;
+}
+
+int sel_index(spl_op op) { return op == SPL_OP_SPMV ? 0 : op == SPL_OP_SPMM ? 1 : -1; }
+
+bool concrete_kind(int k) { return k >= SPL_SCHED_DEFAULT && k <= SPL_MERGE; }
+
+bool selection_kind(const spl_schedule *s) {
+    return s && (s->kind == SPL_SCHED_LEARNED || s->kind == SPL_SCHED_AUTOTUNE);
+}
+
+// The schedules a selection kind chooses among: the installed selector's
+// candidates (SPL_SCHED_LEARNED needs one; SPL_SCHED_AUTOTUNE uses them when
+// present), else the library's list.
+spl_status selection_candidates(spl_context *ctx, spl_op op, int kind,
+                                const std::vector<spl_schedule> *&out) {
+    const int i = sel_index(op);
+    if (i < 0)
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "learned and autotuned schedules cover SpMV and SpMM");
+    if (ctx->sel[i].K > 0) {
+        out = &ctx->sel[i].cands;
+        return SPL_OK;
+    }
+    if (kind == SPL_SCHED_LEARNED)
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "no schedule selector installed (spl_mlp_load)");
+    out = &default_candidates(op);
+    return SPL_OK;
+}
+
+// Events of one autotuning run, destroyed on every exit path.
+struct EventSet {
+    std::vector<hipEvent_t> e;
+    explicit EventSet(int n) : e(n, nullptr) {}
+    ~EventSet() {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// Resolve SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE to one concrete schedule
+// (`chosen`, which `sched` then points to); other kinds pass through.
+spl_status select_schedule(spl_context *ctx, spl_op op, const spl_sparse *B, const spl_dense *X,
+                           spl_dense *Y, const spl_schedule *&sched, spl_schedule &chosen,
+                           spl_stream stream) {
+    if (!selection_kind(sched)) return SPL_OK;
+    if (sched->kind == SPL_SCHED_LEARNED) {
+        SPL_CHECK(spl_mlp_predict(ctx, op, B, &chosen, stream));
+    } else {
+        const std::vector<spl_schedule> *c = nullptr;
+        SPL_CHECK(selection_candidates(ctx, op, SPL_SCHED_AUTOTUNE, c));
+        SPL_CHECK(spl_autotune(ctx, op, B, X, Y, c->data(), static_cast<int>(c->size()), 3,
+                               &chosen, nullptr, stream));
+    }
+    sched = &chosen;
+    return SPL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -555,6 +656,9 @@ spl_status spl_context_destroy(spl_context *ctx) {
         (void)hipEventDestroy(m.stop);
     }
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+    for (auto &sl : ctx->sel)
+        for (float *b : {sl.params, sl.norm, sl.m, sl.v, sl.scratch})
+            if (b) (void)hipFree(b);
     delete ctx;
     return SPL_OK;
     SPL_GUARD_END
@@ -642,15 +746,26 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
     Plan p;
     switch (op) {
     case SPL_OP_SPMV:
+    case SPL_OP_SPMM: {
         SPL_CHECK(check_sparse(ctx, B, 2));
-        SPL_CHECK(resolve_spmv(ctx, B, sched, p));
-        *bytes = spmv_ws(B, p);
+        // a selection kind needs room for whichever candidate it picks
+        std::vector<spl_schedule> one;
+        const std::vector<spl_schedule> *list = &one;
+        if (selection_kind(sched))
+            SPL_CHECK(selection_candidates(ctx, op, sched->kind, list));
+        else
+            one.push_back(sched ? *sched : spl_schedule{});
+        for (const spl_schedule &c : *list) {
+            if (op == SPL_OP_SPMV) {
+                SPL_CHECK(resolve_spmv(ctx, B, &c, p));
+                *bytes = std::max(*bytes, spmv_ws(B, p));
+            } else {
+                SPL_CHECK(resolve_spmm(ctx, B, ncols, &c, p));
+                *bytes = std::max(*bytes, spmm_ws(B, ncols, p));
+            }
+        }
         return SPL_OK;
-    case SPL_OP_SPMM:
-        SPL_CHECK(check_sparse(ctx, B, 2));
-        SPL_CHECK(resolve_spmm(ctx, B, ncols, sched, p));
-        *bytes = spmm_ws(B, ncols, p);
-        return SPL_OK;
+    }
     case SPL_OP_SPTTV: {
         SPL_CHECK(check_sparse(ctx, B, 3));
         const spl_sparse v = fiber_view(B);
@@ -789,6 +904,8 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     SPL_CHECK(check_dense(ctx, a, "a", 1, B->dims[0], -1));
     if (B->vtype == SPL_BF16 || c->dtype != B->vtype || a->dtype != B->vtype)
         return fail(ctx, SPL_ERR_DTYPE, "SpMV needs vals, c and a all F64 or all F32");
+    spl_schedule chosen{};
+    SPL_CHECK(select_schedule(ctx, SPL_OP_SPMV, B, c, a, sched, chosen, stream));
     Plan p;
     SPL_CHECK(resolve_spmv(ctx, B, sched, p));
     SPL_CHECK(set_device(ctx));
@@ -838,6 +955,8 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     if (!ok)
         return fail(ctx, SPL_ERR_DTYPE,
                     "SpMM dtypes (vals, C, A) must be (F64,F64,F64), (F32,F32,F32) or (BF16,BF16,F32)");
+    spl_schedule chosen{};
+    SPL_CHECK(select_schedule(ctx, SPL_OP_SPMM, B, C, A, sched, chosen, stream));
     Plan p;
     SPL_CHECK(resolve_spmm(ctx, B, N, sched, p));
     SPL_CHECK(set_device(ctx));
@@ -1208,6 +1327,191 @@ spl_status spl_adam_step(spl_context *ctx, int64_t n, float *params, float *m, f
     SPL_CHECK(set_device(ctx));
     SPL_HIP(spl::launch_adam(n, params, m, v, grad, lr, beta1, beta2, eps, step,
                              static_cast<hipStream_t>(stream)),
+            "Adam launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_autotune(spl_context *ctx, spl_op op, const spl_sparse *B, const spl_dense *X,
+                        spl_dense *Y, const spl_schedule *candidates, int ncand, int reps,
+                        spl_schedule *best, float *times_ms, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (sel_index(op) < 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "spl_autotune covers SpMV and SpMM");
+    if (!best) return fail(ctx, SPL_ERR_ARG, "NULL best");
+    if (reps < 1 || reps > 100) return fail(ctx, SPL_ERR_ARG, "reps must be 1..100");
+    const spl_schedule *list = candidates;
+    int n = ncand;
+    if (!list) {
+        if (ncand != 0) return fail(ctx, SPL_ERR_ARG, "NULL candidates with ncand != 0");
+        const std::vector<spl_schedule> &d = default_candidates(op);
+        list = d.data();
+        n = static_cast<int>(d.size());
+    }
+    if (n < 1 || n > 4096) return fail(ctx, SPL_ERR_ARG, "ncand must be 1..4096");
+    for (int i = 0; i < n; ++i)
+        if (!concrete_kind(list[i].kind))
+            return fail(ctx, SPL_ERR_ARG, "candidate %d: kind must be DEFAULT, ROW, NNZ or MERGE", i);
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    EventSet ev(2 * reps);
+    for (hipEvent_t &e : ev.e) SPL_HIP(hipEventCreate(&e), "hipEventCreate");
+    std::vector<float> med(n), t(reps);
+    for (int i = 0; i < n; ++i) {
+        auto call = [&]() {
+            return op == SPL_OP_SPMV ? spl_spmv(ctx, B, X, Y, &list[i], nullptr, 0, stream)
+                                     : spl_spmm(ctx, B, X, Y, &list[i], nullptr, 0, stream);
+        };
+        SPL_CHECK(call());  // untimed: first-touch effects and workspace growth
+        for (int r = 0; r < reps; ++r) {
+            SPL_HIP(hipEventRecord(ev.e[2 * r], s), "hipEventRecord");
+            SPL_CHECK(call());
+            SPL_HIP(hipEventRecord(ev.e[2 * r + 1], s), "hipEventRecord");
+        }
+        SPL_HIP(hipEventSynchronize(ev.e[2 * reps - 1]), "hipEventSynchronize");
+        for (int r = 0; r < reps; ++r)
+            SPL_HIP(hipEventElapsedTime(&t[r], ev.e[2 * r], ev.e[2 * r + 1]),
+                    "hipEventElapsedTime");
+        std::sort(t.begin(), t.end());
+        med[i] = t[reps / 2];
+    }
+    const int k = static_cast<int>(std::min_element(med.begin(), med.end()) - med.begin());
+    *best = list[k];
+    if (times_ms) std::copy(med.begin(), med.end(), times_ms);
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mlp_load(spl_context *ctx, spl_op op, int K, const spl_schedule *candidates,
+                        const float *params, const float *norm) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    const int i = sel_index(op);
+    if (i < 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "schedule selectors cover SpMV and SpMM");
+    if (K < 1 || K > 256) return fail(ctx, SPL_ERR_ARG, "K must be 1..256");
+    if (!candidates || !params) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    for (int k = 0; k < K; ++k)
+        if (!concrete_kind(candidates[k].kind))
+            return fail(ctx, SPL_ERR_ARG, "candidate %d: kind must be DEFAULT, ROW, NNZ or MERGE", k);
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");  // the old buffers may be in use
+    spl_context::Selector &sl = ctx->sel[i];
+    for (float **b : {&sl.params, &sl.norm, &sl.m, &sl.v, &sl.scratch}) {
+        if (*b) (void)hipFree(*b);
+        *b = nullptr;
+    }
+    sl = spl_context::Selector{};
+    const int64_t np = spl::mlp_param_count(K);
+    const size_t pb = static_cast<size_t>(np) * sizeof(float);
+    for (auto [b, bytes] : {std::pair<float **, size_t>{&sl.params, pb}, {&sl.m, pb}, {&sl.v, pb},
+                            {&sl.norm, 14 * sizeof(float)},
+                            {&sl.scratch, static_cast<size_t>(8 + K) * sizeof(float)}}) {
+        if (hipMalloc(reinterpret_cast<void **>(b), bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, SPL_ERR_NOMEM, "hipMalloc(%zu) for the selector failed", bytes);
+        }
+    }
+    float ident[14];
+    for (int j = 0; j < 7; ++j) {
+        ident[j] = 0.0f;
+        ident[7 + j] = 1.0f;
+    }
+    SPL_HIP(hipMemcpy(sl.params, params, pb, hipMemcpyHostToDevice), "hipMemcpy");
+    SPL_HIP(hipMemcpy(sl.norm, norm ? norm : ident, sizeof ident, hipMemcpyHostToDevice),
+            "hipMemcpy");
+    SPL_HIP(hipMemset(sl.m, 0, pb), "hipMemset");
+    SPL_HIP(hipMemset(sl.v, 0, pb), "hipMemset");
+    sl.K = K;
+    sl.nparams = np;
+    sl.cands.assign(candidates, candidates + K);
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mlp_save(spl_context *ctx, spl_op op, int *K, int cap, spl_schedule *candidates,
+                        float *params, float *norm) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    const int i = sel_index(op);
+    if (i < 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "schedule selectors cover SpMV and SpMM");
+    if (!K) return fail(ctx, SPL_ERR_ARG, "NULL K");
+    const spl_context::Selector &sl = ctx->sel[i];
+    if (sl.K == 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "no schedule selector installed");
+    *K = sl.K;
+    if (cap < sl.K) return SPL_OK;
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (candidates) std::copy(sl.cands.begin(), sl.cands.end(), candidates);
+    if (params)
+        SPL_HIP(hipMemcpy(params, sl.params, static_cast<size_t>(sl.nparams) * sizeof(float),
+                          hipMemcpyDeviceToHost),
+                "hipMemcpy");
+    if (norm) SPL_HIP(hipMemcpy(norm, sl.norm, 14 * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mlp_predict(spl_context *ctx, spl_op op, const spl_sparse *B, spl_schedule *out,
+                           spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    const int i = sel_index(op);
+    if (i < 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "schedule selectors cover SpMV and SpMM");
+    if (!out) return fail(ctx, SPL_ERR_ARG, "NULL output");
+    const spl_context::Selector &sl = ctx->sel[i];
+    if (sl.K == 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "no schedule selector installed (spl_mlp_load)");
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *feat = sl.scratch, *Y = sl.scratch + 8;
+    SPL_CHECK(spl_features(ctx, B, feat, nullptr, 0, stream));
+    SPL_HIP(spl::launch_mlp_forward(sl.K, sl.params, feat, sl.norm, 1, Y, nullptr, s),
+            "MLP forward launch");
+    std::vector<float> y(sl.K);
+    SPL_HIP(hipMemcpyAsync(y.data(), Y, y.size() * sizeof(float), hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync");
+    SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const int k = static_cast<int>(std::min_element(y.begin(), y.end()) - y.begin());
+    *out = sl.cands[k];
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_mlp_train_step(spl_context *ctx, spl_op op, const float *X, const float *T,
+                              int64_t batch, float lr, float *loss, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    const int i = sel_index(op);
+    if (i < 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "schedule selectors cover SpMV and SpMM");
+    spl_context::Selector &sl = ctx->sel[i];
+    if (sl.K == 0) return fail(ctx, SPL_ERR_UNSUPPORTED, "no schedule selector installed (spl_mlp_load)");
+    if (batch < 1 || batch > (1LL << 24)) return fail(ctx, SPL_ERR_ARG, "batch must be 1..2^24");
+    if (!X || !T) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int K = sl.K;
+    // context workspace: activations, predictions, gradient, backward scratch
+    const size_t n_act = static_cast<size_t>(128 + 7) * batch, n_y = static_cast<size_t>(K) * batch;
+    const size_t n_dz = static_cast<size_t>(128 + K) * batch, n_lb = static_cast<size_t>(batch);
+    const size_t need = (align_up(n_act * 4) + align_up(n_y * 4) + align_up(sl.nparams * 4) +
+                         align_up(n_dz * 4) + align_up(n_lb * 4));
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, nullptr, 0, need, &ws));
+    char *w = static_cast<char *>(ws);
+    auto take = [&](size_t count) {
+        float *p = reinterpret_cast<float *>(w);
+        w += align_up(count * 4);
+        return p;
+    };
+    float *act = take(n_act), *Y = take(n_y), *grad = take(sl.nparams), *dZ = take(n_dz),
+          *loss_b = take(n_lb);
+    SPL_HIP(spl::launch_mlp_forward(K, sl.params, X, sl.norm, batch, Y, act, s),
+            "MLP forward launch");
+    SPL_HIP(spl::launch_mlp_backward(K, sl.params, batch, Y, T, act, dZ, loss_b, grad, loss, s),
+            "MLP backward launch");
+    ++sl.step;
+    SPL_HIP(spl::launch_adam(sl.nparams, sl.params, sl.m, sl.v, grad, lr, 0.9f, 0.999f, 1e-8f,
+                             sl.step, s),
             "Adam launch");
     return SPL_OK;
     SPL_GUARD_END

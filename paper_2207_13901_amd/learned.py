@@ -27,11 +27,11 @@ from typing import Dict, List, Optional
 import numpy as np
 import torch
 
-from . import CSR, Context, autotune, schedule, spmm, spmv
+from . import CSR, Context, schedule, spmm, spmv, tuning
 
 IN = 7
 
-SPMV_CANDIDATES = autotune.SPMV_CANDIDATES
+SPMV_CANDIDATES = tuning.SPMV_CANDIDATES
 SPMM_CANDIDATES: List[Dict] = [
     dict(kind="row", col_tile=32),
     dict(kind="nnz", tile=1024, col_tile=32, items_per_lane=16),
@@ -240,13 +240,13 @@ def collect(ids, out_path: str, device="cuda", reps: int = 5, max_nnz: float = 1
             y = torch.empty(n, dtype=torch.float32, device=dev)
             row = dict(s, feat=features(B).cpu().tolist())
             row["spmv_ms"] = [
-                autotune.time_call(lambda sc=schedule(**c): spmv(B, x, y, sched=sc), reps=reps)
+                tuning.time_call(lambda sc=schedule(**c): spmv(B, x, y, sched=sc), reps=reps)
                 for c in SPMV_CANDIDATES]
             if with_spmm:
                 D = torch.ones(n, SPMM_COLS, dtype=torch.float32, device=dev)
                 A = torch.empty(n, SPMM_COLS, dtype=torch.float32, device=dev)
                 row["spmm_ms"] = [
-                    autotune.time_call(lambda sc=schedule(**c): spmm(B, D, A, sched=sc), reps=reps)
+                    tuning.time_call(lambda sc=schedule(**c): spmm(B, D, A, sched=sc), reps=reps)
                     for c in SPMM_CANDIDATES]
                 del D, A
             out.write(json.dumps(row) + "\n")

@@ -18,8 +18,8 @@ pytestmark = pytest.mark.gpu
 def _spl():
     need_gpu()
     import paper_2207_13901_amd as spl
-    from paper_2207_13901_amd import autotune
-    return spl, autotune
+    from paper_2207_13901_amd import tuning
+    return spl, tuning
 
 
 def _sample_rows(pos, k=1500, seed=0):
@@ -40,7 +40,7 @@ def c2():
 
 
 def test_config2_spmv_sampled(c2):
-    spl, autotune = _spl()
+    spl, tuning = _spl()
     c, h = c2
     n = c["n"]
     rows = _sample_rows(h["pos"])
@@ -48,14 +48,14 @@ def test_config2_spmv_sampled(c2):
         B = spl.CSR(c["pos"], c["crd"], c["vals"].to(dtype), (n, n))
         x = c["x"].to(dtype)
         ref, S = oracle.spmv(h["pos"], h["crd"], host64(B.vals), host64(x), rows=rows)
-        for cand in autotune.SPMV_CANDIDATES[4:]:  # skip the slowest row splits
+        for cand in tuning.SPMV_CANDIDATES[4:]:  # skip the slowest row splits
             y = spl.spmv(B, x, sched=spl.schedule(**cand))
             assert_close(host64(y[torch.as_tensor(rows, device=y.device)]), ref, S, rtol,
                          f"spmv {dtype} {cand}")
 
 
 def test_config2_spmm_sampled(c2):
-    spl, autotune = _spl()
+    spl, tuning = _spl()
     c, h = c2
     n = c["n"]
     rows = _sample_rows(h["pos"], k=400, seed=1)
@@ -64,7 +64,7 @@ def test_config2_spmm_sampled(c2):
         D = c["B"].to(torch.float32).to(dtype)
         Dh = host64(D)
         ref, S = oracle.spmm(h["pos"], h["crd"], host64(B.vals), Dh, rows=rows)
-        for cand in autotune.SPMM_CANDIDATES[1:]:
+        for cand in tuning.SPMM_CANDIDATES[1:]:
             A = spl.spmm(B, D, sched=spl.schedule(**cand))
             got = host64(A[torch.as_tensor(rows, device=A.device)])
             assert_close(got, ref, S, rtol, f"spmm {dtype} {cand}")
