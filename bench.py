@@ -14,7 +14,11 @@ before warm-up).  `value` is GFLOP/s of the step (2 nnz + 2 nnz N flops).
 Besides the headline line it reports, from the same run:
  - roofline: the dominant leaf kernel (SpMM) against the 8 TB/s HBM peak,
    with its duration taken from HIP events the library records around that
-   kernel on its own stream during the timed steps;
+   kernel on its own stream during the timed steps, and its HBM-side
+   traffic from hardware counters when they were taken on these sources;
+ - leaf_spread: min / median / max per-launch time of the SpMV and SpMM
+   leaves, back to back (warm) and after a 1 GiB write that flushes the
+   256 MB MALL (cold);
  - variants: FP64 SpMV/SpMM and BF16 SpMM (FP32 accumulation) with the same
    schedules, and the row / non-zero / merge schedules compared;
  - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
@@ -335,6 +339,30 @@ def main():
     flops = 2.0 * nnz + 2.0 * nnz * N_COLS
     gflops = flops / (ms_per_step * 1e-3) / 1e9
 
+    # per-launch spread of the two leaf kernels (untimed loop after the
+    # timed steps, one read-back per step), warm and with the 256 MB MALL
+    # flushed by a 1 GiB write before each step
+    spread = {}
+    if not args.profile:
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        for mode in ("warm", "cold"):
+            per = {"spmv": [], "spmm": []}
+            for _ in range(10):
+                if mode == "cold":
+                    flush.fill_(1.0)
+                torch.cuda.synchronize()
+                spl.timing_enable(True)
+                step()
+                spl.timing_enable(False)
+                per["spmv"].append(spl.timing_read(N.OP_SPMV)[1])
+                per["spmm"].append(spl.timing_read(N.OP_SPMM)[1])
+            for op, v in per.items():
+                v = sorted(v)
+                spread.setdefault(op, {})[mode] = {"min_ms": round(v[0], 5),
+                                                   "median_ms": round(v[len(v) // 2], 5),
+                                                   "max_ms": round(v[-1], 5)}
+        del flush
+
     bytes_v32, bytes_m32 = algorithmic_bytes(n, n, nnz, N_COLS, 4, 4, 4)
     spmm_ms = msm / max(lm, 1)
     spmv_ms = msv / max(lv, 1)
@@ -382,6 +410,7 @@ def main():
                          "frac_hbm": round(achieved / HBM_PEAK_GBS, 4),
                          "GFLOP_s": round(2 * nnz * N_COLS / (spmm_ms * 1e-3) / 1e9, 2)},
         },
+        "leaf_spread": spread,
         "autotune": {
             "spmv_ms": {json.dumps(c, sort_keys=True): round(t, 4) for c, t in res_v},
             "spmm_ms": {json.dumps(c, sort_keys=True): round(t, 4) for c, t in res_m},

@@ -15,6 +15,10 @@
    values uniform[0, 1]; c uniform[0, 1]; rank-32 factors N(0, 1); a second
    value array on the same pattern for the inner product.
 5. Schedule-selection corpus (see ``corpus``).
+6. The paper's weak-scaling SpMV matrix at one GPU's share: banded CSR
+   20,000,000 x 20,000,000 whose row i holds columns max(0, i - 17) ..
+   min(n - 1, i + 17) (35 per interior row, 699,999,694 nonzeros, about
+   700 million); FP64 values and vector uniform[-1, 1].
 
 ``scale`` shrinks every size by the same factor for tests (the degree cap
 shrinks with it), keeping the structure: power-law rows, ragged tails, and
@@ -119,3 +123,24 @@ def config4(device="cpu", scale=1.0, R=32, kind_vals="unit", with_dense=True):
         out["C"] = gen.values(gen.key_for(4, 5), J * R, dev, "normal").reshape(J, R)
         out["D"] = gen.values(gen.key_for(4, 6), K * R, dev, "normal").reshape(K, R)
     return out
+
+
+def banded(device="cpu", n=20_000_000, half_width=17, kind="sym"):
+    """Banded CSR (config 6): row i holds columns max(0, i - w) ..
+    min(n - 1, i + w); values and the vector in float64."""
+    dev = _dev(device)
+    w = int(half_width)
+    i = torch.arange(n, dtype=torch.int64, device=dev)
+    lo = torch.clamp(i - w, min=0)
+    deg = torch.clamp(i + w, max=n - 1) - lo + 1
+    del i
+    pos = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    pos[1:] = torch.cumsum(deg, 0)
+    nnz = int(pos[-1].item())
+    row = torch.repeat_interleave(torch.arange(n, dtype=torch.int64, device=dev), deg)
+    crd = (lo[row] + torch.arange(nnz, dtype=torch.int64, device=dev) - pos[:-1][row])
+    crd = crd.to(torch.int32)
+    del row, lo, deg
+    vals = gen.values(gen.key_for(6, 1), nnz, dev, kind)
+    x = gen.values(gen.key_for(6, 2), n, dev, kind)
+    return dict(n=n, m=n, pos=pos.to(torch.int32), crd=crd, vals=vals, x=x, half_width=w)
