@@ -21,6 +21,8 @@ Besides the headline line it reports, from the same run:
    256 MB MALL (cold);
  - variants: FP64 SpMV/SpMM and BF16 SpMM (FP32 accumulation) with the same
    schedules, and the row / non-zero / merge schedules compared;
+ - ops: every other leaf at its full workload, and the SpMV of the paper's
+   weak-scaling study at one GPU's share (banded, 7e8 nonzeros, FP64);
  - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10]
@@ -106,6 +108,32 @@ def _rate(ms, nbytes, flops):
             "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
 
 
+def measure_banded(dev, spl, tuning, torch):
+    """One GPU's share of the paper's weak-scaling SpMV: the banded CSR of
+    20,000,000 rows with 35 nonzeros per interior row (699,999,694), FP64
+    values and vector; the fastest of a few schedules, median of 10 calls."""
+    from workloads import configs
+    print("[bench] generating the 7e8-nonzero banded matrix", file=sys.stderr, flush=True)
+    c = configs.banded(device=dev)
+    n = c["n"]
+    nnz = int(c["crd"].numel())
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    x = c["x"]
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    cands = ([dict(kind="row", lanes_per_row=L) for L in (8, 16, 32, 64)] +
+             [dict(kind="merge", tile=2048, items_per_lane=8),
+              dict(kind="merge", tile=8192, items_per_lane=8),
+              dict(kind="nnz", tile=4096, items_per_lane=8)])
+    best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
+    ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
+    out = _rate(ms, 4 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)
+    out.update(schedule=best, n=n, nnz=nnz,
+               schedules_ms={json.dumps(c, sort_keys=True): round(t, 4) for c, t in res})
+    del B, c, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
@@ -189,9 +217,13 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     a = torch.empty(1, dtype=torch.float64, device=dev)
     ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
     res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
+    del B64, C64, B32, c4
+    torch.cuda.empty_cache()
+    res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
         "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",
+        "banded": "CSR 20000000^2, rows i-17..i+17 (699999694 nnz), FP64",
     }
     return res
 

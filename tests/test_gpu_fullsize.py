@@ -131,3 +131,25 @@ def test_config4_csf_ops():
     ref, S = oracle.inner((h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals"].cpu().numpy()),
                           (h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals2"].cpu().numpy()))
     assert abs(float(a.item()) - ref) <= 1e-12 * S
+
+
+def test_banded_weak_scaling_share_spmv_sampled():
+    # one GPU's share of the paper's weak-scaling SpMV: 7e8 nonzeros, FP64
+    spl, _ = _spl()
+    c = configs.banded(device="cuda")
+    n = c["n"]
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    rs = np.random.RandomState(6)
+    rows = np.unique(np.concatenate([rs.randint(0, n, 400), [0, 1, 16, 17, 18, n - 18, n - 17,
+                                                              n - 2, n - 1]]))
+    r = torch.as_tensor(rows, device="cuda")
+    p0, p1 = c["pos"][r].long(), c["pos"][r + 1].long()
+    cnt = (p1 - p0).cpu().numpy()
+    idx = torch.cat([torch.arange(a, b, device="cuda") for a, b in zip(p0.tolist(), p1.tolist())])
+    spos = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    ref, S = oracle.spmv(spos, c["crd"][idx].cpu().numpy(), c["vals"][idx].cpu().numpy(),
+                         c["x"].cpu().numpy())
+    for sc in (dict(kind="default"), dict(kind="row", lanes_per_row=32),
+               dict(kind="nnz", tile=4096, items_per_lane=8)):
+        y = spl.spmv(B, c["x"], sched=spl.schedule(**sc))
+        assert_close(host64(y[r]), ref, S, 1e-12, f"banded spmv {sc}")
