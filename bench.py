@@ -217,7 +217,14 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     a = torch.empty(1, dtype=torch.float64, device=dev)
     ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
     res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
-    del B64, C64, B32, c4
+    # the co-iteration of two patterns: the same coordinates in other arrays,
+    # so every fiber is looked up and every position matched
+    Cg = spl.CSF(c4["pos1"].clone(), c4["crd1"].clone(), c4["pos2"].clone(), c4["crd2"].clone(),
+                 c4["vals2"], (I, J, Kd))
+    ms = tuning.time_call(lambda: spl.inner(B64, Cg, a), reps=10, warmup=3)
+    res["inner_general_f64"] = _rate(ms, 2 * (4 * (I + 1) + 4 * F + 4 * (F + 1) + 12 * nnz),
+                                     2 * nnz)
+    del B64, C64, B32, Cg, c4
     torch.cuda.empty_cache()
     res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
     res["workloads"] = {

@@ -263,17 +263,22 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * and writes 4 consecutive rank columns with one vector access when R,
  * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
  * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 8
- * (otherwise one column per lane); 1 = one column per lane.  The workspace query returns the
- * one-column-per-lane size, enough for both. */
+ * (otherwise one column per lane); 1 = one column per lane.  The workspace
+ * query returns the one-column-per-lane size, enough for both. */
 spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                       const spl_dense *D, spl_dense *A, const spl_schedule *sched,
                       void *workspace, size_t workspace_bytes, spl_stream stream);
 
-/* Inner product  a = B(i,j,k) * C(i,j,k)  (every index summed; order-2
- * operands are accepted too).  B and C must share one pattern: identical
- * pos and crd pointers (else SPL_ERR_UNSUPPORTED).  Values both F64 or both
- * F32, summed in F64 with a fixed reduction order; the result is one double
- * written to `out` (device). */
+/* Inner product  a = B(i,j,k) * C(i,j,k)  (every index summed, the TIN
+ * statement with no free index, Sec. II-A; order-2 operands are accepted
+ * too).  When B and C share one pattern (identical pos and crd pointers and
+ * equal nnz) the aligned values are multiplied; otherwise the two patterns
+ * are co-iterated (Sec. IV-C): each coordinate of B's last-but-one level is
+ * looked up in C's segment of the same parent, and for CSF the two sorted
+ * last-level lists are merged, so only coordinates both store contribute.
+ * Same dimensions required.  Values both F64 or both F32, summed in F64
+ * with a fixed reduction order; the result is one double written to `out`
+ * (device).  The workspace depends on B only. */
 spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C, double *out,
                      const spl_schedule *sched, void *workspace, size_t workspace_bytes,
                      spl_stream stream);

@@ -446,6 +446,14 @@ size_t sddmm_ws(const spl_sparse *B, const Plan &p) {
 
 constexpr int64_t kInnerParts = 2048;
 
+// Workspace of an inner product with B as the first operand: the shared-
+// pattern partials or the general co-iteration's per-workgroup partials.
+size_t inner_ws(const spl_sparse *B) {
+    const int64_t units = B->order == 2 ? B->nnz : B->nfibers;
+    return align_up(static_cast<size_t>(std::max(kInnerParts, spl::inner_general_parts(units))) *
+                    sizeof(double));
+}
+
 size_t spadd3_ws(int64_t n) {
     return align_up(static_cast<size_t>(spl::spadd3_scan_tiles(n)) * 8) + align_up(8);
 }
@@ -785,7 +793,9 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
         return SPL_OK;
     case SPL_OP_INNER:
         if (!B) return fail(ctx, SPL_ERR_ARG, "sparse operand is NULL");
-        *bytes = align_up(kInnerParts * sizeof(double));
+        if (B->order != 2 && B->order != 3) return fail(ctx, SPL_ERR_FORMAT, "order must be 2 or 3");
+        SPL_CHECK(check_sparse(ctx, B, B->order));
+        *bytes = inner_ws(B);
         return SPL_OK;
     case SPL_OP_SPADD3:
         SPL_CHECK(check_sparse(ctx, B, 2));
@@ -1097,23 +1107,32 @@ spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
     if (order != 2 && order != 3) return fail(ctx, SPL_ERR_FORMAT, "order must be 2 or 3");
     SPL_CHECK(check_sparse(ctx, B, order));
     SPL_CHECK(check_sparse(ctx, C, order));
-    if (!same_dims(B, C) || B->nnz != C->nnz)
-        return fail(ctx, SPL_ERR_SHAPE, "operands differ in shape or nnz");
+    if (!same_dims(B, C))
+        return fail(ctx, SPL_ERR_SHAPE, "operands differ in shape");
     if (B->vtype != C->vtype || B->vtype == SPL_BF16)
         return fail(ctx, SPL_ERR_DTYPE, "inner product needs both F64 or both F32 values");
+    bool shared = B->nnz == C->nnz;
     for (int l = 1; l < order; ++l)
-        if (B->pos[l] != C->pos[l] || B->crd[l] != C->crd[l])
-            return fail(ctx, SPL_ERR_UNSUPPORTED,
-                        "operands must share one pattern (identical pos/crd arrays)");
+        shared = shared && B->pos[l] == C->pos[l] && B->crd[l] == C->crd[l];
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr;
-    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
-                            align_up(kInnerParts * sizeof(double)), &ws));
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, inner_ws(B), &ws));
     LeafTimer tm(ctx, SPL_OP_INNER, s);
-    SPL_HIP(spl::launch_inner(B->vtype, B->nnz, B->vals, C->vals, static_cast<double *>(ws),
-                              kInnerParts, out, s),
-            "inner product launch");
+    if (shared) {
+        // one pattern (the same pos/crd arrays): the aligned values' dot product
+        SPL_HIP(spl::launch_inner(B->vtype, B->nnz, B->vals, C->vals, static_cast<double *>(ws),
+                                  kInnerParts, out, s),
+                "inner product launch");
+    } else {
+        const bool o3 = order == 3;
+        SPL_HIP(spl::launch_inner_general(
+                    B->vtype, order, B->dims[0], o3 ? B->nfibers : B->nnz, B->pos[1], B->crd[1],
+                    o3 ? B->pos[2] : nullptr, o3 ? B->crd[2] : nullptr, B->vals, C->pos[1],
+                    C->crd[1], o3 ? C->pos[2] : nullptr, o3 ? C->crd[2] : nullptr, C->vals,
+                    static_cast<double *>(ws), out, s),
+                "inner product launch");
+    }
     tm.stop();
     return SPL_OK;
     SPL_GUARD_END

@@ -472,6 +472,11 @@ hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t str
                                             ceil_div(t.ntiles, stride), carry, A, lda, s);
 }
 
+hipError_t launch_inner_final(int64_t nparts, const double *part, double *out, hipStream_t s) {
+    k_inner_final<<<1, kBlock, 0, s>>>(nparts, part, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_inner(int vtype, int64_t nnz, const void *a, const void *b, double *part,
                         int64_t nparts, double *out, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(nparts));

@@ -131,6 +131,11 @@ def test_config4_csf_ops():
     ref, S = oracle.inner((h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals"].cpu().numpy()),
                           (h["pos1"], h["crd1"], h["pos2"], h["crd2"], c["vals2"].cpu().numpy()))
     assert abs(float(a.item()) - ref) <= 1e-12 * S
+    # the co-iteration path on the same coordinates held in other arrays
+    Cg = spl.CSF(c["pos1"].clone(), c["crd1"].clone(), c["pos2"].clone(), c["crd2"].clone(),
+                 c["vals2"], (I, J, K))
+    ag = spl.inner(B64, Cg)
+    assert abs(float(ag.item()) - ref) <= 1e-12 * S
 
 
 def test_banded_weak_scaling_share_spmv_sampled():

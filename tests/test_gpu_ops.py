@@ -132,10 +132,11 @@ def test_inner_product(dtype):
         assert abs(float(a.item()) - had) <= 1e-12 * S
         a2 = spl.inner(B, C)
         assert torch.equal(a, a2)  # fixed reduction order
-    # distinct pattern arrays are refused
-    other = spl.CSF(B.pos1.clone(), B.crd1, B.pos2, B.crd2, C.vals, B.shape)
-    with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
-        spl.inner(B, other)
+    # the same pattern in other arrays takes the co-iteration path: same sum
+    other = spl.CSF(B.pos1.clone(), B.crd1.clone(), B.pos2.clone(), B.crd2.clone(), C.vals,
+                    B.shape)
+    assert_close(host64(spl.inner(B, other)), np.array([ref]), np.array([S]), 1e-12,
+                 "inner, same pattern in copies")
 
 
 def _c3(scale=0.002, K=128, kind="sym"):
@@ -265,3 +266,81 @@ def test_spadd3_long_rows_span_output_windows():
     assert np.array_equal(A.pos.cpu().numpy(), rpos)
     assert np.array_equal(A.crd.cpu().numpy(), rcrd)
     assert np.array_equal(host64(A.vals), rvals)
+
+
+def _perturbed_csf(c, rs, drop=0.3, extra=0.3):
+    """A second CSF pattern: c's coordinates with a fraction dropped and
+    random ones added (sorted, distinct), new values."""
+    I, J, K = c["I"], c["J"], c["K"]
+    p1, c1, p2, c2 = c["pos1"], c["crd1"], c["pos2"], c["crd2"]
+    coords = set()
+    for i in range(I):
+        for f in range(p1[i], p1[i + 1]):
+            for p in range(p2[f], p2[f + 1]):
+                if rs.rand() >= drop:
+                    coords.add((i, int(c1[f]), int(c2[p])))
+    nnz = len(c2)
+    for _ in range(int(extra * nnz)):
+        coords.add((int(rs.randint(I)), int(rs.randint(J)), int(rs.randint(K))))
+    coords = sorted(coords)
+    crd1, pos2, crd2 = [], [0], []
+    last = None
+    counts = np.zeros(I, dtype=np.int64)
+    for (i, j, k) in coords:
+        if (i, j) != last:
+            crd1.append(j)
+            pos2.append(pos2[-1])
+            counts[i] += 1
+            last = (i, j)
+        crd2.append(k)
+        pos2[-1] += 1
+    pos1 = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    vals = rs.uniform(-1, 1, len(crd2))
+    return (pos1, np.array(crd1, np.int32), np.array(pos2, np.int32), np.array(crd2, np.int32),
+            vals)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inner_product_general_patterns(dtype):
+    spl = _spl()
+    rs = np.random.RandomState(21)
+    for c in (_tiny_csf(9), _numpy(configs.config4(scale=0.0005, with_dense=False))):
+        B = _csf(spl, c, dtype)
+        hp = _perturbed_csf(c, rs)
+        Cc = spl.CSF(_t(hp[0]), _t(hp[1]), _t(hp[2]), _t(hp[3]), _t(hp[4], torch.float64).to(dtype),
+                     B.shape)
+        bh = (c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals))
+        ch = (hp[0], hp[1], hp[2], hp[3], host64(Cc.vals))
+        ref, S = oracle.inner(bh, ch)
+        assert_close(host64(spl.inner(B, Cc)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "inner general CSF")
+        assert_close(host64(spl.inner(Cc, B)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "inner general CSF, swapped")
+    # CSR: the three SpAdd3 operands share 30% of their rows
+    c3 = configs.config3(scale=0.002, with_dense=False)
+    shape = (c3["n"], c3["m"])
+    mats = [_csr_dev(spl, c3[k], shape, dtype) for k in "BC"]
+    hs = [(c3[k]["pos"].numpy(), c3[k]["crd"].numpy(), None, None, host64(m.vals))
+          for k, m in zip("BC", mats)]
+    ref, S = oracle.inner(hs[0], hs[1])
+    assert_close(host64(spl.inner(mats[0], mats[1])), np.array([ref]), np.array([S]),
+                 RTOL[dtype], "inner general CSR")
+    # disjoint patterns give exactly 0; an empty operand too
+    rs2 = np.random.RandomState(4)
+    p, cc, v = tiny.csr(rs2, 50, 40, 0.2)
+    A1 = spl.CSR(_t(p), _t(cc), _t(v, dtype), (50, 40))
+    pe, ce = [0], []
+    for i in range(50):
+        row = sorted(set(int(x) for x in cc[p[i]:p[i + 1]] if x % 2 == 0))
+        ce.extend(row)
+        pe.append(len(ce))
+    po, co = [0], []
+    for i in range(50):
+        row = sorted(set(int(x) for x in cc[p[i]:p[i + 1]] if x % 2 == 1))
+        co.extend(row)
+        po.append(len(co))
+    E = spl.CSR(_t(pe), _t(ce), _t(np.ones(len(ce)), dtype), (50, 40))
+    O = spl.CSR(_t(po), _t(co), _t(np.ones(len(co)), dtype), (50, 40))
+    assert float(spl.inner(E, O).item()) == 0.0
+    Z = spl.CSR(_t(np.zeros(51)), _t(np.zeros(0)), _t(np.zeros(0), dtype), (50, 40))
+    assert float(spl.inner(Z, A1).item()) == 0.0 and float(spl.inner(A1, Z).item()) == 0.0
