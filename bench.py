@@ -123,7 +123,9 @@ def measure_banded(dev, spl, tuning, torch):
     cands = ([dict(kind="row", lanes_per_row=L) for L in (8, 16, 32, 64)] +
              [dict(kind="merge", tile=2048, items_per_lane=8),
               dict(kind="merge", tile=8192, items_per_lane=8),
-              dict(kind="nnz", tile=4096, items_per_lane=8)])
+              dict(kind="merge", tile=4096, items_per_lane=4),
+              dict(kind="nnz", tile=4096, items_per_lane=8)] +
+             [dict(kind="merge", tile=T, items_per_lane=8, variant=1) for T in (8192, 16384, 32768)])
     best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
     ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
     out = _rate(ms, 4 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)

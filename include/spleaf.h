@@ -220,7 +220,11 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
  * B CSR n x m; c vector m; a vector n.  dtypes: vals, c, a all F64, or all
  * F32 (products and sums in F64, rounded once per output).  Schedules: ROW,
  * NNZ, MERGE (default MERGE), and SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE
- * (resolved first to one of the candidates, which synchronizes on
+ * (below).  sched->variant (MERGE only): 0 = a workgroup walks chunks of
+ * 256 * items_per_lane merged items; 1 = each wave walks chunks of
+ * 64 * items_per_lane on its own (default tile 4 chunks per wave).  Kinds
+ * SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE are resolved first to one of the
+ * candidates (which synchronizes on
  * `stream`; a caller workspace must then fit every candidate, as
  * spl_workspace_query returns for those kinds). */
 spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
@@ -248,7 +252,8 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
  * (A.pos = B.pos[1], A.crd = B.crd[1]) and only its values are written,
  * one per fiber, into the vector A of length B->nfibers.  dtypes: vals, c, A
  * all F64, or all F32 (F64 sums).  The schedule applies to the fiber level
- * (fibers play the role of SpMV rows): ROW, NNZ or MERGE (default). */
+ * (fibers play the role of SpMV rows): ROW, NNZ or MERGE (default), with
+ * sched->variant as for spl_spmv. */
 spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
                      spl_dense *A, const spl_schedule *sched, void *workspace,
                      size_t workspace_bytes, spl_stream stream);

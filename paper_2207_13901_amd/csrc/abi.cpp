@@ -143,6 +143,10 @@ int lanes_for_mean(double mean) {
     return L;
 }
 
+// Merged items per SpMV leaf chunk: a workgroup's (variant 0) or a wave's
+// (variant 1) lanes times the items each walks.
+int64_t spmv_chunk(const Plan &p) { return (p.variant == 1 ? 64 : 256) * p.items; }
+
 spl_status resolve_spmv(spl_context *ctx, const spl_sparse *B, const spl_schedule *s, Plan &p) {
     spl_schedule d{};
     if (!s) s = &d;
@@ -155,7 +159,13 @@ spl_status resolve_spmv(spl_context *ctx, const spl_sparse *B, const spl_schedul
     if (!pow2_in(p.lanes, 1, 64)) return fail(ctx, SPL_ERR_ARG, "lanes_per_row must be 1..64, power of 2");
     p.items = s->items_per_lane ? s->items_per_lane : 8;
     if (p.items != 4 && p.items != 8) return fail(ctx, SPL_ERR_ARG, "SpMV items_per_lane must be 4 or 8");
-    p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 256 / p.lanes : 256 * p.items);
+    if (s->variant != 0 && s->variant != 1)
+        return fail(ctx, SPL_ERR_ARG, "SpMV variant must be 0 (workgroup) or 1 (wave)");
+    if (s->variant == 1 && p.kind != SPL_MERGE)
+        return fail(ctx, SPL_ERR_ARG, "SpMV variant 1 needs the MERGE schedule");
+    p.variant = s->variant;
+    p.tile = s->tile ? s->tile
+                     : (p.kind == SPL_ROW ? 256 / p.lanes : (p.variant ? 4 : 1) * spmv_chunk(p));
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
     return SPL_OK;
 }
@@ -315,7 +325,6 @@ Pieces pieces_for(const Plan &p, int64_t rows, int64_t nnz, int64_t chunk) {
     return q;
 }
 
-int64_t spmv_chunk(const Plan &p) { return 256 * p.items; }
 // Merged items per leaf chunk: lane groups of one workgroup times the items
 // each group walks.
 int64_t spmm_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.items; }
@@ -939,7 +948,7 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     LeafTimer tm(ctx, SPL_OP_SPMV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, n, B->pos[1], B->crd[1], B->vals, c->data,
                                    a->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
-                                   static_cast<double *>(cv.carry), s),
+                                   /*wave=*/p.variant == 1, static_cast<double *>(cv.carry), s),
             "SpMV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
@@ -1036,7 +1045,7 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
     LeafTimer tm(ctx, SPL_OP_SPTTV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, F, v.pos[1], v.crd[1], B->vals, c->data,
                                    A->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
-                                   static_cast<double *>(cv.carry), s),
+                                   /*wave=*/p.variant == 1, static_cast<double *>(cv.carry), s),
             "SpTTV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, F, cv.tiles, q.stride,
