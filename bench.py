@@ -136,6 +136,46 @@ def measure_banded(dev, spl, tuning, torch):
     return out
 
 
+def measure_ddc(dev, spl, tuning, torch):
+    """SpTTV and SpMTTKRP (FP32) on the (Dense, Dense, Compressed) tensor
+    shaped like the paper's "patents": 46 x 239,172 x 239,172 with 1e8
+    values over 11,001,912 fibers; autotuned schedule, median of 10 calls.
+    The MTTKRP time includes writing out the Dense middle level."""
+    from workloads import configs
+    print("[bench] generating the (Dense, Dense, Compressed) tensor", file=sys.stderr, flush=True)
+    c = configs.ddc(device=dev)
+    I, J, Kd = c["I"], c["J"], c["K"]
+    F = I * J
+    nnz = int(c["crd2"].numel())
+    R = c["C"].shape[1]
+    B = spl.DDC(c["pos2"], c["crd2"], c["vals"].to(torch.float32), (I, J, Kd))
+    cv = c["c"].to(torch.float32)
+    A = torch.empty(F, dtype=torch.float32, device=dev)
+    out = {}
+    best, _ = tuning.search(lambda s: (lambda: spl.spttv(B, cv, A, sched=s)),
+                            tuning.SPMV_CANDIDATES, reps=5)
+    st = spl.schedule(**best)
+    ms = tuning.time_call(lambda: spl.spttv(B, cv, A, sched=st), reps=10, warmup=3)
+    out["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+    out["spttv_f32"]["schedule"] = best
+    del A
+    C = c["C"].to(torch.float32)
+    D = c["D"].to(torch.float32)
+    M = torch.empty(I, R, dtype=torch.float32, device=dev)
+    ws = spl.workspace(spl.N.OP_MTTKRP, B, R)
+    best, _ = tuning.search(lambda s: (lambda: spl.mttkrp(B, C, D, M, sched=s)),
+                            tuning.MTTKRP_CANDIDATES, reps=3)
+    sk = spl.schedule(**best)
+    ms = tuning.time_call(lambda: spl.mttkrp(B, C, D, M, sched=sk, ws=ws), reps=10, warmup=3)
+    nbytes = 4 * (F + 1) + 8 * nnz + 4 * (J + Kd) * R + 4 * I * R
+    out["mttkrp_f32"] = _rate(ms, nbytes, 2 * R * (nnz + F))
+    out["mttkrp_f32"]["schedule"] = best
+    out["workload"] = f"(Dense, Dense, Compressed) {I}x{J}x{Kd}, {nnz} nnz, {F} fibers, R={R}"
+    del B, C, D, M, c, cv, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
@@ -229,6 +269,7 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None):
     del B64, C64, B32, Cg, c4
     torch.cuda.empty_cache()
     res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
+    res["ddc"] = measure_ddc(dev, spl, tuning, torch)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
         "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",

@@ -94,10 +94,14 @@ typedef struct spl_context spl_context;
 typedef void *spl_stream; /* a hipStream_t; NULL is the null stream */
 
 /* A sparse operand (Sec. III-B).  level[0] must be SPL_DENSE and the others
- * SPL_COMPRESSED; pos[l]/crd[l] are used for Compressed levels l >= 1 and
- * ignored for level 0.  nnz must equal pos[order-1][last] (the caller knows
- * it; the library does not read it back).  For CSF, F = pos[1][dims[0]]
- * fibers is passed in nfibers. */
+ * SPL_COMPRESSED, except that a 3-tensor's middle level may be SPL_DENSE
+ * too: (Dense, Dense, Compressed), the format of the paper's "patents"
+ * tensor (Sec. VI).  pos[l]/crd[l] are used for Compressed levels l >= 1 and
+ * ignored for Dense ones.  nnz must equal pos[order-1][last] (the caller
+ * knows it; the library does not read it back).  For CSF, F = pos[1][dims[0]]
+ * fibers is passed in nfibers; for (Dense, Dense, Compressed), nfibers must
+ * be dims[0] * dims[1] and fiber f = i * dims[1] + j owns positions
+ * [pos[2][f], pos[2][f+1]). */
 typedef struct spl_sparse {
     int32_t order;          /* 2 (CSR) or 3 (CSF)                              */
     int32_t vtype;          /* spl_dtype of vals                               */
@@ -253,7 +257,9 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
  * one per fiber, into the vector A of length B->nfibers.  dtypes: vals, c, A
  * all F64, or all F32 (F64 sums).  The schedule applies to the fiber level
  * (fibers play the role of SpMV rows): ROW, NNZ or MERGE (default), with
- * sched->variant as for spl_spmv. */
+ * sched->variant as for spl_spmv.  For a (Dense, Dense, Compressed) B the
+ * fibers are all I * J pairs (i,j), so A is the dense I x J matrix, row-major
+ * (an empty fiber gives 0). */
 spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
                      spl_dense *A, const spl_schedule *sched, void *workspace,
                      size_t workspace_bytes, spl_stream stream);
@@ -269,7 +275,10 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
  * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 8
  * (otherwise one column per lane); 1 = one column per lane.  The workspace
- * query returns the one-column-per-lane size, enough for both. */
+ * query returns the one-column-per-lane size, enough for both.  A
+ * (Dense, Dense, Compressed) B is accepted: its middle level's pos/crd
+ * (I + 1 and I * J int32) are written into the workspace, counted by the
+ * query, and the leaf runs as for CSF. */
 spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                       const spl_dense *D, spl_dense *A, const spl_schedule *sched,
                       void *workspace, size_t workspace_bytes, spl_stream stream);
@@ -283,7 +292,10 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
  * last-level lists are merged, so only coordinates both store contribute.
  * Same dimensions required.  Values both F64 or both F32, summed in F64
  * with a fixed reduction order; the result is one double written to `out`
- * (device).  The workspace depends on B only. */
+ * (device).  Either operand may be (Dense, Dense, Compressed): unless the
+ * two share one pattern, a Dense middle level is written out as pos/crd in
+ * the workspace first.  The workspace query covers B; when C's middle level
+ * is Dense, a caller workspace must also hold the query for C. */
 spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C, double *out,
                      const spl_schedule *sched, void *workspace, size_t workspace_bytes,
                      spl_stream stream);

@@ -51,6 +51,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.orc_spadd3_symbolic.restype = _i64
         lib.orc_inner.restype = ctypes.c_double
+        lib.orc_inner3.restype = ctypes.c_double
         for name in ("orc_row_split", "orc_nnz_split", "orc_merge_split",
                      "orc_csf_split", "orc_rows_finished_at"):
             getattr(lib, name).restype = _i64
@@ -217,6 +218,61 @@ def inner(B, C):
     a = lib.orc_inner(_i64(I), idx(B[0]), idx(B[1]), idx(B[2]), idx(B[3]), bvp,
                       idx(C[0]), idx(C[1]), idx(C[2]), idx(C[3]), cvp,
                       ctypes.byref(S))
+    return float(a), float(S.value)
+
+
+def spttv_ddc(I, J, pos2, crd2, vals, c):
+    """SpTTV of a (Dense, Dense, Compressed) tensor: A(i,j) for every (i,j),
+    returned flattened row-major (I*J values) with S."""
+    lib = _load()
+    p2, p2p = _i32(pos2)
+    c2, c2p = _i32(crd2)
+    v, vp = _f64(vals)
+    cc, ccp = _f64(c)
+    A, Ap = _out(I * J)
+    S, Sp = _out(I * J)
+    lib.orc_spttv_ddc(_i64(I), _i64(J), p2p, c2p, vp, ccp, Ap, Sp)
+    return A, S
+
+
+def mttkrp_ddc(I, J, pos2, crd2, vals, C, D, rows=None):
+    """SpMTTKRP of a (Dense, Dense, Compressed) tensor; returns (A, S)."""
+    lib = _load()
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    D = np.ascontiguousarray(np.asarray(D, dtype=np.float64))
+    R = C.shape[1]
+    p2, p2p = _i32(pos2)
+    c2, c2p = _i32(crd2)
+    v, vp = _f64(vals)
+    Cc, Cp = _f64(C)
+    Dd, Dp = _f64(D)
+    r, rp, nr = _rows(rows)
+    cnt = nr if rows is not None else I
+    A, Ap = _out((cnt, R))
+    S, Sp = _out((cnt, R))
+    lib.orc_mttkrp_ddc(_i64(I), _i64(J), _i64(R), p2p, c2p, vp, Cp, _i64(R), Dp, _i64(R),
+                       rp, _i64(nr), Ap, _i64(R), Sp)
+    return A, S
+
+
+def inner3(I, J, B, C):
+    """Inner product of two I x J x K tensors given as (pos1, crd1, pos2, crd2,
+    vals); pos1 = crd1 = None marks a Dense middle level.  Returns (a, S)."""
+    lib = _load()
+    keep = []
+
+    def idx(a):
+        if a is None:
+            return None
+        arr, p = _i32(a)
+        keep.append(arr)
+        return p
+
+    bv, bvp = _f64(B[4])
+    cv, cvp = _f64(C[4])
+    S = ctypes.c_double(0.0)
+    a = lib.orc_inner3(_i64(I), _i64(J), idx(B[0]), idx(B[1]), idx(B[2]), idx(B[3]), bvp,
+                       idx(C[0]), idx(C[1]), idx(C[2]), idx(C[3]), cvp, ctypes.byref(S))
     return float(a), float(S.value)
 
 

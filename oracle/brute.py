@@ -37,6 +37,21 @@ def dense_csf(pos1, crd1, pos2, crd2, vals, shape):
     return T, M
 
 
+def dense_ddc(pos2, crd2, vals, shape):
+    """Densify a (Dense, Dense, Compressed) 3-tensor (fiber f = i*J + j) and
+    its mask."""
+    T = np.zeros(shape, dtype=np.float64)
+    M = np.zeros(shape, dtype=bool)
+    I, J, _ = shape
+    for i in range(I):
+        for j in range(J):
+            f = i * J + j
+            for p in range(pos2[f], pos2[f + 1]):
+                T[i, j, crd2[p]] += float(vals[p])
+                M[i, j, crd2[p]] = True
+    return T, M
+
+
 def spmv(Bd, c):
     return np.einsum("ij,j->i", Bd, c)
 

@@ -307,6 +307,108 @@ double orc_inner(int64_t I,
 }
 
 /* ------------------------------------------------------------------------ */
+/* (Dense, Dense, Compressed) 3-tensors (Sec. III-B; the format the paper    */
+/* uses for its "patents" tensor, Sec. VI).  A Dense level stores nothing:   */
+/* under slice i every coordinate j in [0, J) is present, at position        */
+/* i*J + j of the middle level.  Only the last level has pos2/crd2, indexed  */
+/* by that position.  The loops below are the statements' loops over this    */
+/* coordinate tree, with the Dense middle level iterated as a full range.    */
+/* ------------------------------------------------------------------------ */
+
+/* SpTTV A(i,j) = B(i,j,k) * c(k): one output per (i,j), A row-major I x J. */
+void orc_spttv_ddc(int64_t I, int64_t J, const int32_t *pos2, const int32_t *crd2,
+                   const double *vals, const double *c, double *A, double *A_S)
+{
+    for (int64_t i = 0; i < I; ++i) {
+        for (int64_t j = 0; j < J; ++j) {
+            int64_t f = i * J + j;
+            ld sum = 0.0L, mag = 0.0L;
+            for (int64_t p = pos2[f]; p < pos2[f + 1]; ++p) {
+                ld term = (ld)vals[p] * (ld)c[crd2[p]];
+                sum += term;
+                mag += ld_abs(term);
+            }
+            A[f] = (double)sum;
+            if (A_S) A_S[f] = (double)mag;
+        }
+    }
+}
+
+/* SpMTTKRP A(i,l) = B(i,j,k) * C(j,l) * D(k,l) with B in (Dense, Dense,    */
+/* Compressed); rows != NULL evaluates only those slices (compacted).        */
+void orc_mttkrp_ddc(int64_t I, int64_t J, int64_t R, const int32_t *pos2,
+                    const int32_t *crd2, const double *vals, const double *C,
+                    int64_t ldc, const double *D, int64_t ldd, const int64_t *rows,
+                    int64_t nrows, double *A, int64_t lda, double *S)
+{
+    int64_t count = rows ? nrows : I;
+    ld *acc = (ld *)malloc(sizeof(ld) * (size_t)(R > 0 ? R : 1));
+    ld *mag = (ld *)malloc(sizeof(ld) * (size_t)(R > 0 ? R : 1));
+    for (int64_t r = 0; r < count; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        for (int64_t l = 0; l < R; ++l) { acc[l] = 0.0L; mag[l] = 0.0L; }
+        for (int64_t j = 0; j < J; ++j) {
+            int64_t f = i * J + j;
+            for (int64_t p = pos2[f]; p < pos2[f + 1]; ++p) {
+                int64_t k = crd2[p];
+                for (int64_t l = 0; l < R; ++l) {
+                    ld term = (ld)vals[p] * (ld)C[j * ldc + l] * (ld)D[k * ldd + l];
+                    acc[l] += term;
+                    mag[l] += ld_abs(term);
+                }
+            }
+        }
+        for (int64_t l = 0; l < R; ++l) {
+            A[r * lda + l] = (double)acc[l];
+            if (S) S[r * lda + l] = (double)mag[l];
+        }
+    }
+    free(acc);
+    free(mag);
+}
+
+/* Inner product of two 3-tensors of shape I x J x K whose middle levels may */
+/* each be Dense (pos1 == NULL) or Compressed.  Co-iteration of the middle   */
+/* level (Sec. IV-C): Dense with Dense visits every j; a Compressed side is  */
+/* iterated and the Dense side located at i*J + j; two Compressed sides are  */
+/* intersected.  The last levels are then intersected as for CSF.           */
+double orc_inner3(int64_t I, int64_t J,
+                  const int32_t *Bpos1, const int32_t *Bcrd1,
+                  const int32_t *Bpos2, const int32_t *Bcrd2, const double *Bv,
+                  const int32_t *Cpos1, const int32_t *Ccrd1,
+                  const int32_t *Cpos2, const int32_t *Ccrd2, const double *Cv,
+                  double *S)
+{
+    ld sum = 0.0L, mag = 0.0L;
+    for (int64_t i = 0; i < I; ++i) {
+        if (!Bpos1 && !Cpos1) {
+            for (int64_t j = 0; j < J; ++j) {
+                int64_t f = i * J + j;
+                intersect_level(Bpos2[f], Bpos2[f + 1], Cpos2[f], Cpos2[f + 1], Bcrd2, Ccrd2,
+                                1, NULL, NULL, NULL, NULL, Bv, Cv, &sum, &mag);
+            }
+        } else if (!Bpos1) {
+            for (int64_t g = Cpos1[i]; g < Cpos1[i + 1]; ++g) {
+                int64_t f = i * J + Ccrd1[g];
+                intersect_level(Bpos2[f], Bpos2[f + 1], Cpos2[g], Cpos2[g + 1], Bcrd2, Ccrd2,
+                                1, NULL, NULL, NULL, NULL, Bv, Cv, &sum, &mag);
+            }
+        } else if (!Cpos1) {
+            for (int64_t f = Bpos1[i]; f < Bpos1[i + 1]; ++f) {
+                int64_t g = i * J + Bcrd1[f];
+                intersect_level(Bpos2[f], Bpos2[f + 1], Cpos2[g], Cpos2[g + 1], Bcrd2, Ccrd2,
+                                1, NULL, NULL, NULL, NULL, Bv, Cv, &sum, &mag);
+            }
+        } else {
+            intersect_level(Bpos1[i], Bpos1[i + 1], Cpos1[i], Cpos1[i + 1], Bcrd1, Ccrd1, 0,
+                            Bpos2, Cpos2, Bcrd2, Ccrd2, Bv, Cv, &sum, &mag);
+        }
+    }
+    if (S) *S = (double)mag;
+    return (double)sum;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Partitions of a Compressed level (Sec. III-A, IV-B, Table I).             */
 /*                                                                           */
 /* A tile of a leaf kernel is described by the pair (row, position) at which */

@@ -5,9 +5,9 @@ only marshal torch tensors (device memory) and the current HIP stream into
 the C structs; every step of every operation runs in the library's HIP
 kernels.  The names follow the C entry points without the ``spl_`` prefix.
 
-Sparse operands are ``CSR`` (Dense, Compressed) and ``CSF`` (Dense,
-Compressed, Compressed) objects holding int32 pos/crd and a value tensor,
-all on the same GPU.
+Sparse operands are ``CSR`` (Dense, Compressed), ``CSF`` (Dense,
+Compressed, Compressed) and ``DDC`` (Dense, Dense, Compressed) objects
+holding int32 pos/crd and a value tensor, all on the same GPU.
 """
 from __future__ import annotations
 
@@ -22,7 +22,7 @@ from . import _native as N
 from ._native import SpleafError
 
 __all__ = [
-    "CSR", "CSF", "Context", "schedule", "spmv", "spmm", "tile_bounds",
+    "CSR", "CSF", "DDC", "Context", "schedule", "spmv", "spmm", "tile_bounds",
     "validate", "op_parse", "op_tin", "workspace_query", "workspace", "SpleafError",
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
@@ -97,6 +97,41 @@ class CSF:
 
     def with_vals(self, vals: torch.Tensor) -> "CSF":
         return CSF(self.pos1, self.crd1, self.pos2, self.crd2, vals, self.shape)
+
+    @property
+    def nfibers(self) -> int:
+        return self.crd1.numel()
+
+
+@dataclass
+class DDC:
+    """(Dense, Dense, Compressed) 3-tensor I x J x K: fiber f = i*J + j owns
+    positions [pos2[f], pos2[f+1]); pos2 int32[I*J+1], crd2 int32[nnz] (k per
+    value), vals[nnz]."""
+    pos2: torch.Tensor
+    crd2: torch.Tensor
+    vals: torch.Tensor
+    shape: tuple
+
+    def struct(self) -> N.SplSparse:
+        s = N.SplSparse()
+        s.order = 3
+        s.vtype = _dtype_code(self.vals)
+        for d in range(3):
+            s.dims[d] = self.shape[d]
+        s.level[0], s.level[1], s.level[2] = N.DENSE, N.DENSE, N.COMPRESSED
+        s.pos[2], s.crd[2] = _ptr(self.pos2), _ptr(self.crd2)
+        s.vals = _ptr(self.vals)
+        s.nnz = self.crd2.numel()
+        s.nfibers = self.shape[0] * self.shape[1]
+        return s
+
+    def with_vals(self, vals: torch.Tensor) -> "DDC":
+        return DDC(self.pos2, self.crd2, vals, self.shape)
+
+    @property
+    def nfibers(self) -> int:
+        return self.shape[0] * self.shape[1]
 
 
 def _dense(t: torch.Tensor) -> N.SplDense:
@@ -232,7 +267,7 @@ def tile_bounds(B, sched, ctx: Optional[Context] = None):
     dev = (B.pos if isinstance(B, CSR) else B.pos2).device
     ctx, stream = _ctx_stream(B.vals, ctx)
     s = B.struct()
-    rows = B.shape[0] if isinstance(B, CSR) else B.crd1.numel()
+    rows = B.shape[0] if isinstance(B, CSR) else B.nfibers
     items = rows + s.nnz
     cap = items // max(sched.tile, 1) + 3
     tr = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -300,10 +335,11 @@ def _sched_ptr(sched):
 def spttv(B: CSF, c: torch.Tensor, A: Optional[torch.Tensor] = None, sched=None,
           ctx: Optional[Context] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """A(i,j) = B(i,j,k) * c(k): returns the values of A, one per fiber of B
-    (A's pos/crd are B's pos1/crd1)."""
+    (for CSF, A's pos/crd are B's pos1/crd1; for DDC, A is dense I x J,
+    flattened row-major)."""
     ctx, stream = _ctx_stream(B.vals, ctx)
     if A is None:
-        A = torch.empty(B.crd1.numel(), dtype=B.vals.dtype, device=B.vals.device)
+        A = torch.empty(B.nfibers, dtype=B.vals.dtype, device=B.vals.device)
     s = B.struct()
     ws, nb = _workspace(N.OP_SPTTV, B, 1, sched, ctx, B.vals.device, ws)
     ctx.check(ctx.lib.spl_spttv(ctx.h, ctypes.byref(s), ctypes.byref(_dense(c)),
@@ -334,6 +370,11 @@ def inner(B, C, out: Optional[torch.Tensor] = None, ctx: Optional[Context] = Non
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=B.vals.device)
     sb, sc = B.struct(), C.struct()
+    if ws is None and isinstance(C, DDC):
+        # a Dense middle level of C is written out in the workspace as well
+        nbytes = (workspace_query(N.OP_INNER, B, 1, None, ctx) +
+                  workspace_query(N.OP_INNER, C, 1, None, ctx))
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=B.vals.device)
     ws, nb = _workspace(N.OP_INNER, B, 1, None, ctx, B.vals.device, ws)
     ctx.check(ctx.lib.spl_inner(ctx.h, ctypes.byref(sb), ctypes.byref(sc), out.data_ptr(),
                                 None, _ptr(ws), nb, stream), "spl_inner")

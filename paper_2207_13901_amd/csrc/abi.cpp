@@ -87,9 +87,13 @@ spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order) {
                     B->order);
     if (B->level[0] != SPL_DENSE)
         return fail(ctx, SPL_ERR_FORMAT, "level 0 must be Dense");
+    // a 3-tensor's middle level may be Dense: (Dense, Dense, Compressed)
+    const bool dmid = order == 3 && B->level[1] == SPL_DENSE;
     for (int l = 1; l < order; ++l)
-        if (B->level[l] != SPL_COMPRESSED)
-            return fail(ctx, SPL_ERR_FORMAT, "level %d must be Compressed", l);
+        if (B->level[l] != SPL_COMPRESSED && !(l == 1 && dmid))
+            return fail(ctx, SPL_ERR_FORMAT, order == 3 && l == 1
+                                                 ? "level 1 must be Dense or Compressed"
+                                                 : "level %d must be Compressed", l);
     if (!valid_dtype(B->vtype)) return fail(ctx, SPL_ERR_DTYPE, "unknown value dtype %d", B->vtype);
     for (int l = 0; l < order; ++l)
         if (B->dims[l] < 0 || B->dims[l] > kIndexMax)
@@ -100,7 +104,9 @@ spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order) {
     if (order == 3 && (B->nfibers < 0 || B->nfibers > kIndexMax))
         return fail(ctx, SPL_ERR_SHAPE, "nfibers = %lld out of range",
                     static_cast<long long>(B->nfibers));
-    for (int l = 1; l < order; ++l) {
+    if (dmid && B->nfibers != B->dims[0] * B->dims[1])
+        return fail(ctx, SPL_ERR_SHAPE, "a Dense middle level holds dims[0] * dims[1] fibers");
+    for (int l = dmid ? 2 : 1; l < order; ++l) {
         if (!B->pos[l]) return fail(ctx, SPL_ERR_ARG, "pos[%d] is NULL", l);
         const int64_t children = (l == order - 1) ? B->nnz : B->nfibers;
         if (children > 0 && !B->crd[l]) return fail(ctx, SPL_ERR_ARG, "crd[%d] is NULL", l);
@@ -375,6 +381,36 @@ spl_sparse fiber_view(const spl_sparse *B) {
     v.crd[1] = B->crd[2];
     v.level[2] = SPL_DENSE;
     return v;
+}
+
+// A (Dense, Dense, Compressed) 3-tensor: the middle level is Dense, so slice
+// i holds fibers [i J, (i + 1) J) and fiber f has coordinate j = f mod J
+// (Sec. III-B, Table I).  The MTTKRP and inner-product leaves walk a
+// Compressed middle level; for a Dense one, its pos/crd are written into the
+// call's workspace first (I + 1 and I J int32) and the leaves run unchanged.
+bool dense_middle(const spl_sparse *B) { return B->order == 3 && B->level[1] == SPL_DENSE; }
+
+size_t dense_middle_ws(const spl_sparse *B) {
+    if (!dense_middle(B)) return 0;
+    return align_up(static_cast<size_t>(B->dims[0] + 1) * 4) +
+           align_up(static_cast<size_t>(B->nfibers) * 4);
+}
+
+// A Compressed-middle view of B, whose middle level is expanded at `ws`
+// (advanced past it) when it is Dense.
+spl_status expand_middle(spl_context *ctx, const spl_sparse *B, char *&ws, spl_sparse &v,
+                         hipStream_t s) {
+    v = *B;
+    if (!dense_middle(B)) return SPL_OK;
+    int32_t *pos1 = reinterpret_cast<int32_t *>(ws);
+    ws += align_up(static_cast<size_t>(B->dims[0] + 1) * 4);
+    int32_t *crd1 = reinterpret_cast<int32_t *>(ws);
+    ws += align_up(static_cast<size_t>(B->nfibers) * 4);
+    SPL_HIP(spl::launch_dense_level(B->dims[0], B->dims[1], pos1, crd1, s), "dense level launch");
+    v.level[1] = SPL_COMPRESSED;
+    v.pos[1] = pos1;
+    v.crd[1] = crd1;
+    return SPL_OK;
 }
 
 spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Plan &p) {
@@ -793,7 +829,7 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
     case SPL_OP_MTTKRP:
         SPL_CHECK(check_sparse(ctx, B, 3));
         SPL_CHECK(resolve_mttkrp(ctx, ncols, sched, p));
-        *bytes = mttkrp_ws(B, ncols, p);
+        *bytes = dense_middle_ws(B) + mttkrp_ws(B, ncols, p);
         return SPL_OK;
     case SPL_OP_SDDMM:
         SPL_CHECK(check_sparse(ctx, B, 2));
@@ -804,7 +840,7 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
         if (!B) return fail(ctx, SPL_ERR_ARG, "sparse operand is NULL");
         if (B->order != 2 && B->order != 3) return fail(ctx, SPL_ERR_FORMAT, "order must be 2 or 3");
         SPL_CHECK(check_sparse(ctx, B, B->order));
-        *bytes = inner_ws(B);
+        *bytes = dense_middle_ws(B) + inner_ws(B);
         return SPL_OK;
     case SPL_OP_SPADD3:
         SPL_CHECK(check_sparse(ctx, B, 2));
@@ -852,7 +888,7 @@ spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream
     SPL_CHECK(check_sparse(ctx, B, B->order == 3 ? 3 : 2));
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int l = 1; l < B->order; ++l) {
+    for (int l = dense_middle(B) ? 2 : 1; l < B->order; ++l) {
         const int64_t parents = l == 1 ? B->dims[0] : B->nfibers;
         const int64_t children = l == B->order - 1 ? B->nnz : B->nfibers;
         const int64_t extent = B->dims[l];
@@ -1081,9 +1117,14 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     // the workspace query assumed one column per lane: the larger size
     p.vec = mttkrp_vec(p, C, D, A);
     void *ws = nullptr;
-    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, mttkrp_ws(B, R, p), &ws));
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
+                            dense_middle_ws(B) + mttkrp_ws(B, R, p), &ws));
+    char *wp = static_cast<char *>(ws);
+    spl_sparse bv;
+    SPL_CHECK(expand_middle(ctx, B, wp, bv, s));
+    B = &bv;
     const Pieces q = mttkrp_pieces(B, p);
-    Carved cv = carve(ws, q.count);
+    Carved cv = carve(wp, q.count);
     if (p.kind == SPL_NNZ)
         SPL_HIP(spl::launch_csf_nnz_bounds(I, B->pos[1], B->nfibers, B->pos[2], B->nnz, p.tile,
                                            cv.tiles, s),
@@ -1120,13 +1161,26 @@ spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
         return fail(ctx, SPL_ERR_SHAPE, "operands differ in shape");
     if (B->vtype != C->vtype || B->vtype == SPL_BF16)
         return fail(ctx, SPL_ERR_DTYPE, "inner product needs both F64 or both F32 values");
-    bool shared = B->nnz == C->nnz;
+    // one pattern: the same arrays at every stored level (a Dense middle level
+    // is the same for both once the shapes agree)
+    bool shared = B->nnz == C->nnz && dense_middle(B) == dense_middle(C);
     for (int l = 1; l < order; ++l)
-        shared = shared && B->pos[l] == C->pos[l] && B->crd[l] == C->crd[l];
+        if (!(l == 1 && dense_middle(B)))
+            shared = shared && B->pos[l] == C->pos[l] && B->crd[l] == C->crd[l];
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr;
-    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, inner_ws(B), &ws));
+    const size_t expand = shared ? 0 : dense_middle_ws(B) + dense_middle_ws(C);
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, expand + inner_ws(B), &ws));
+    char *wp = static_cast<char *>(ws);
+    spl_sparse bx, cx;
+    if (!shared) {
+        SPL_CHECK(expand_middle(ctx, B, wp, bx, s));
+        SPL_CHECK(expand_middle(ctx, C, wp, cx, s));
+        B = &bx;
+        C = &cx;
+    }
+    ws = wp;
     LeafTimer tm(ctx, SPL_OP_INNER, s);
     if (shared) {
         // one pattern (the same pos/crd arrays): the aligned values' dot product

@@ -61,6 +61,9 @@ hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, in
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 
 // ---- csf.hip -------------------------------------------------------------
+// pos (I + 1 entries) and crd (I * J entries) of a Dense level of extent J
+// under I parents, written out as a Compressed level would store them.
+hipError_t launch_dense_level(int64_t I, int64_t J, int32_t *pos, int32_t *crd, hipStream_t s);
 // Fiber-aligned non-zero split of a CSF tensor: t.row = slice, t.pos = fiber.
 hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
                                  int64_t nnz, int64_t T, const Tiles &t, hipStream_t s);

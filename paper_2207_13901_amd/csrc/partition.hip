@@ -15,6 +15,8 @@
 //    (number of rows finished at position t*T, t*T); tile 0 starts at (0, 0)
 //    so that leading empty rows belong to it.
 //  - Merge split: tile t starts at the point t*M of the merged sequence.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -67,7 +69,30 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const int
     tpos[t] = static_cast<int32_t>(d - i);
 }
 
+// The pos and crd arrays a Dense level of extent J under I parents would
+// have if it were stored compressed (the Dense level functions, Sec. III-B
+// and Table I): parent i owns positions [i J, (i + 1) J) and position f holds
+// coordinate f mod J.
+__global__ __launch_bounds__(kBlock) void k_dense_level(int64_t I, int64_t J,
+                                                        int32_t *__restrict__ pos,
+                                                        int32_t *__restrict__ crd) {
+    const int64_t F = I * J;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t f = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; f < F; f += stride)
+        crd[f] = static_cast<int32_t>(f % J);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i <= I; i += stride)
+        pos[i] = static_cast<int32_t>(i * J);
+}
+
 }  // namespace
+
+hipError_t launch_dense_level(int64_t I, int64_t J, int32_t *pos, int32_t *crd, hipStream_t s) {
+    const int64_t F = I * J;
+    const int64_t work = (F > I + 1 ? F : I + 1);
+    const int64_t blocks = std::min<int64_t>(ceil_div(work, kBlock), 8192);
+    k_dense_level<<<dim3(static_cast<unsigned>(blocks)), kBlock, 0, s>>>(I, J, pos, crd);
+    return hipGetLastError();
+}
 
 int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size) {
     int64_t items = kind == SPL_ROW ? rows : kind == SPL_NNZ ? nnz : rows + nnz;

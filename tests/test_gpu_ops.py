@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+from paper_2207_13901_amd import _native as N
 from tests import tiny
 from tests.gpu_util import RTOL, assert_close, dev, host64, need_gpu
 from workloads import configs
@@ -345,3 +346,106 @@ def test_inner_product_general_patterns(dtype):
     assert float(spl.inner(E, O).item()) == 0.0
     Z = spl.CSR(_t(np.zeros(51)), _t(np.zeros(0)), _t(np.zeros(0), dtype), (50, 40))
     assert float(spl.inner(Z, A1).item()) == 0.0 and float(spl.inner(A1, Z).item()) == 0.0
+
+
+# ------------------------------------------- (Dense, Dense, Compressed) -----
+
+def _ddc(spl, c, dtype, vals_key="vals"):
+    return spl.DDC(_t(c["pos2"]), _t(c["crd2"]), _t(c[vals_key], torch.float64).to(dtype),
+                   (c["I"], c["J"], c["K"]))
+
+
+def _tiny_ddc(seed, I=7, J=13, K=300, density=0.03, kind="float"):
+    rs = np.random.RandomState(seed)
+    p2, c2, v = tiny.ddc(rs, I, J, K, density, kind=kind)
+    return dict(I=I, J=J, K=K, pos2=p2, crd2=c2, vals=v, vals2=rs.uniform(-1, 1, len(v)))
+
+
+def _ddc_cases():
+    # the patents-shaped workload scaled down (46 x 478 x 478, 2e5 values,
+    # about 9 per fiber), a tiny one with many empty fibers, a single fiber,
+    # and one with no values at all
+    return [_numpy(configs.ddc(scale=0.002, R=32)), _tiny_ddc(1), _tiny_ddc(2, I=1, J=1),
+            _tiny_ddc(3, I=3, J=4, density=0.0)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ddc_spttv(dtype):
+    spl = _spl()
+    for c in _ddc_cases():
+        B = _ddc(spl, c, dtype)
+        cv = _t(np.linspace(-1, 1, c["K"]), torch.float64).to(dtype)
+        ref, S = oracle.spttv_ddc(c["I"], c["J"], c["pos2"], c["crd2"], host64(B.vals),
+                                  host64(cv))
+        for sc in TTV_SCHEDULES:
+            A = spl.spttv(B, cv, sched=spl.schedule(**sc))
+            assert A.numel() == c["I"] * c["J"]
+            assert_close(host64(A), ref, S, RTOL[dtype], f"ddc spttv {sc} I={c['I']}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_ddc_mttkrp(dtype):
+    spl = _spl()
+    rs = np.random.RandomState(11)
+    for c in _ddc_cases():
+        R = 32 if "C" in c else 5
+        Cn = c.get("C", rs.normal(size=(c["J"], R)))
+        Dn = c.get("D", rs.normal(size=(c["K"], R)))
+        B = _ddc(spl, c, dtype)
+        C = _t(Cn, torch.float64).to(torch.float32).to(dtype)
+        D = _t(Dn, torch.float64).to(torch.float32).to(dtype)
+        ref, S = oracle.mttkrp_ddc(c["I"], c["J"], c["pos2"], c["crd2"], host64(B.vals),
+                                   host64(C), host64(D))
+        for sc in MTTKRP_SCHEDULES:
+            A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+            assert_close(host64(A), ref, S, 1e-5, f"ddc mttkrp {dtype} {sc} I={c['I']}")
+        # a caller workspace sized by the query (it holds the expanded level)
+        ws = spl.workspace(N.OP_MTTKRP, B, R)
+        A = spl.mttkrp(B, C, D, ws=ws)
+        assert_close(host64(A), ref, S, 1e-5, "ddc mttkrp, caller workspace")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ddc_inner_product(dtype):
+    spl = _spl()
+    for c in _ddc_cases()[:3]:
+        I, J = c["I"], c["J"]
+        B = _ddc(spl, c, dtype)
+        bh = (None, None, c["pos2"], c["crd2"], host64(B.vals))
+        # one pattern: aligned values
+        B2 = _ddc(spl, c, dtype, "vals2")
+        ref, S = oracle.inner3(I, J, bh, (None, None, c["pos2"], c["crd2"], host64(B2.vals)))
+        assert_close(host64(spl.inner(B, B2)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "ddc inner, one pattern")
+        # another (Dense, Dense, Compressed) pattern, and the same one as CSF
+        o = _tiny_ddc(40, I=I, J=J, K=c["K"], density=0.02 if c["K"] > 100 else 0.3)
+        O = _ddc(spl, o, dtype)
+        oh = (None, None, o["pos2"], o["crd2"], host64(O.vals))
+        ref, S = oracle.inner3(I, J, bh, oh)
+        assert_close(host64(spl.inner(B, O)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "ddc inner, two patterns")
+        q1, d1, q2, d2 = tiny.ddc_to_csf(o["pos2"], o["crd2"], I, J)
+        Of = spl.CSF(_t(q1), _t(d1), _t(q2), _t(d2), O.vals, B.shape)
+        for x, y, hx, hy in ((B, Of, bh, (q1, d1, q2, d2, host64(O.vals))),
+                             (Of, B, (q1, d1, q2, d2, host64(O.vals)), bh)):
+            ref, S = oracle.inner3(I, J, hx, hy)
+            assert_close(host64(spl.inner(x, y)), np.array([ref]), np.array([S]), RTOL[dtype],
+                         "ddc inner with CSF")
+
+
+def test_ddc_errors():
+    spl = _spl()
+    import ctypes
+    c = _tiny_ddc(5)
+    B = _ddc(spl, c, torch.float64)
+    ctx = spl.Context.get()
+    s = B.struct()
+    s.nfibers = c["I"] * c["J"] + 1
+    assert ctx.lib.spl_validate(ctx.h, ctypes.byref(s), None) == N.ERR_SHAPE
+    s = B.struct()
+    s.level[2] = N.DENSE
+    assert ctx.lib.spl_validate(ctx.h, ctypes.byref(s), None) == N.ERR_FORMAT
+    spl.validate(B)  # well-formed: only the Compressed level is checked
+    bad = spl.DDC(B.pos2, torch.flip(B.crd2, [0]).contiguous(), B.vals, B.shape)
+    with pytest.raises(spl.SpleafError, match="INVALID"):
+        spl.validate(bad)

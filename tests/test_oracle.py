@@ -255,6 +255,62 @@ def test_inner_order2():
     close(np.array([a]), np.array([brute.inner(Bd, Cd)]), np.array([S]), 1e-14)
 
 
+# ------------------------------------- (Dense, Dense, Compressed) tensors --
+
+@pytest.mark.parametrize("seed", range(12))
+def test_ddc_kernels_match_einsum(seed):
+    rs = np.random.RandomState(900 + seed)
+    I, J, K, R = rs.randint(1, 6), rs.randint(1, 6), rs.randint(1, 7), rs.randint(1, 5)
+    p2, c2, v = tiny.ddc(rs, I, J, K, rs.uniform(0.05, 0.9))
+    Td, _ = brute.dense_ddc(p2, c2, v, (I, J, K))
+    c = rs.uniform(-1, 1, K)
+    A, S = oracle.spttv_ddc(I, J, p2, c2, v, c)
+    close(A, brute.spttv(Td, c).reshape(-1), S, 1e-14)
+    Cf, Df = rs.uniform(-1, 1, (J, R)), rs.uniform(-1, 1, (K, R))
+    M, SM = oracle.mttkrp_ddc(I, J, p2, c2, v, Cf, Df)
+    close(M, brute.mttkrp(Td, Cf, Df), SM, 1e-14)
+    rows = np.array([I - 1, 0], dtype=np.int64)
+    Mr, _ = oracle.mttkrp_ddc(I, J, p2, c2, v, Cf, Df, rows=rows)
+    assert np.array_equal(Mr, M[rows])
+    # inner products: DDC with DDC, DDC with CSF (both orders), CSF with CSF
+    q2, d2, w = tiny.ddc(rs, I, J, K, rs.uniform(0.05, 0.9))
+    Ud, _ = brute.dense_ddc(q2, d2, w, (I, J, K))
+    ref = brute.inner(Td, Ud)
+    a, Sa = oracle.inner3(I, J, (None, None, p2, c2, v), (None, None, q2, d2, w))
+    close(np.array([a]), np.array([ref]), np.array([Sa]), 1e-14)
+    e1, f1, e2, f2 = tiny.ddc_to_csf(q2, d2, I, J)
+    a, Sa = oracle.inner3(I, J, (None, None, p2, c2, v), (e1, f1, e2, f2, w))
+    close(np.array([a]), np.array([ref]), np.array([Sa]), 1e-14)
+    a, Sa = oracle.inner3(I, J, (e1, f1, e2, f2, w), (None, None, p2, c2, v))
+    close(np.array([a]), np.array([ref]), np.array([Sa]), 1e-14)
+    b1, g1, b2, g2 = tiny.ddc_to_csf(p2, c2, I, J)
+    a, Sa = oracle.inner3(I, J, (b1, g1, b2, g2, v), (e1, f1, e2, f2, w))
+    close(np.array([a]), np.array([ref]), np.array([Sa]), 1e-14)
+
+
+def test_ddc_reduces_to_csr_and_csf():
+    rs = np.random.RandomState(31)
+    I, J, K = 4, 5, 9
+    p2, c2, v = tiny.ddc(rs, I, J, K, 0.35, kind="int")
+    # integer values: every sum is exact, so the results match bit for bit
+    c = rs.randint(-3, 4, K).astype(np.float64)
+    A, _ = oracle.spttv_ddc(I, J, p2, c2, v, c)
+    # as a CSR matrix of I*J rows (the Dense levels fused), SpTTV is SpMV
+    y, _ = oracle.spmv(p2, c2, v, c)
+    assert np.array_equal(A, y)
+    # as CSF with the empty fibers dropped: the CSF oracle on the fibers kept
+    q1, d1, q2, d2 = tiny.ddc_to_csf(p2, c2, I, J)
+    Af, _ = oracle.spttv(q1, q2, d2, v, c)
+    fib = np.repeat(np.arange(I), np.diff(q1)) * J + d1
+    assert np.array_equal(A[fib], Af)
+    empty = np.setdiff1d(np.arange(I * J), fib)
+    assert np.all(A[empty] == 0.0)
+    Cf, Df = rs.randint(-2, 3, (J, 3)).astype(float), rs.randint(-2, 3, (K, 3)).astype(float)
+    M, _ = oracle.mttkrp_ddc(I, J, p2, c2, v, Cf, Df)
+    Mf, _ = oracle.mttkrp(q1, d1, q2, d2, v, Cf, Df)
+    assert np.array_equal(M, Mf)
+
+
 # ------------------------------------------------------- partition math ----
 
 def image(pos, src_rows):

@@ -68,3 +68,14 @@ def test_banded_pattern():
     for i in (0, 1, w, w + 1, 500, n - w - 1, n - 1):
         assert list(crd[pos[i]:pos[i + 1]]) == list(range(max(0, i - w), min(n - 1, i + w) + 1))
     assert c["vals"].dtype == torch.float64 and c["x"].numel() == n
+
+
+def test_ddc_tensor_exact_nonzeros_and_layout():
+    c = configs.ddc(scale=0.001, with_dense=False)
+    I, J, K = c["I"], c["J"], c["K"]
+    pos2, crd2 = c["pos2"].numpy(), c["crd2"].numpy()
+    assert pos2.size == I * J + 1 and pos2[0] == 0
+    assert pos2[-1] == int(round(1e8 * 0.001)) == crd2.size
+    _rows_distinct_sorted(pos2, crd2, K)
+    per_slice = pos2[np.arange(1, I + 1) * J] - pos2[np.arange(I) * J]
+    assert per_slice.max() - per_slice.min() <= 1

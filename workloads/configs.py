@@ -19,6 +19,12 @@
    20,000,000 x 20,000,000 whose row i holds columns max(0, i - 17) ..
    min(n - 1, i + 17) (35 per interior row, 699,999,694 nonzeros, about
    700 million); FP64 values and vector uniform[-1, 1].
+7. (Dense, Dense, Compressed) 3-tensor shaped like the paper's "patents"
+   tensor (a short dense first mode, two long modes): 46 x 239,172 x 239,172
+   with exactly 1e8 nonzeros split evenly over the 46 slices, distinct
+   uniform (j, k) pairs per slice (so every one of the 11,001,912 fibers
+   holds about 9 values); values and c uniform[0, 1]; rank-32 factors
+   N(0, 1).  Synthetic: only the shape and format stand in for the dataset.
 
 ``scale`` shrinks every size by the same factor for tests (the degree cap
 shrinks with it), keeping the structure: power-law rows, ragged tails, and
@@ -144,3 +150,31 @@ def banded(device="cpu", n=20_000_000, half_width=17, kind="sym"):
     vals = gen.values(gen.key_for(6, 1), nnz, dev, kind)
     x = gen.values(gen.key_for(6, 2), n, dev, kind)
     return dict(n=n, m=n, pos=pos.to(torch.int32), crd=crd, vals=vals, x=x, half_width=w)
+
+
+def ddc(device="cpu", scale=1.0, R=32, I=46, with_dense=True):
+    """Config 7: (Dense, Dense, Compressed) tensor; pos2 indexes all I*J
+    fibers (fiber f = i*J + j)."""
+    dev = _dev(device)
+    J = K = max(1, int(round(239_172 * scale)))
+    target = int(round(1e8 * scale))
+    sizes = np.full(I, target // I, dtype=np.int64)
+    sizes[: target % I] += 1
+    pos1, crd1, pos2c, crd2 = gen.csf_from_slice_sizes(sizes, J, K, gen.key_for(7, 1), dev)
+    # scatter the compressed fibers' lengths to their (i, j) slots
+    fib_i = torch.repeat_interleave(torch.arange(I, device=dev), pos1[1:] - pos1[:-1])
+    slot = fib_i.to(torch.int64) * J + crd1.to(torch.int64)
+    count = torch.zeros(I * J, dtype=torch.int64, device=dev)
+    count[slot] = (pos2c[1:] - pos2c[:-1]).to(torch.int64)
+    pos2 = torch.zeros(I * J + 1, dtype=torch.int64, device=dev)
+    pos2[1:] = torch.cumsum(count, 0)
+    del count, slot, fib_i, pos2c
+    nnz = int(crd2.numel())
+    out = dict(I=I, J=J, K=K, pos2=pos2.to(torch.int32), crd2=crd2,
+               vals=gen.values(gen.key_for(7, 2), nnz, dev, "unit"),
+               vals2=gen.values(gen.key_for(7, 3), nnz, dev, "unit"),
+               c=gen.values(gen.key_for(7, 4), K, dev, "unit"))
+    if with_dense:
+        out["C"] = gen.values(gen.key_for(7, 5), J * R, dev, "normal").reshape(J, R)
+        out["D"] = gen.values(gen.key_for(7, 6), K * R, dev, "normal").reshape(K, R)
+    return out
