@@ -165,10 +165,10 @@ spl_status resolve_spmv(spl_context *ctx, const spl_sparse *B, const spl_schedul
     if (!pow2_in(p.lanes, 1, 64)) return fail(ctx, SPL_ERR_ARG, "lanes_per_row must be 1..64, power of 2");
     p.items = s->items_per_lane ? s->items_per_lane : 8;
     if (p.items != 4 && p.items != 8) return fail(ctx, SPL_ERR_ARG, "SpMV items_per_lane must be 4 or 8");
-    if (s->variant != 0 && s->variant != 1)
-        return fail(ctx, SPL_ERR_ARG, "SpMV variant must be 0 (workgroup) or 1 (wave)");
-    if (s->variant == 1 && p.kind != SPL_MERGE)
-        return fail(ctx, SPL_ERR_ARG, "SpMV variant 1 needs the MERGE schedule");
+    if (s->variant < 0 || s->variant > 2)
+        return fail(ctx, SPL_ERR_ARG, "SpMV variant must be 0 (workgroup), 1 (wave) or 2 (flags)");
+    if (s->variant != 0 && p.kind != SPL_MERGE)
+        return fail(ctx, SPL_ERR_ARG, "SpMV variants 1 and 2 need the MERGE schedule");
     p.variant = s->variant;
     p.tile = s->tile ? s->tile
                      : (p.kind == SPL_ROW ? 256 / p.lanes : (p.variant ? 4 : 1) * spmv_chunk(p));
@@ -984,7 +984,7 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     LeafTimer tm(ctx, SPL_OP_SPMV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, n, B->pos[1], B->crd[1], B->vals, c->data,
                                    a->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
-                                   /*wave=*/p.variant == 1, static_cast<double *>(cv.carry), s),
+                                   p.variant, static_cast<double *>(cv.carry), s),
             "SpMV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
@@ -1081,7 +1081,7 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
     LeafTimer tm(ctx, SPL_OP_SPTTV, s);
     SPL_HIP(spl::launch_spmv_tiles(B->vtype, p.items, F, v.pos[1], v.crd[1], B->vals, c->data,
                                    A->data, cv.tiles, q.stride, /*exact_chunks=*/p.kind == SPL_MERGE,
-                                   /*wave=*/p.variant == 1, static_cast<double *>(cv.carry), s),
+                                   p.variant, static_cast<double *>(cv.carry), s),
             "SpTTV tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmv_fixup(B->vtype, F, cv.tiles, q.stride,

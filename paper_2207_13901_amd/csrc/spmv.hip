@@ -33,6 +33,8 @@
 //
 // Accumulation is in double for both double and float data (a float output
 // is rounded once from the double sum, then once more if a carry lands on it).
+#include <type_traits>
+
 #include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"
@@ -372,7 +374,185 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pipe(
     if (tid == 0) carry[blockIdx.x] = open;
 }
 
-// Order the LDS accesses of the lanes of one wave (no workgroup barrier).
+// A raw buffer descriptor over `bytes` bytes at `base` (data format word of
+// gfx9): lane offsets at or past `bytes` read 0 without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
+}
+constexpr int kNtAux = 2;  // non-temporal cache policy for streamed arrays
+
+template <typename V>
+__device__ __forceinline__ V chunk_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float chunk_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNtAux));
+}
+template <>
+__device__ __forceinline__ double chunk_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNtAux));
+}
+
+// Exclusive sum of `v` over the lanes of the workgroup before this one.
+// The adds are conditioned on the shuffled source lane (data, not the lane
+// index alone), so the shuffles stay outside any lane mask.
+__device__ __forceinline__ int block_exclusive_sum(int v, int *s_wave_total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    int inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int u = __shfl_up(inc, off);
+        const int src = __shfl_up(lane, off);
+        if (src < lane) inc += u;
+    }
+    if (lane == kWave - 1) s_wave_total[wave] = inc;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wave_total[w];
+    return before + inc - v;
+}
+
+// Merge-split leaf with row-end flags (schedule variant 2).  The same
+// pieces, pipeline and carries as k_spmv_pipe, but instead of the row ends
+// the staging writes a flag byte at each row end's place in the chunk's
+// merged sequence (row end r of the chunk sits at r + pos[r+1] - chunk
+// start).  A lane reads its ITEMS flags with one LDS load, counts them, and
+// an exclusive sum over the workgroup gives the rows finished before its
+// first item; its walk then needs no search and no row-end reads: a flagged
+// item finishes the open row, any other adds the next product.
+template <typename V, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_spmv_flag(
+    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
+    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
+    int64_t stride, double *__restrict__ carry) {
+    static_assert(ITEMS == 4 || ITEMS == 8, "flags are read as one 4- or 8-byte word");
+    using Flags = typename std::conditional<ITEMS == 4, uint32_t, uint64_t>::type;
+    constexpr int kChunk = kBlock * ITEMS;
+    __shared__ double s_prod[2][kChunk + 1];  // + a spare slot for the walk
+    // byte k: merged item k is a row end; byte kChunk is a spare
+    __shared__ __align__(8) uint8_t s_flag[2][kChunk + 8];
+    __shared__ int s_wave_total[kBlock / kWave];
+    __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
+    __shared__ double s_last_val[kBlock / kWave];
+    __shared__ double s_open;
+
+    const int tid = threadIdx.x;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
+    auto bound_i = [&](int64_t c) { return static_cast<int64_t>(trow[c < pend ? c : pend]); };
+    auto bound_p = [&](int64_t c) { return static_cast<int64_t>(tpos[c < pend ? c : pend]); };
+    auto flag_word = [&](int buf) -> Flags & { return reinterpret_cast<Flags *>(s_flag[buf])[tid]; };
+
+    // Loads are not predicated per lane: each goes through a buffer
+    // descriptor over the chunk's own rows or positions, so a lane past its
+    // end reads 0 (the hardware range check) and the stash sends its flag
+    // and product to the spare slots.  The lane offsets do not depend on the
+    // chunk.
+    int e2[ITEMS], k2[ITEMS], e1[ITEMS];
+    V v2[ITEMS], v1[ITEMS], x1[ITEMS];
+    auto load = [&](int64_t bi, int64_t bp, int nr, int np) {
+        const auto rp = chunk_rsrc(pos + bi + 1, 4 * nr);
+        const auto rc = chunk_rsrc(crd + bp, 4 * np);
+        const auto rv = chunk_rsrc(vals + bp, static_cast<int>(sizeof(V)) * np);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t k = static_cast<uint32_t>(tid + j * kBlock);
+            e2[j] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rp, k * 4, 0, 0));
+            k2[j] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rc, k * 4, 0, kNtAux));
+            v2[j] = chunk_load<V>(rv, k * static_cast<uint32_t>(sizeof(V)));
+        }
+    };
+    auto gather = [&](int np) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            e1[j] = e2[j];
+            v1[j] = v2[j];
+        }
+        if (np > 0) {  // lanes past the positions gather x[0]
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) x1[j] = x[k2[j]];
+        }
+    };
+    // chunk starting at position bp into buffer `buf`: flags and products
+    auto stash = [&](int buf, int nr, int np, int64_t bp) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            s_flag[buf][k < nr ? k + static_cast<int>(e1[j] - bp) : kChunk] = 1;
+            s_prod[buf][k < np ? k : kChunk] = to_f64(v1[j]) * to_f64(x1[j]);
+        }
+    };
+
+    flag_word(0) = 0;
+    flag_word(1) = 0;
+    int64_t bi0 = bound_i(p0), bp0 = bound_p(p0);
+    int64_t bi1 = bound_i(p0 + 1), bp1 = bound_p(p0 + 1);
+    int64_t bi2 = bound_i(p0 + 2), bp2 = bound_p(p0 + 2);
+    int64_t bi3 = bound_i(p0 + 3), bp3 = bound_p(p0 + 3);
+    load(bi0, bp0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0));
+    gather(static_cast<int>(bp1 - bp0));
+    __syncthreads();  // flags cleared
+    stash(0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0), bp0);
+    load(bi1, bp1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1));
+    gather(static_cast<int>(bp2 - bp1));
+    load(bi2, bp2, static_cast<int>(bi3 - bi2), static_cast<int>(bp3 - bp2));
+
+    double open = 0.0;
+    int buf = 0;
+    for (int64_t c = p0; c < pend; ++c) {
+        const int64_t bi4 = bound_i(c + 4), bp4 = bound_p(c + 4);
+        __syncthreads();  // buffer `buf` holds chunk c
+        const int nr = static_cast<int>(bi1 - bi0), np = static_cast<int>(bp1 - bp0);
+        const int total = nr + np;
+        const int d0 = min(tid * ITEMS, total);
+        const int steps = min(d0 + ITEMS, total) - d0;
+        const Flags fl = flag_word(buf);
+        flag_word(buf) = 0;  // cleared for the chunk after next
+        int a = block_exclusive_sum(static_cast<int>(__builtin_popcountll(fl)), s_wave_total);
+        int b = d0 - a;
+        const double *sprod = s_prod[buf];
+        double *s_out = s_prod[buf ^ 1];  // finished rows until written out
+        double acc = tid == 0 ? open : 0.0;
+#pragma unroll
+        for (int st = 0; st < ITEMS; ++st) {
+            const bool fin = (fl >> (8 * st)) & 1;
+            const bool add = !fin && st < steps;
+            const double pv = sprod[b];  // b <= np; slot kChunk is the spare
+            s_out[fin ? a : kChunk] = acc;
+            acc = (fin ? 0.0 : acc) + (add ? pv : 0.0);
+            a += fin ? 1 : 0;
+            b += add ? 1 : 0;
+        }
+        double v = block_segmented_scan(acc, a, s_first_key, s_last_key, s_last_val);
+        int next_key = __shfl_down(a, 1);
+        const int lane = tid & (kWave - 1), wave = tid / kWave;
+        if (lane == kWave - 1) next_key = wave + 1 < kBlock / kWave ? s_first_key[wave + 1] : -1;
+        if (next_key != a) {
+            if (a < nr)
+                s_out[a] += v;
+            else
+                s_open = v;
+        }
+        __syncthreads();
+        for (int k = tid; k < nr; k += kBlock) store_stream(y + bi0 + k, static_cast<V>(s_out[k]));
+        open = s_open;
+        __syncthreads();  // the row sums are out of the buffer the stash refills
+        if (c + 1 < pend) {
+            stash(buf ^ 1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1), bp1);
+            gather(static_cast<int>(bp3 - bp2));
+            if (c + 3 < pend) load(bi3, bp3, static_cast<int>(bi4 - bi3), static_cast<int>(bp4 - bp3));
+        }
+        bi0 = bi1; bp0 = bp1;
+        bi1 = bi2; bp1 = bp2;
+        bi2 = bi3; bp2 = bp3;
+        bi3 = bi4; bp3 = bp4;
+        buf ^= 1;
+    }
+    if (tid == 0) carry[blockIdx.x] = open;
+}
+
+// Order the LDS accesses of the lanes of one wave (no workgroup barrier).// Order the LDS accesses of the lanes of one wave (no workgroup barrier).
 __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -528,9 +708,19 @@ hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int
 template <typename V>
 hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const int32_t *crd,
                                const V *vals, const V *x, V *y, const Tiles &t, int64_t stride,
-                               bool exact, bool wave, double *carry, hipStream_t s) {
+                               bool exact, int variant, double *carry, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
-    if (wave) {
+    if (variant == 2) {
+        if (!exact) return hipErrorInvalidValue;
+        if (items <= 4)
+            k_spmv_flag<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        else
+            k_spmv_flag<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        return hipGetLastError();
+    }
+    if (variant == 1) {
         if (!exact) return hipErrorInvalidValue;
         dim3 wgrid(static_cast<unsigned>(ceil_div(ceil_div(t.ntiles, stride), kBlock / kWave)));
         if (items <= 4)
@@ -587,16 +777,16 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
 
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
-                             const Tiles &t, int64_t stride, bool exact_chunks, bool wave,
+                             const Tiles &t, int64_t stride, bool exact_chunks, int variant,
                              double *carry, hipStream_t s) {
     if (dtype == SPL_F64)
         return spmv_tiles_dispatch<double>(items, n, pos, crd, static_cast<const double *>(vals),
                                            static_cast<const double *>(x),
                                            static_cast<double *>(y), t, stride, exact_chunks,
-                                           wave, carry, s);
+                                           variant, carry, s);
     return spmv_tiles_dispatch<float>(items, n, pos, crd, static_cast<const float *>(vals),
                                       static_cast<const float *>(x), static_cast<float *>(y), t,
-                                      stride, exact_chunks, wave, carry, s);
+                                      stride, exact_chunks, variant, carry, s);
 }
 
 }  // namespace spl

@@ -30,6 +30,10 @@ SCHEDULES_SPMV = [
     dict(kind="merge", variant=1), dict(kind="merge", tile=100, items_per_lane=4, variant=1),
     dict(kind="merge", tile=5000, items_per_lane=8, variant=1),
     dict(kind="merge", tile=3000, items_per_lane=4, variant=1),
+    # row-end flag leaf: one chunk, several, ragged
+    dict(kind="merge", variant=2), dict(kind="merge", tile=1024, items_per_lane=4, variant=2),
+    dict(kind="merge", tile=9000, items_per_lane=8, variant=2),
+    dict(kind="merge", tile=7777, items_per_lane=4, variant=2),
 ]
 SCHEDULES_SPMM = [
     dict(kind="row", col_tile=32), dict(kind="row", col_tile=8),
@@ -241,7 +245,8 @@ def test_host_errors_reported():
     with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
         spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                  sched=spl.schedule("row", lanes_per_row=3))
-    for bad in (dict(kind="nnz", variant=1), dict(kind="merge", variant=2)):
+    for bad in (dict(kind="nnz", variant=1), dict(kind="row", variant=2),
+                dict(kind="merge", variant=3)):
         with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
             spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                      sched=spl.schedule(**bad))
