@@ -392,24 +392,81 @@ __device__ __forceinline__ double chunk_load<double>(__amdgpu_buffer_rsrc_t r, u
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNtAux));
 }
 
+// Wave-wide inclusive scans with DPP (GFX9 data-parallel primitives): four
+// shifts inside each row of 16 lanes, then lane 15 of rows 0 and 2 is added
+// to rows 1 and 3, and lane 31 to rows 2 and 3.  A lane whose source is out
+// of its row, or whose row is masked off, receives the `old` operand.
+template <int CTL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTL, ROWS, 0xf, false);
+}
+template <int CTL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_inclusive_sum(int s) {
+    s += dpp_i32<0x111, 0xf>(0, s);  // row_shr:1
+    s += dpp_i32<0x112, 0xf>(0, s);  // row_shr:2
+    s += dpp_i32<0x114, 0xf>(0, s);  // row_shr:4
+    s += dpp_i32<0x118, 0xf>(0, s);  // row_shr:8
+    s += dpp_i32<0x142, 0xa>(0, s);  // row_bcast:15 into rows 1, 3
+    s += dpp_i32<0x143, 0xc>(0, s);  // row_bcast:31 into rows 2, 3
+    return s;
+}
+
+// One step of the segmented scan: add the source lane's sum when it holds
+// the same key (key -1 from a lane without a source never matches).
+template <int CTL, int ROWS>
+__device__ __forceinline__ void seg_step(double &v, int key) {
+    const int k = dpp_i32<CTL, ROWS>(-1, key);
+    const double t = dpp_f64<CTL, ROWS>(0.0, v);
+    if (k == key) v += t;
+}
+
+// Inclusive sum of `v` over the lanes of the wave up to this one that share
+// its key (keys non-decreasing over the lanes).
+__device__ __forceinline__ double wave_segmented_sum(double v, int key) {
+    seg_step<0x111, 0xf>(v, key);
+    seg_step<0x112, 0xf>(v, key);
+    seg_step<0x114, 0xf>(v, key);
+    seg_step<0x118, 0xf>(v, key);
+    seg_step<0x142, 0xa>(v, key);
+    seg_step<0x143, 0xc>(v, key);
+    return v;
+}
+
 // Exclusive sum of `v` over the lanes of the workgroup before this one.
-// The adds are conditioned on the shuffled source lane (data, not the lane
-// index alone), so the shuffles stay outside any lane mask.
 __device__ __forceinline__ int block_exclusive_sum(int v, int *s_wave_total) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    int inc = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int u = __shfl_up(inc, off);
-        const int src = __shfl_up(lane, off);
-        if (src < lane) inc += u;
-    }
+    const int inc = wave_inclusive_sum(v);
     if (lane == kWave - 1) s_wave_total[wave] = inc;
     __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wave; ++w) before += s_wave_total[w];
+    static_assert(kBlock / kWave == 4, "four waves per workgroup");
+    const int4 t = *reinterpret_cast<const int4 *>(s_wave_total);
+    const int before = (wave > 0 ? t.x : 0) + (wave > 1 ? t.y : 0) + (wave > 2 ? t.z : 0);
     return before + inc - v;
+}
+
+// block_segmented_scan with the wave part done by DPP.
+__device__ __forceinline__ double block_segmented_scan_dpp(double v, int key, int *s_first_key,
+                                                          int *s_last_key, double *s_last_val) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    v = wave_segmented_sum(v, key);
+    if (lane == 0) s_first_key[wave] = key;
+    if (lane == kWave - 1) {
+        s_last_key[wave] = key;
+        s_last_val[wave] = v;
+    }
+    __syncthreads();
+    for (int w = wave - 1; w >= 0; --w) {
+        if (s_last_key[w] != key) break;
+        v += s_last_val[w];
+        if (s_first_key[w] != key) break;
+    }
+    return v;
 }
 
 // Merge-split leaf with row-end flags (schedule variant 2).  The same
@@ -432,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
     __shared__ double s_prod[2][kChunk + 1];  // + a spare slot for the walk
     // byte k: merged item k is a row end; byte kChunk is a spare
     __shared__ __align__(8) uint8_t s_flag[2][kChunk + 8];
-    __shared__ int s_wave_total[kBlock / kWave];
+    __shared__ __align__(16) int s_wave_total[kBlock / kWave];
     __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
     __shared__ double s_last_val[kBlock / kWave];
     __shared__ double s_open;
@@ -524,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
             a += fin ? 1 : 0;
             b += add ? 1 : 0;
         }
-        double v = block_segmented_scan(acc, a, s_first_key, s_last_key, s_last_val);
+        double v = block_segmented_scan_dpp(acc, a, s_first_key, s_last_key, s_last_val);
         int next_key = __shfl_down(a, 1);
         const int lane = tid & (kWave - 1), wave = tid / kWave;
         if (lane == kWave - 1) next_key = wave + 1 < kBlock / kWave ? s_first_key[wave + 1] : -1;
