@@ -121,11 +121,10 @@ def measure_banded(dev, spl, tuning, torch):
     x = c["x"]
     y = torch.empty(n, dtype=torch.float64, device=dev)
     cands = ([dict(kind="row", lanes_per_row=L) for L in (8, 16, 32, 64)] +
-             [dict(kind="merge", tile=2048, items_per_lane=8),
-              dict(kind="merge", tile=8192, items_per_lane=8),
-              dict(kind="merge", tile=4096, items_per_lane=4),
-              dict(kind="nnz", tile=4096, items_per_lane=8)] +
-             [dict(kind="merge", tile=T, items_per_lane=8, variant=1) for T in (8192, 16384, 32768)])
+             [dict(kind="merge", tile=T, items_per_lane=4) for T in (4096, 16384)] +
+             [dict(kind="merge", tile=T, items_per_lane=8) for T in (8192, 32768)] +
+             [dict(kind="merge", tile=4096, items_per_lane=4, variant=1),
+              dict(kind="nnz", tile=4096, items_per_lane=8)])
     best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
     ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
     out = _rate(ms, 4 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)
@@ -134,6 +133,17 @@ def measure_banded(dev, spl, tuning, torch):
     del B, c, x, y
     torch.cuda.empty_cache()
     return out
+
+
+# SpTTV runs the SpMV leaf on the fiber level: the SpMV candidates plus
+# longer merge tiles (several chunks per workgroup), which short fibers favour
+def _ttv_candidates():
+    from paper_2207_13901_amd import tuning
+    return tuning.SPMV_CANDIDATES + [dict(kind="merge", tile=T, items_per_lane=it)
+                                     for T, it in ((4096, 4), (16384, 4), (8192, 8), (32768, 8))]
+
+
+TTV_CANDIDATES = _ttv_candidates()
 
 
 def measure_ddc(dev, spl, tuning, torch):
@@ -153,7 +163,7 @@ def measure_ddc(dev, spl, tuning, torch):
     A = torch.empty(F, dtype=torch.float32, device=dev)
     out = {}
     best, _ = tuning.search(lambda s: (lambda: spl.spttv(B, cv, A, sched=s)),
-                            tuning.SPMV_CANDIDATES, reps=5)
+                            TTV_CANDIDATES, reps=5)
     st = spl.schedule(**best)
     ms = tuning.time_call(lambda: spl.spttv(B, cv, A, sched=st), reps=10, warmup=3)
     out["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
@@ -231,7 +241,7 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None):
         best_t = fixed["spttv"]
     else:
         best_t, _ = tuning.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
-                                    tuning.SPMV_CANDIDATES, reps=5)
+                                    TTV_CANDIDATES, reps=5)
     st = spl.schedule(**best_t)
     ms = tuning.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
     res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)

@@ -224,9 +224,11 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
  * B CSR n x m; c vector m; a vector n.  dtypes: vals, c, a all F64, or all
  * F32 (products and sums in F64, rounded once per output).  Schedules: ROW,
  * NNZ, MERGE (default MERGE), and SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE
- * (below).  sched->variant (MERGE only): 0 = a workgroup walks chunks of
- * 256 * items_per_lane merged items; 1 = each wave walks chunks of
- * 64 * items_per_lane on its own (default tile 4 chunks per wave).  Kinds
+ * (below).  sched->variant (MERGE only; both walk chunks of
+ * 256 * items_per_lane merged items): 0 = the row ends are staged as flags
+ * in the merged sequence and each lane's start comes from a count (default);
+ * 1 = each lane finds its start by a merge-path search over the row ends.
+ * Kinds
  * SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE are resolved first to one of the
  * candidates (which synchronizes on
  * `stream`; a caller workspace must then fit every candidate, as

@@ -32,9 +32,8 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
 // Tiled leaves: one workgroup per `stride` consecutive partition pieces of
 // `t`; carries are one per workgroup.
 // exact_chunks: every piece of `t` is at most one chunk of 256 * items merged
-// items (merge split): the pipelined leaf k_spmv_pipe; variant 1: chunks of
-// 64 * items and the wave-level leaf k_spmv_wave; variant 2: the row-end
-// flag leaf k_spmv_flag.
+// items (merge split): the row-end flag leaf k_spmv_flag (variant 0) or the
+// row-end search leaf k_spmv_pipe (variant 1).
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
                              const Tiles &t, int64_t stride, bool exact_chunks, int variant,

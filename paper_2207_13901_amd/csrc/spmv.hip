@@ -25,11 +25,12 @@
 //    non-zero algorithm of Sec. II-D requires.  No floating-point atomics,
 //    so results are bitwise reproducible.
 //
-//  * k_spmv_pipe: the merge-split form of k_spmv_tiles with its staging
-//    software-pipelined two chunks deep.
+//  * k_spmv_pipe (schedule variant 1): the merge-split form of
+//    k_spmv_tiles with its staging software-pipelined two chunks deep.
 //
-//  * k_spmv_wave (schedule variant 1): the same per wave, chunks of
-//    64 * ITEMS items, no workgroup barrier.
+//  * k_spmv_flag (merge split, default): the same pipeline with the row
+//    ends staged as flags in the merged sequence, so that no lane searches
+//    or reads row ends (see below).
 //
 // Accumulation is in double for both double and float data (a float output
 // is rounded once from the double sum, then once more if a carry lands on it).
@@ -469,8 +470,9 @@ __device__ __forceinline__ double block_segmented_scan_dpp(double v, int key, in
     return v;
 }
 
-// Merge-split leaf with row-end flags (schedule variant 2).  The same
-// pieces, pipeline and carries as k_spmv_pipe, but instead of the row ends
+// Merge-split leaf with row-end flags (the default; k_spmv_pipe is schedule
+// variant 1).  The same pieces, pipeline and carries as k_spmv_pipe, but
+// instead of the row ends
 // the staging writes a flag byte at each row end's place in the chunk's
 // merged sequence (row end r of the chunk sits at r + pos[r+1] - chunk
 // start).  A lane reads its ITEMS flags with one LDS load, counts them, and
@@ -609,139 +611,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
     if (tid == 0) carry[blockIdx.x] = open;
 }
 
-// Order the LDS accesses of the lanes of one wave (no workgroup barrier).// Order the LDS accesses of the lanes of one wave (no workgroup barrier).
-__device__ __forceinline__ void wave_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wave-level form of k_spmv_pipe (merge split, schedule variant 1): each
-// wave works alone on `stride` consecutive pieces of exactly one chunk of
-// 64 * ITEMS merged items, in a private double-buffered LDS region, with
-// the same two-deep pipeline of loads and gathers, the same branch-free
-// walk, and a wave segmented scan (shuffles) in place of the workgroup one:
-// no workgroup barrier anywhere.  One tile (and one carry) per wave.
-template <typename V, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_spmv_wave(
-    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
-    const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
-    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
-    int64_t stride, double *__restrict__ carry) {
-    constexpr int kChunk = kWave * ITEMS;
-    constexpr int kWaves = kBlock / kWave;
-    __shared__ double s_prod[kWaves][2][kChunk + 1];  // + a spare slot for the walk
-    __shared__ int32_t s_end[kWaves][2][kChunk];
-
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wv;
-    const int64_t p0 = tile * stride;
-    if (p0 >= npieces) return;  // wave-uniform; no workgroup barrier follows
-    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
-    auto bound_i = [&](int64_t c) { return static_cast<int64_t>(trow[c < pend ? c : pend]); };
-    auto bound_p = [&](int64_t c) { return static_cast<int64_t>(tpos[c < pend ? c : pend]); };
-
-    int e2[ITEMS], k2[ITEMS], e1[ITEMS];
-    V v2[ITEMS], v1[ITEMS], x1[ITEMS];
-    auto load = [&](int64_t bi, int64_t bp, int nr, int np) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int k = lane + j * kWave;
-            if (k < nr) e2[j] = pos[bi + 1 + k];
-            if (k < np) {
-                k2[j] = load_stream(crd + bp + k);
-                v2[j] = load_stream(vals + bp + k);
-            }
-        }
-    };
-    auto gather = [&](int np) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            e1[j] = e2[j];
-            v1[j] = v2[j];
-            if (lane + j * kWave < np) x1[j] = x[k2[j]];
-        }
-    };
-    auto stash = [&](int buf, int nr, int np) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int k = lane + j * kWave;
-            if (k < nr) s_end[wv][buf][k] = e1[j];
-            if (k < np) s_prod[wv][buf][k] = to_f64(v1[j]) * to_f64(x1[j]);
-        }
-    };
-
-    int64_t bi0 = bound_i(p0), bp0 = bound_p(p0);
-    int64_t bi1 = bound_i(p0 + 1), bp1 = bound_p(p0 + 1);
-    int64_t bi2 = bound_i(p0 + 2), bp2 = bound_p(p0 + 2);
-    int64_t bi3 = bound_i(p0 + 3), bp3 = bound_p(p0 + 3);
-    load(bi0, bp0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0));
-    gather(static_cast<int>(bp1 - bp0));
-    stash(0, static_cast<int>(bi1 - bi0), static_cast<int>(bp1 - bp0));
-    load(bi1, bp1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1));
-    gather(static_cast<int>(bp2 - bp1));
-    load(bi2, bp2, static_cast<int>(bi3 - bi2), static_cast<int>(bp3 - bp2));
-
-    double open = 0.0;
-    int buf = 0;
-    for (int64_t c = p0; c < pend; ++c) {
-        const int64_t bi4 = bound_i(c + 4), bp4 = bound_p(c + 4);
-        wave_fence();  // buffer `buf` holds chunk c
-        const int nr = static_cast<int>(bi1 - bi0), np = static_cast<int>(bp1 - bp0);
-        const int total = nr + np;
-        const int d0 = min(lane * ITEMS, total);
-        const int d1 = min(d0 + ITEMS, total);
-        const int32_t *send = s_end[wv][buf];
-        const double *sprod = s_prod[wv][buf];
-        double *s_out = s_prod[wv][buf ^ 1];  // finished rows until written out
-        int a = static_cast<int>(merge_search(d0, nr, np, bp0, [&](int64_t m) { return send[m]; }));
-        int b = d0 - a;
-        double acc = lane == 0 ? open : 0.0;
-#pragma unroll
-        for (int st = 0; st < ITEMS; ++st) {
-            const bool in = d0 + st < d1;
-            const int32_t e = send[a < kChunk ? a : kChunk - 1];
-            const double pv = sprod[b < kChunk ? b : kChunk - 1];
-            const bool fin = in && a < nr && e <= bp0 + b;
-            const bool add = in && !fin;
-            s_out[fin ? a : kChunk] = acc;
-            acc = fin ? 0.0 : (add ? acc + pv : acc);
-            a += fin ? 1 : 0;
-            b += add ? 1 : 0;
-        }
-        // segmented inclusive sum over the lanes by the row each is inside
-        double v = acc;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const double vu = __shfl_up(v, off);
-            const int ku = __shfl_up(a, off);
-            if (lane >= off && ku == a) v += vu;
-        }
-        wave_fence();  // the walk's row sums are in s_out
-        // key of the next lane, -1 past the last (an OR, not a select: the
-        // compiler would move a shuffle that one lane ignores under a lane
-        // mask, and a shuffle from a masked-off lane reads 0)
-        const int next_key = __shfl_down(a, 1) | -static_cast<int>(lane == kWave - 1);
-        if (next_key != a && a < nr) s_out[a] += v;
-        // the last lane is always inside the row left open (a == nr there)
-        open = __shfl(v, kWave - 1);
-        wave_fence();
-        for (int k = lane; k < nr; k += kWave) store_stream(y + bi0 + k, static_cast<V>(s_out[k]));
-        wave_fence();  // the row sums are out of the buffer the stash refills
-        if (c + 1 < pend) {
-            stash(buf ^ 1, static_cast<int>(bi2 - bi1), static_cast<int>(bp2 - bp1));
-            gather(static_cast<int>(bp3 - bp2));
-            if (c + 3 < pend) load(bi3, bp3, static_cast<int>(bi4 - bi3), static_cast<int>(bp4 - bp3));
-        }
-        bi0 = bi1; bp0 = bp1;
-        bi1 = bi2; bp1 = bp2;
-        bi2 = bi3; bp2 = bp3;
-        bi3 = bi4; bp3 = bp4;
-        buf ^= 1;
-    }
-    if (lane == 0) carry[tile] = open;
-}
-
 template <typename V>
 hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int32_t *crd,
                              const V *vals, const V *x, V *y, hipStream_t s) {
@@ -767,25 +636,13 @@ hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const i
                                const V *vals, const V *x, V *y, const Tiles &t, int64_t stride,
                                bool exact, int variant, double *carry, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
-    if (variant == 2) {
-        if (!exact) return hipErrorInvalidValue;
+    if (exact && variant == 0) {
         if (items <= 4)
             k_spmv_flag<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
                                                        t.ntiles, stride, carry);
         else
             k_spmv_flag<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
                                                        t.ntiles, stride, carry);
-        return hipGetLastError();
-    }
-    if (variant == 1) {
-        if (!exact) return hipErrorInvalidValue;
-        dim3 wgrid(static_cast<unsigned>(ceil_div(ceil_div(t.ntiles, stride), kBlock / kWave)));
-        if (items <= 4)
-            k_spmv_wave<V, 4><<<wgrid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
-                                                        t.ntiles, stride, carry);
-        else
-            k_spmv_wave<V, 8><<<wgrid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
-                                                        t.ntiles, stride, carry);
         return hipGetLastError();
     }
     if (exact) {

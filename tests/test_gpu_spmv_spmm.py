@@ -26,14 +26,10 @@ SCHEDULES_SPMV = [
     dict(kind="merge", tile=777), dict(kind="default"),
     # several chunks per workgroup: the pipelined leaf's steady state
     dict(kind="merge", tile=8192, items_per_lane=4), dict(kind="merge", tile=6000, items_per_lane=8),
-    # wave-level leaf: default (4 chunks per wave), one chunk, several ragged
-    dict(kind="merge", variant=1), dict(kind="merge", tile=100, items_per_lane=4, variant=1),
-    dict(kind="merge", tile=5000, items_per_lane=8, variant=1),
-    dict(kind="merge", tile=3000, items_per_lane=4, variant=1),
-    # row-end flag leaf: one chunk, several, ragged
-    dict(kind="merge", variant=2), dict(kind="merge", tile=1024, items_per_lane=4, variant=2),
-    dict(kind="merge", tile=9000, items_per_lane=8, variant=2),
-    dict(kind="merge", tile=7777, items_per_lane=4, variant=2),
+    # row-end search leaf: one chunk, several, ragged
+    dict(kind="merge", variant=1), dict(kind="merge", tile=1024, items_per_lane=4, variant=1),
+    dict(kind="merge", tile=9000, items_per_lane=8, variant=1),
+    dict(kind="merge", tile=7777, items_per_lane=4, variant=1),
 ]
 SCHEDULES_SPMM = [
     dict(kind="row", col_tile=32), dict(kind="row", col_tile=8),
@@ -245,8 +241,8 @@ def test_host_errors_reported():
     with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
         spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                  sched=spl.schedule("row", lanes_per_row=3))
-    for bad in (dict(kind="nnz", variant=1), dict(kind="row", variant=2),
-                dict(kind="merge", variant=3)):
+    for bad in (dict(kind="nnz", variant=1), dict(kind="row", variant=1),
+                dict(kind="merge", variant=2)):
         with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
             spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                      sched=spl.schedule(**bad))
