@@ -186,7 +186,7 @@ def measure_ddc(dev, spl, tuning, torch):
     return out
 
 
-def measure_other_ops(dev, spl, tuning, torch, fixed=None):
+def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
     200,000^3 CSF tensor with 1e8 nonzeros.  SpTTV and SpMTTKRP run with the
@@ -278,8 +278,9 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None):
                                      2 * nnz)
     del B64, C64, B32, Cg, c4
     torch.cuda.empty_cache()
-    res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
-    res["ddc"] = measure_ddc(dev, spl, tuning, torch)
+    if next_rows:
+        res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
+        res["ddc"] = measure_ddc(dev, spl, tuning, torch)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
         "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",
@@ -307,6 +308,8 @@ def main():
                     help="JSON schedule for SpMM instead of autotuning")
     ap.add_argument("--sched", action="append", default=[], metavar="OP=JSON",
                     help="fixed schedule for spttv or mttkrp (repeatable)")
+    ap.add_argument("--no-next", action="store_true",
+                    help="leave out the banded and (Dense, Dense, Compressed) workloads")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the SDDMM/SpAdd3/SpTTV/SpMTTKRP/inner-product measurements")
     ap.add_argument("--calibrate", action="store_true",
@@ -340,7 +343,8 @@ def main():
         op, js = item.split("=", 1)
         fixed[op] = json.loads(js)
     if args.ops_only:
-        print(json.dumps({"ops": measure_other_ops(dev, spl, tuning, torch, fixed)}),
+        print(json.dumps({"ops": measure_other_ops(dev, spl, tuning, torch, fixed,
+                                                   not args.no_next)}),
               flush=True)
         return
     t0 = time.time()
@@ -564,7 +568,7 @@ def main():
     if not args.profile and not args.no_ops:
         del B64, B16, D64, D16, A64
         torch.cuda.empty_cache()
-        out["ops"] = measure_other_ops(dev, spl, tuning, torch, fixed)
+        out["ops"] = measure_other_ops(dev, spl, tuning, torch, fixed, not args.no_next)
 
     if not args.profile and not args.no_cpu:
         import oracle
