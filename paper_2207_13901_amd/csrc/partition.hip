@@ -14,7 +14,8 @@
 //    T positions, rows recovered by a preimage through pos): tile t starts at
 //    (number of rows finished at position t*T, t*T); tile 0 starts at (0, 0)
 //    so that leading empty rows belong to it.
-//  - Merge split: tile t starts at the point t*M of the merged sequence.
+//  - Merge split: tile t starts at the point t*M of the merged sequence
+//    (a search per tile, or one sweep over the rows when they are few).
 #include <algorithm>
 
 #include "device.hpp"
@@ -69,6 +70,32 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const int
     tpos[t] = static_cast<int32_t>(d - i);
 }
 
+// The merge split by a sweep over the rows instead of a search per tile:
+// row i (i < rows) owns the merged indices i + pos[i] .. i + pos[i+1] (its
+// positions, then its end), so every tile start d = t M in that range has
+// trow = i and tpos = d - i (the merge-path search gives the same i: the row
+// ends before index d are those of rows 0 .. i-1).  The virtual row `rows`
+// owns the bounds at or past the end, (rows, nnz).  One lane per row; reading pos once costs
+// less than a 20-step dependent search per tile when rows are few.
+__global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const int32_t *pos,
+                                                        int64_t nnz, int64_t M, int64_t ntiles,
+                                                        int32_t *trow, int32_t *tpos) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i > rows) return;
+    if (i == rows) {  // every bound at or past the end: the last, and all when there are no items
+        for (int64_t t = (rows + nnz + M - 1) / M; t <= ntiles; ++t) {
+            trow[t] = static_cast<int32_t>(rows);
+            tpos[t] = static_cast<int32_t>(nnz);
+        }
+        return;
+    }
+    const int64_t lo = i + pos[i], hi = i + pos[i + 1];
+    for (int64_t t = (lo + M - 1) / M; t * M <= hi; ++t) {
+        trow[t] = static_cast<int32_t>(i);
+        tpos[t] = static_cast<int32_t>(t * M - i);
+    }
+}
+
 // The pos and crd arrays a Dense level of extent J under I parents would
 // have if it were stored compressed (the Dense level functions, Sec. III-B
 // and Table I): parent i owns positions [i J, (i + 1) J) and position f holds
@@ -100,6 +127,10 @@ int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size) {
     return nt > 0 ? nt : 1;
 }
 
+// Up to this many rows the merge split is computed by the sweep (a read of
+// 4 (rows + 1) bytes); beyond, by one merge-path search per tile.
+constexpr int64_t kMergeSweepRows = 8000000;
+
 hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_t nnz,
                               int64_t size, const Tiles &t, hipStream_t s) {
     dim3 grid(static_cast<unsigned>((t.ntiles + 1 + kBlock - 1) / kBlock));
@@ -111,7 +142,11 @@ hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_
         k_nnz_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
         break;
     default:
-        k_merge_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
+        if (rows <= kMergeSweepRows)
+            k_merge_sweep<<<dim3(static_cast<unsigned>(ceil_div(rows + 1, kBlock))), kBlock, 0, s>>>(
+                rows, pos, nnz, size, t.ntiles, t.row, t.pos);
+        else
+            k_merge_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
         break;
     }
     return hipGetLastError();

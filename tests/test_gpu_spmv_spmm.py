@@ -92,6 +92,26 @@ def test_tile_bounds_match_oracle(kind, size):
         assert np.array_equal(tp.cpu().numpy(), rp)
 
 
+def test_merge_bounds_above_the_sweep_limit():
+    # more than 8,000,000 rows: the merge split is found by a search per tile
+    # (below, by a sweep over the rows); both must equal the oracle's split
+    spl = _spl()
+    rs = np.random.RandomState(17)
+    for n in (8_000_000, 9_000_001):
+        deg = (rs.random_sample(n) < 0.1).astype(np.int64) * rs.randint(1, 4, n)
+        deg[n // 2] = 50_000  # one row across many tiles
+        pos = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(deg, out=pos[1:])
+        nnz = int(pos[-1])
+        crd = np.zeros(nnz, dtype=np.int32)
+        B = _csr(spl, pos.astype(np.int32), crd, np.ones(nnz), (n, 1), torch.float64)
+        for size in (7, 2048):
+            tr, tp = spl.tile_bounds(B, spl.schedule("merge", tile=size))
+            rr, rp = oracle.merge_split(pos.astype(np.int32), size)
+            assert np.array_equal(tr.cpu().numpy(), rr), (n, size)
+            assert np.array_equal(tp.cpu().numpy(), rp), (n, size)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_spmv_config1_all_schedules(dtype):
     spl = _spl()
