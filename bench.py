@@ -135,6 +135,42 @@ def measure_banded(dev, spl, tuning, torch):
     return out
 
 
+def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
+    """The value-range partition of the power-law matrix's columns into
+    eight equal blocks (one kernel), and the SpMV as the sum of the eight
+    column blocks' windowed products (FP64), against the whole SpMV."""
+    import numpy as np
+    from workloads import configs
+    c = configs.config2(device=dev, with_dense=False)
+    n = c["n"]
+    nnz = int(c["crd"].numel())
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    x = c["x"]
+    bounds = torch.as_tensor(np.linspace(0, n, ncolors + 1).astype(np.int32), device=dev)
+    out = torch.empty(ncolors + 1, n, dtype=torch.int32, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    ms_p = tuning.time_call(lambda: spl.coord_partition(B, bounds, out), reps=10, warmup=3)
+    spl.coord_partition(B, bounds, out)
+    lanes = [dict(kind="row", lanes_per_row=L) for L in (1, 2, 4, 8)]
+
+    def windows(sc):
+        for col in range(ncolors):
+            spl.spmv_window(B, out[col], out[col + 1], x, y, sched=sc)
+
+    best, _ = tuning.search(lambda sc: (lambda: windows(sc)), lanes, reps=3)
+    sb = spl.schedule(**best)
+    ms_w = tuning.time_call(lambda: windows(sb), reps=10, warmup=3)
+    res = {"partition": _rate(ms_p, 4 * (n + 1) + 4 * nnz + 4 * (ncolors + 1) * n, 0),
+           "windows_spmv_f64": _rate(ms_w, ncolors * 8 * n + 12 * nnz + 8 * n + ncolors * 8 * n,
+                                     2 * nnz)}
+    res["windows_spmv_f64"]["schedule"] = best
+    res["workload"] = (f"power-law CSR {n}^2, {nnz} nnz, FP64; {ncolors} equal column blocks, "
+                       f"the SpMV as the {ncolors} blocks' windowed products")
+    del B, c, x, out, y
+    torch.cuda.empty_cache()
+    return res
+
+
 # SpTTV runs the SpMV leaf on the fiber level: the SpMV candidates plus
 # longer merge tiles (several chunks per workgroup), which short fibers favour
 def _ttv_candidates():
@@ -281,6 +317,7 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
     if next_rows:
         res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
         res["ddc"] = measure_ddc(dev, spl, tuning, torch)
+        res["coord_partition"] = measure_coord_partition(dev, spl, tuning, torch)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
         "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",

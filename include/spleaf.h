@@ -237,6 +237,33 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
                     spl_dense *a, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);
 
+/* Universe partition of B's Compressed level by coordinate value ranges,
+ * carried to the rows by a preimage (Sec. III-A; Table I: a Compressed
+ * level's universe partition colors each stored coordinate by the value
+ * range that holds it, and the preimage through pos gives each row the
+ * positions of each color).  B CSR n x m.  bounds: device int32[ncolors+1],
+ * non-decreasing (color c holds coordinates in [bounds[c], bounds[c+1]);
+ * bounds[0] <= 0 and bounds[ncolors] >= m make the colors cover every
+ * column).  out: device int32[(ncolors+1) * n], written: out[c*n + i] is
+ * the first position of row i whose coordinate is >= bounds[c]
+ * (pos[i+1] if none), so color c of row i is the positions
+ * [out[c*n+i], out[(c+1)*n+i]).  Coordinates must be sorted within rows
+ * (spl_validate).  The rows of a color are the windows spl_spmv_window
+ * takes. */
+spl_status spl_coord_partition(spl_context *ctx, const spl_sparse *B, int32_t ncolors,
+                               const int32_t *bounds, int32_t *out, spl_stream stream);
+
+/* SpMV over position windows: a(i) = sum over p in [begin[i], end[i]) of
+ * B.vals[p] * c(B.crd[p]) — for one color of spl_coord_partition, the
+ * product of B's column block with c.  B CSR n x m; begin, end: device
+ * int32[n] with pos[i] <= begin[i] <= end[i] <= pos[i+1] (not checked: they
+ * are read as row bounds); c vector m; a vector n, every entry written.
+ * dtypes as spl_spmv.  Schedule: ROW only (lanes_per_row; default by the
+ * mean row length of B), so no workspace. */
+spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t *begin,
+                           const int32_t *end, const spl_dense *c, spl_dense *a,
+                           const spl_schedule *sched, spl_stream stream);
+
 /* SpMM  A(i,j) = B(i,k) * C(k,j)   (Sec. VI-A).
  * B CSR n x m; C dense m x N; A dense n x N.  dtypes (vals, C, A): all F64;
  * all F32; or vals and C BF16 with A F32 (F32 accumulation).  Schedules:

@@ -221,6 +221,35 @@ def inner(B, C):
     return float(a), float(S.value)
 
 
+def coord_partition(pos, crd, bounds):
+    """Value-range partition of a CSR's columns: out int32[ncolors+1, n]."""
+    lib = _load()
+    n = len(pos) - 1
+    p, pp = _i32(pos)
+    c, cp = _i32(crd)
+    b, bp = _i32(bounds)
+    ncolors = len(bounds) - 1
+    out = np.zeros((ncolors + 1) * max(n, 0), dtype=np.int32)
+    lib.orc_coord_partition(_i64(n), pp, cp, _i64(ncolors), bp,
+                            out.ctypes.data_as(_i32p))
+    return out.reshape(ncolors + 1, n)
+
+
+def spmv_window(begin, end, crd, vals, c):
+    """a(i) over positions [begin[i], end[i]); returns (a, S)."""
+    lib = _load()
+    n = len(begin)
+    b, bp = _i32(begin)
+    e, ep = _i32(end)
+    k, kp = _i32(crd)
+    v, vp = _f64(vals)
+    x, xp = _f64(c)
+    a, ap = _out(n)
+    S, Sp = _out(n)
+    lib.orc_spmv_window(_i64(n), bp, ep, kp, vp, xp, ap, Sp)
+    return a, S
+
+
 def spttv_ddc(I, J, pos2, crd2, vals, c):
     """SpTTV of a (Dense, Dense, Compressed) tensor: A(i,j) for every (i,j),
     returned flattened row-major (I*J values) with S."""

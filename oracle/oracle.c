@@ -409,6 +409,44 @@ double orc_inner3(int64_t I, int64_t J,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Universe partition of a Compressed level by coordinate value ranges       */
+/* (Sec. III-A; Table I): each stored coordinate takes the color of the      */
+/* range [bounds[c], bounds[c+1]) holding its value, and the preimage        */
+/* through pos gives each row its positions of that color.  out[c*n + i] =   */
+/* pos[i] + the number of coordinates of row i below bounds[c]; with sorted  */
+/* coordinates, color c of row i is then [out[c*n+i], out[(c+1)*n+i]).        */
+/* ------------------------------------------------------------------------ */
+void orc_coord_partition(int64_t n, const int32_t *pos, const int32_t *crd, int64_t ncolors,
+                         const int32_t *bounds, int32_t *out)
+{
+    for (int64_t c = 0; c <= ncolors; ++c) {
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t below = 0;
+            for (int64_t p = pos[i]; p < pos[i + 1]; ++p)
+                if (crd[p] < bounds[c]) ++below;
+            out[c * n + i] = (int32_t)(pos[i] + below);
+        }
+    }
+}
+
+/* SpMV over position windows: a(i) = sum over p in [begin[i], end[i]) of    */
+/* vals[p] * c[crd[p]] (one color of the partition above).                  */
+void orc_spmv_window(int64_t n, const int32_t *begin, const int32_t *end, const int32_t *crd,
+                     const double *vals, const double *c, double *a, double *S)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        ld sum = 0.0L, mag = 0.0L;
+        for (int64_t p = begin[i]; p < end[i]; ++p) {
+            ld term = (ld)vals[p] * (ld)c[crd[p]];
+            sum += term;
+            mag += ld_abs(term);
+        }
+        a[i] = (double)sum;
+        if (S) S[i] = (double)mag;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Partitions of a Compressed level (Sec. III-A, IV-B, Table I).             */
 /*                                                                           */
 /* A tile of a leaf kernel is described by the pair (row, position) at which */

@@ -22,11 +22,11 @@ from . import _native as N
 from ._native import SpleafError
 
 __all__ = [
-    "CSR", "CSF", "DDC", "Context", "schedule", "spmv", "spmm", "tile_bounds",
+    "CSR", "CSF", "Context", "schedule", "spmv", "spmm", "tile_bounds",
     "validate", "op_parse", "op_tin", "workspace_query", "workspace", "SpleafError",
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
-    "schedule_dict",
+    "schedule_dict", "coord_partition", "spmv_window", "DDC",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -242,6 +242,35 @@ def spmv(B: CSR, c: torch.Tensor, a: Optional[torch.Tensor] = None, sched=None,
                                ctypes.byref(_dense(a)),
                                ctypes.byref(sched) if sched else None,
                                _ptr(ws), nb, stream), "spl_spmv")
+    return a
+
+
+def coord_partition(B: CSR, bounds: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    ctx: Optional[Context] = None) -> torch.Tensor:
+    """Value-range partition of B's columns: bounds int32[ncolors+1] on the
+    device; returns out int32[ncolors+1, n] with color c of row i at
+    positions [out[c, i], out[c+1, i])."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    ncolors = bounds.numel() - 1
+    if out is None:
+        out = torch.empty(ncolors + 1, B.shape[0], dtype=torch.int32, device=B.vals.device)
+    s = B.struct()
+    ctx.check(ctx.lib.spl_coord_partition(ctx.h, ctypes.byref(s), ncolors, _ptr(bounds),
+                                          _ptr(out), stream), "spl_coord_partition")
+    return out
+
+
+def spmv_window(B: CSR, begin: torch.Tensor, end: torch.Tensor, c: torch.Tensor,
+                a: Optional[torch.Tensor] = None, sched=None,
+                ctx: Optional[Context] = None) -> torch.Tensor:
+    """a(i) = sum of B's values times c over positions [begin[i], end[i])."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    if a is None:
+        a = torch.empty(B.shape[0], dtype=B.vals.dtype, device=B.vals.device)
+    s = B.struct()
+    ctx.check(ctx.lib.spl_spmv_window(ctx.h, ctypes.byref(s), _ptr(begin), _ptr(end),
+                                      ctypes.byref(_dense(c)), ctypes.byref(_dense(a)),
+                                      _sched_ptr(sched), stream), "spl_spmv_window")
     return a
 
 

@@ -968,7 +968,7 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     if (n == 0) return SPL_OK;
     if (p.kind == SPL_ROW) {
         LeafTimer tm(ctx, SPL_OP_SPMV, s);
-        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, B->pos[1], B->crd[1], B->vals, c->data,
+        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, B->pos[1], nullptr, B->crd[1], B->vals, c->data,
                                      a->data, s),
                 "SpMV row launch");
         tm.stop();
@@ -1046,6 +1046,51 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     SPL_GUARD_END
 }
 
+spl_status spl_coord_partition(spl_context *ctx, const spl_sparse *B, int32_t ncolors,
+                               const int32_t *bounds, int32_t *out, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    if (ncolors < 1) return fail(ctx, SPL_ERR_ARG, "ncolors must be at least 1");
+    const int64_t n = B->dims[0];
+    if (n == 0) return SPL_OK;
+    if (!bounds || !out) return fail(ctx, SPL_ERR_ARG, "NULL bounds or output");
+    SPL_CHECK(set_device(ctx));
+    SPL_HIP(spl::launch_coord_split(n, B->pos[1], B->crd[1], static_cast<int64_t>(ncolors) + 1,
+                                    bounds, out, static_cast<hipStream_t>(stream)),
+            "coordinate partition launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t *begin,
+                           const int32_t *end, const spl_dense *c, spl_dense *a,
+                           const spl_schedule *sched, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    SPL_CHECK(check_dense(ctx, c, "c", 1, B->dims[1], -1));
+    SPL_CHECK(check_dense(ctx, a, "a", 1, B->dims[0], -1));
+    if (B->vtype == SPL_BF16 || c->dtype != B->vtype || a->dtype != B->vtype)
+        return fail(ctx, SPL_ERR_DTYPE, "SpMV needs vals, c and a all F64 or all F32");
+    Plan p;
+    SPL_CHECK(resolve_spmv(ctx, B, sched, p));
+    if (sched && sched->kind != SPL_SCHED_DEFAULT && p.kind != SPL_ROW)
+        return fail(ctx, SPL_ERR_ARG, "a windowed SpMV runs the ROW schedule only");
+    const int64_t n = B->dims[0];
+    if (n == 0) return SPL_OK;
+    if (!begin || !end) return fail(ctx, SPL_ERR_ARG, "NULL window bounds");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LeafTimer tm(ctx, SPL_OP_SPMV, s);
+    SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, begin, end, B->crd[1], B->vals, c->data,
+                                 a->data, s),
+            "windowed SpMV launch");
+    tm.stop();
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
 spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, spl_dense *A,
                      const spl_schedule *sched, void *workspace, size_t workspace_bytes,
                      spl_stream stream) {
@@ -1065,7 +1110,7 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
     if (F == 0) return SPL_OK;
     if (p.kind == SPL_ROW) {
         LeafTimer tm(ctx, SPL_OP_SPTTV, s);
-        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, F, v.pos[1], v.crd[1], B->vals, c->data,
+        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, F, v.pos[1], nullptr, v.crd[1], B->vals, c->data,
                                      A->data, s),
                 "SpTTV row launch");
         tm.stop();

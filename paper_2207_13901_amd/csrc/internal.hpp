@@ -26,9 +26,11 @@ hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_
                               int64_t size, const Tiles &t, hipStream_t s);
 
 // ---- spmv.hip ------------------------------------------------------------
-hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
-                           const int32_t *crd, const void *vals, const void *x, void *y,
-                           hipStream_t s);
+// Row split: row i covers positions [pos_b[i], pos_e[i]); pos_e == nullptr
+// means CSR (pos_e = pos_b + 1).
+hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos_b,
+                           const int32_t *pos_e, const int32_t *crd, const void *vals,
+                           const void *x, void *y, hipStream_t s);
 // Tiled leaves: one workgroup per `stride` consecutive partition pieces of
 // `t`; carries are one per workgroup.
 // exact_chunks: every piece of `t` is at most one chunk of 256 * items merged
@@ -61,6 +63,10 @@ hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, in
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 
 // ---- csf.hip -------------------------------------------------------------
+// Value-range partition of a Compressed level: out[c * rows + i] = first
+// position of parent i whose coordinate is >= bounds[c], c < nbounds.
+hipError_t launch_coord_split(int64_t rows, const int32_t *pos, const int32_t *crd, int64_t nbounds,
+                              const int32_t *bounds, int32_t *out, hipStream_t s);
 // pos (I + 1 entries) and crd (I * J entries) of a Dense level of extent J
 // under I parents, written out as a Compressed level would store them.
 hipError_t launch_dense_level(int64_t I, int64_t J, int32_t *pos, int32_t *crd, hipStream_t s);

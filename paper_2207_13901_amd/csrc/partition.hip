@@ -96,6 +96,34 @@ __global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const int3
     }
 }
 
+// Universe partition of a Compressed level by coordinate value ranges,
+// carried up to the parent level by a preimage (Sec. III-A; Table I, the
+// Compressed level's value-range partition): parent i's positions whose
+// coordinate lies in [bounds[c], bounds[c+1]) are [out[c][i], out[c+1][i]),
+// where out[c][i] is the first position of parent i with coordinate at
+// least bounds[c] (coordinates are sorted within a parent).  One lane per
+// (bound, parent) pair, a binary search inside the parent's segment; lanes
+// of a wave share the bound, so the writes of one bound are coalesced.
+__global__ __launch_bounds__(kBlock) void k_coord_split(int64_t rows, const int32_t *__restrict__ pos,
+                                                        const int32_t *__restrict__ crd,
+                                                        int64_t nbounds,
+                                                        const int32_t *__restrict__ bounds,
+                                                        int32_t *__restrict__ out) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (k >= nbounds * rows) return;
+    const int64_t c = k / rows, i = k - c * rows;
+    const int32_t b = bounds[c];
+    int64_t lo = pos[i], hi = pos[i + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (crd[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[k] = static_cast<int32_t>(lo);
+}
+
 // The pos and crd arrays a Dense level of extent J under I parents would
 // have if it were stored compressed (the Dense level functions, Sec. III-B
 // and Table I): parent i owns positions [i J, (i + 1) J) and position f holds
@@ -112,6 +140,15 @@ __global__ __launch_bounds__(kBlock) void k_dense_level(int64_t I, int64_t J,
 }
 
 }  // namespace
+
+hipError_t launch_coord_split(int64_t rows, const int32_t *pos, const int32_t *crd, int64_t nbounds,
+                              const int32_t *bounds, int32_t *out, hipStream_t s) {
+    const int64_t lanes = nbounds * rows;
+    if (lanes == 0) return hipSuccess;
+    k_coord_split<<<dim3(static_cast<unsigned>(ceil_div(lanes, kBlock))), kBlock, 0, s>>>(
+        rows, pos, crd, nbounds, bounds, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_dense_level(int64_t I, int64_t J, int32_t *pos, int32_t *crd, hipStream_t s) {
     const int64_t F = I * J;

@@ -7,6 +7,8 @@
 //    partition of the rows into blocks of 256/L per workgroup, image to the
 //    positions).  No carries: every row is finished by the group that owns
 //    it.  Good for short, even rows; a long row serializes on its group.
+//    Rows are given by begin and end arrays, so the same leaf runs over the
+//    position windows of one color of a coordinate-value partition.
 //
 //  * k_spmv_tiles: non-zero or merge split.  A workgroup owns `stride`
 //    consecutive pieces of the level partition computed by partition.hip
@@ -44,7 +46,8 @@ namespace spl {
 namespace {
 
 template <int L, typename V>
-__global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *__restrict__ pos,
+__global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *__restrict__ pos_b,
+                                                     const int32_t *__restrict__ pos_e,
                                                      const int32_t *__restrict__ crd,
                                                      const V *__restrict__ vals,
                                                      const V *__restrict__ x, V *__restrict__ y) {
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *_
     const int lane = threadIdx.x % L;
     double acc = 0.0;
     if (row < n) {
-        const int p0 = pos[row], p1 = pos[row + 1];
+        const int p0 = pos_b[row], p1 = pos_e[row];
         int p = p0 + lane;
         // two independent partial sums keep two gathers in flight per lane
         double acc2 = 0.0;
@@ -73,7 +76,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_row(int64_t n, const int32_t *_
 // lane's rows at once, so short rows (fibers of a CSF tensor) keep kRows
 // independent gathers in flight instead of one.
 template <typename V, int kRows>
-__global__ __launch_bounds__(kBlock) void k_spmv_row_multi(int64_t n, const int32_t *__restrict__ pos,
+__global__ __launch_bounds__(kBlock) void k_spmv_row_multi(int64_t n,
+                                                           const int32_t *__restrict__ pos_b,
+                                                           const int32_t *__restrict__ pos_e,
                                                            const int32_t *__restrict__ crd,
                                                            const V *__restrict__ vals,
                                                            const V *__restrict__ x,
@@ -84,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_row_multi(int64_t n, const int3
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const int64_t r = r0 + static_cast<int64_t>(k) * kBlock;
-        p[k] = r < n ? pos[r] : 0;
-        e[k] = r < n ? pos[r + 1] : 0;
+        p[k] = r < n ? pos_b[r] : 0;
+        e[k] = r < n ? pos_e[r] : 0;
         acc[k] = 0.0;
     }
     for (;;) {
@@ -612,12 +617,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
 }
 
 template <typename V>
-hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos, const int32_t *crd,
-                             const V *vals, const V *x, V *y, hipStream_t s) {
+hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos_b, const int32_t *pos_e,
+                             const int32_t *crd, const V *vals, const V *x, V *y, hipStream_t s) {
     auto go = [&](auto kern, int rows_per_block) {
         int64_t blocks = (n + rows_per_block - 1) / rows_per_block;
         if (blocks == 0) return hipSuccess;
-        kern<<<dim3(static_cast<unsigned>(blocks)), kBlock, 0, s>>>(n, pos, crd, vals, x, y);
+        kern<<<dim3(static_cast<unsigned>(blocks)), kBlock, 0, s>>>(n, pos_b, pos_e, crd, vals, x,
+                                                                    y);
         return hipGetLastError();
     };
     switch (lanes) {
@@ -679,13 +685,15 @@ hipError_t launch_spmv_fixup(int dtype, int64_t n, const Tiles &t, int64_t strid
     return spmv_fixup_dispatch<float>(n, t, stride, carry, static_cast<float *>(y), s);
 }
 
-hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos,
-                           const int32_t *crd, const void *vals, const void *x, void *y,
-                           hipStream_t s) {
+hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos_b,
+                           const int32_t *pos_e, const int32_t *crd, const void *vals,
+                           const void *x, void *y, hipStream_t s) {
+    if (!pos_e) pos_e = pos_b + 1;  // CSR: row i ends where row i + 1 begins
     if (dtype == SPL_F64)
-        return spmv_row_dispatch<double>(lanes, n, pos, crd, static_cast<const double *>(vals),
+        return spmv_row_dispatch<double>(lanes, n, pos_b, pos_e, crd,
+                                         static_cast<const double *>(vals),
                                          static_cast<const double *>(x), static_cast<double *>(y), s);
-    return spmv_row_dispatch<float>(lanes, n, pos, crd, static_cast<const float *>(vals),
+    return spmv_row_dispatch<float>(lanes, n, pos_b, pos_e, crd, static_cast<const float *>(vals),
                                     static_cast<const float *>(x), static_cast<float *>(y), s);
 }
 

@@ -54,6 +54,29 @@ def test_config2_spmv_sampled(c2):
                          f"spmv {dtype} {cand}")
 
 
+def test_config2_coord_partition_windows_sampled(c2):
+    # eight column blocks: the partition equals the oracle's on sampled rows,
+    # and the eight windowed products add up to the SpMV
+    spl, tuning = _spl()
+    c, h = c2
+    n = c["n"]
+    rows = _sample_rows(h["pos"], k=300)
+    bounds = np.linspace(0, n, 9).astype(np.int32)
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    out = spl.coord_partition(B, torch.as_tensor(bounds, device=c["pos"].device))
+    got = out[:, torch.as_tensor(rows, device=out.device)].cpu().numpy()
+    for k, i in enumerate(rows):
+        seg = h["crd"][h["pos"][i]:h["pos"][i + 1]]
+        want = h["pos"][i] + np.searchsorted(seg, bounds, side="left")
+        assert np.array_equal(got[:, k], want), i
+    total = torch.zeros(n, dtype=torch.float64, device=out.device)
+    for col in range(8):
+        total += spl.spmv_window(B, out[col], out[col + 1], c["x"])
+    ref, S = oracle.spmv(h["pos"], h["crd"], host64(B.vals), host64(c["x"]), rows=rows)
+    assert_close(host64(total[torch.as_tensor(rows, device=total.device)]), ref, S, 1e-12,
+                 "sum of column-block windows")
+
+
 def test_config2_spmm_sampled(c2):
     spl, tuning = _spl()
     c, h = c2

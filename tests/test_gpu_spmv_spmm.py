@@ -92,6 +92,37 @@ def test_tile_bounds_match_oracle(kind, size):
         assert np.array_equal(tp.cpu().numpy(), rp)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_coord_partition_and_window_spmv(dtype):
+    spl = _spl()
+    cases = list(_edge_cases().values())
+    c2 = configs.config2(scale=0.002, with_dense=False)
+    cases.append((c2["pos"].numpy(), c2["crd"].numpy(), c2["vals"].numpy(), (c2["n"], c2["n"])))
+    rs = np.random.RandomState(5)
+    for pos, crd, vals, shape in cases:
+        n, m = shape
+        B = _csr(spl, pos, crd, vals, shape, dtype)
+        x = torch.as_tensor(rs.uniform(-1, 1, m), device=dev()).to(dtype)
+        for bounds in ([0, m], np.linspace(0, m, 9).astype(int).tolist(),
+                       [-5, 0, m // 3, m // 3, m + 7], [m, m + 1]):
+            bt = torch.tensor(bounds, dtype=torch.int32, device=dev())
+            out = spl.coord_partition(B, bt)
+            ref = oracle.coord_partition(pos, crd, np.array(bounds, dtype=np.int32))
+            assert np.array_equal(out.cpu().numpy(), ref), (shape, bounds)
+            for c in range(len(bounds) - 1):
+                ra, S = oracle.spmv_window(ref[c], ref[c + 1], crd, host64(B.vals), host64(x))
+                for sc in (None, dict(kind="row", lanes_per_row=1), dict(kind="row", lanes_per_row=8),
+                           dict(kind="row", lanes_per_row=64)):
+                    a = spl.spmv_window(B, out[c], out[c + 1], x,
+                                        sched=spl.schedule(**sc) if sc else None)
+                    assert_close(host64(a), ra, S, RTOL[dtype], f"window {c} {bounds} {sc}")
+    with pytest.raises(spl.SpleafError, match="ROW"):
+        B = _csr(spl, *cases[-1][:3], cases[-1][3], torch.float64)
+        o = spl.coord_partition(B, torch.tensor([0, 10], dtype=torch.int32, device=dev()))
+        spl.spmv_window(B, o[0], o[1], torch.ones(B.shape[1], dtype=torch.float64, device=dev()),
+                        sched=spl.schedule("merge"))
+
+
 def test_merge_bounds_above_the_sweep_limit():
     # more than 8,000,000 rows: the merge split is found by a search per tile
     # (below, by a sweep over the rows); both must equal the oracle's split

@@ -255,6 +255,50 @@ def test_inner_order2():
     close(np.array([a]), np.array([brute.inner(Bd, Cd)]), np.array([S]), 1e-14)
 
 
+# ------------------------------------ value-range partition of a level ----
+
+@pytest.mark.parametrize("seed", range(12))
+def test_coord_partition_is_the_preimage_of_value_ranges(seed):
+    rs = np.random.RandomState(1300 + seed)
+    n, m = rs.randint(1, 30), rs.randint(1, 40)
+    pos, crd, vals = tiny.csr(rs, n, m, rs.uniform(0.0, 0.8), empty_rows={0})
+    ncolors = rs.randint(1, 6)
+    inner = np.sort(rs.randint(-3, m + 4, ncolors - 1))
+    bounds = np.concatenate([[rs.randint(-2, 1)], inner, [m + rs.randint(0, 3)]]).astype(np.int32)
+    out = oracle.coord_partition(pos, crd, bounds)
+    assert out.shape == (ncolors + 1, n)
+    for i in range(n):
+        for c in range(ncolors):
+            want = {p for p in range(pos[i], pos[i + 1]) if bounds[c] <= crd[p] < bounds[c + 1]}
+            assert set(range(out[c, i], out[c + 1, i])) == want, (i, c)
+    # the colors cover every stored coordinate once
+    assert np.array_equal(out[0], pos[:-1]) and np.array_equal(out[-1], pos[1:])
+
+
+def test_coord_partition_windows_sum_to_spmv():
+    rs = np.random.RandomState(77)
+    n, m = 40, 64
+    pos, crd, vals = tiny.csr(rs, n, m, 0.3, empty_rows={3, 39}, full_rows={5}, kind="int")
+    x = rs.randint(-3, 4, m).astype(np.float64)
+    bounds = np.array([0, 10, 10, 33, 50, 64], dtype=np.int32)  # one empty color
+    out = oracle.coord_partition(pos, crd, bounds)
+    total = np.zeros(n)
+    Bd, _ = brute.dense_csr(pos, crd, vals, (n, m))
+    for c in range(len(bounds) - 1):
+        a, _ = oracle.spmv_window(out[c], out[c + 1], crd, vals, x)
+        # the window of color c is B's column block [bounds[c], bounds[c+1])
+        blk = np.zeros_like(Bd)
+        blk[:, bounds[c]:bounds[c + 1]] = Bd[:, bounds[c]:bounds[c + 1]]
+        assert np.array_equal(a, brute.spmv(blk, x))
+        total += a
+    y, _ = oracle.spmv(pos, crd, vals, x)
+    assert np.array_equal(total, y)
+    # one color over all columns is the whole row
+    one = oracle.coord_partition(pos, crd, np.array([0, m], dtype=np.int32))
+    a, _ = oracle.spmv_window(one[0], one[1], crd, vals, x)
+    assert np.array_equal(a, y)
+
+
 # ------------------------------------- (Dense, Dense, Compressed) tensors --
 
 @pytest.mark.parametrize("seed", range(12))
