@@ -208,10 +208,10 @@ def measure_ddc(dev, spl, tuning, torch):
     C = c["C"].to(torch.float32)
     D = c["D"].to(torch.float32)
     M = torch.empty(I, R, dtype=torch.float32, device=dev)
-    ws = spl.workspace(spl.N.OP_MTTKRP, B, R)
     best, _ = tuning.search(lambda s: (lambda: spl.mttkrp(B, C, D, M, sched=s)),
                             tuning.MTTKRP_CANDIDATES, reps=3)
     sk = spl.schedule(**best)
+    ws = spl.workspace(spl.N.OP_MTTKRP, B, R, sk)  # holds the expanded Dense level too
     ms = tuning.time_call(lambda: spl.mttkrp(B, C, D, M, sched=sk, ws=ws), reps=10, warmup=3)
     nbytes = 4 * (F + 1) + 8 * nnz + 4 * (J + Kd) * R + 4 * I * R
     out["mttkrp_f32"] = _rate(ms, nbytes, 2 * R * (nnz + F))

@@ -67,6 +67,9 @@ typedef enum spl_dtype { SPL_F64 = 0, SPL_F32 = 1, SPL_BF16 = 2 } spl_dtype;
 
 typedef enum spl_level_format { SPL_DENSE = 0, SPL_COMPRESSED = 1 } spl_level_format;
 
+/* Element type of the pos arrays of a sparse operand. */
+typedef enum spl_index_type { SPL_I32 = 0, SPL_I64 = 1 } spl_index_type;
+
 /* How the leaf iteration space is cut into tiles (Sec. II-B, II-D, IV-C). */
 typedef enum spl_sched_kind {
     SPL_SCHED_DEFAULT = 0, /* library choice (merge split)                    */
@@ -101,7 +104,12 @@ typedef void *spl_stream; /* a hipStream_t; NULL is the null stream */
  * knows it; the library does not read it back).  For CSF, F = pos[1][dims[0]]
  * fibers is passed in nfibers; for (Dense, Dense, Compressed), nfibers must
  * be dims[0] * dims[1] and fiber f = i * dims[1] + j owns positions
- * [pos[2][f], pos[2][f+1]). */
+ * [pos[2][f], pos[2][f+1]).  pos_type SPL_I64: pos[l] holds the address of
+ * an int64 array (cast to the declared pointer type), so nnz may exceed
+ * 2^31 - 1 (a matrix that fills a large part of one GPU's memory); crd
+ * stays int32 (every dimension is below 2^31).  Only spl_spmv (CSR, MERGE
+ * schedule, variant 0) and its workspace query accept SPL_I64; every other
+ * call returns SPL_ERR_UNSUPPORTED for it. */
 typedef struct spl_sparse {
     int32_t order;          /* 2 (CSR) or 3 (CSF)                              */
     int32_t vtype;          /* spl_dtype of vals                               */
@@ -112,6 +120,7 @@ typedef struct spl_sparse {
     const void *vals;       /* device, nnz values of type vtype                */
     int64_t nnz;            /* stored values                                   */
     int64_t nfibers;        /* CSF only: entries of the middle level           */
+    int32_t pos_type;       /* spl_index_type of pos[] (0 = SPL_I32)           */
 } spl_sparse;
 
 /* A dense operand: vector (ndim 1) or row-major matrix (ndim 2). */

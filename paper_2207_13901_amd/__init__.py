@@ -48,7 +48,8 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 
 @dataclass
 class CSR:
-    """CSR matrix: pos int32[n+1], crd int32[nnz], vals[nnz]; shape (n, m)."""
+    """CSR matrix: pos int32[n+1] (or int64[n+1], accepted by spmv with the
+    merge schedule), crd int32[nnz], vals[nnz]; shape (n, m)."""
     pos: torch.Tensor
     crd: torch.Tensor
     vals: torch.Tensor
@@ -64,6 +65,7 @@ class CSR:
         s.crd[1] = _ptr(self.crd)
         s.vals = _ptr(self.vals)
         s.nnz = self.crd.numel()
+        s.pos_type = N.I64 if self.pos.dtype == torch.int64 else N.I32
         return s
 
     def with_vals(self, vals: torch.Tensor) -> "CSR":

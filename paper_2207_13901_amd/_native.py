@@ -16,6 +16,7 @@ OK, ERR_ARG, ERR_FORMAT, ERR_SHAPE, ERR_DTYPE, ERR_UNSUPPORTED, ERR_WORKSPACE, \
     ERR_NOMEM, ERR_HIP, ERR_INVALID = range(10)
 F64, F32, BF16 = 0, 1, 2
 DENSE, COMPRESSED = 0, 1
+I32, I64 = 0, 1
 SCHED_DEFAULT, ROW, NNZ, MERGE, SCHED_LEARNED, SCHED_AUTOTUNE = 0, 1, 2, 3, 4, 5
 OP_SPMV, OP_SPMM, OP_SPADD3, OP_SDDMM, OP_SPTTV, OP_MTTKRP, OP_INNER = range(7)
 
@@ -31,6 +32,7 @@ class SplSparse(ctypes.Structure):
         ("vals", ctypes.c_void_p),
         ("nnz", ctypes.c_int64),
         ("nfibers", ctypes.c_int64),
+        ("pos_type", ctypes.c_int32),
     ]
 
 

@@ -80,8 +80,14 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 bool valid_dtype(int dt) { return dt == SPL_F64 || dt == SPL_F32 || dt == SPL_BF16; }
 
-spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order) {
+// allow_i64: the caller handles int64 positions (SpMV only).
+spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order, bool allow_i64 = false) {
     if (!B) return fail(ctx, SPL_ERR_ARG, "sparse operand is NULL");
+    if (B->pos_type != SPL_I32 && B->pos_type != SPL_I64)
+        return fail(ctx, SPL_ERR_FORMAT, "unknown pos_type %d", B->pos_type);
+    if (B->pos_type == SPL_I64 && !allow_i64)
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "int64 positions are accepted by SpMV (CSR, MERGE schedule) only");
     if (B->order != order)
         return fail(ctx, SPL_ERR_FORMAT, "expected an order-%d sparse operand, got order %d", order,
                     B->order);
@@ -99,7 +105,8 @@ spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order) {
         if (B->dims[l] < 0 || B->dims[l] > kIndexMax)
             return fail(ctx, SPL_ERR_SHAPE, "dimension %d = %lld out of range", l,
                         static_cast<long long>(B->dims[l]));
-    if (B->nnz < 0 || B->nnz > kIndexMax)
+    const int64_t nnz_max = B->pos_type == SPL_I64 ? (int64_t{1} << 62) : kIndexMax;
+    if (B->nnz < 0 || B->nnz > nnz_max)
         return fail(ctx, SPL_ERR_SHAPE, "nnz = %lld out of range", static_cast<long long>(B->nnz));
     if (order == 3 && (B->nfibers < 0 || B->nfibers > kIndexMax))
         return fail(ctx, SPL_ERR_SHAPE, "nfibers = %lld out of range",
@@ -207,14 +214,18 @@ struct Carved {
     void *carry;
 };
 
-Carved carve(void *ws, int64_t ntiles) {
+// pos64: the tile positions are int64 (tiles.pos64), else int32 (tiles.pos).
+Carved carve(void *ws, int64_t ntiles, bool pos64 = false) {
     char *b = static_cast<char *>(ws);
     Carved c;
     c.tiles.ntiles = ntiles;
     c.tiles.row = reinterpret_cast<int32_t *>(b);
     b += align_up(static_cast<size_t>(ntiles + 1) * 4);
-    c.tiles.pos = reinterpret_cast<int32_t *>(b);
-    b += align_up(static_cast<size_t>(ntiles + 1) * 4);
+    if (pos64)
+        c.tiles.pos64 = reinterpret_cast<int64_t *>(b);
+    else
+        c.tiles.pos = reinterpret_cast<int32_t *>(b);
+    b += align_up(static_cast<size_t>(ntiles + 1) * (pos64 ? 8 : 4));
     c.carry = b;
     return c;
 }
@@ -352,14 +363,16 @@ int spmm_vec(const Plan &p, int vtype, const spl_dense *C, const spl_dense *A) {
     return ok ? v : 1;
 }
 
-size_t tiled_ws(const Pieces &q, int64_t ncols, size_t elem) {
-    return 2 * align_up(static_cast<size_t>(q.count + 1) * 4) +
+size_t tiled_ws(const Pieces &q, int64_t ncols, size_t elem, size_t pos_bytes = 4) {
+    return align_up(static_cast<size_t>(q.count + 1) * 4) +
+           align_up(static_cast<size_t>(q.count + 1) * pos_bytes) +
            align_up(static_cast<size_t>(q.blocks) * ncols * elem);
 }
 
 size_t spmv_ws(const spl_sparse *B, const Plan &p) {
     if (p.kind == SPL_ROW) return 0;
-    return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spmv_chunk(p)), 1, sizeof(double));
+    return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spmv_chunk(p)), 1, sizeof(double),
+                    B->pos_type == SPL_I64 ? 8 : 4);
 }
 
 size_t spmm_ws(const spl_sparse *B, int64_t N, const Plan &p) {
@@ -799,7 +812,7 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
     switch (op) {
     case SPL_OP_SPMV:
     case SPL_OP_SPMM: {
-        SPL_CHECK(check_sparse(ctx, B, 2));
+        SPL_CHECK(check_sparse(ctx, B, 2, op == SPL_OP_SPMV));
         // a selection kind needs room for whichever candidate it picks
         std::vector<spl_schedule> one;
         const std::vector<spl_schedule> *list = &one;
@@ -953,15 +966,20 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
                     spl_stream stream) {
     SPL_GUARD_BEGIN
     if (!ctx) return SPL_ERR_ARG;
-    SPL_CHECK(check_sparse(ctx, B, 2));
+    SPL_CHECK(check_sparse(ctx, B, 2, true));
     SPL_CHECK(check_dense(ctx, c, "c", 1, B->dims[1], -1));
     SPL_CHECK(check_dense(ctx, a, "a", 1, B->dims[0], -1));
     if (B->vtype == SPL_BF16 || c->dtype != B->vtype || a->dtype != B->vtype)
         return fail(ctx, SPL_ERR_DTYPE, "SpMV needs vals, c and a all F64 or all F32");
+    const bool pos64 = B->pos_type == SPL_I64;
+    if (pos64 && selection_kind(sched))
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "int64 positions: MERGE schedules only");
     spl_schedule chosen{};
     SPL_CHECK(select_schedule(ctx, SPL_OP_SPMV, B, c, a, sched, chosen, stream));
     Plan p;
     SPL_CHECK(resolve_spmv(ctx, B, sched, p));
+    if (pos64 && (p.kind != SPL_MERGE || p.variant != 0))
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "int64 positions: MERGE schedule, variant 0 only");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = B->dims[0];
@@ -977,7 +995,22 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmv_ws(B, p), &ws));
     const Pieces q = pieces_for(p, n, B->nnz, spmv_chunk(p));
-    Carved cv = carve(ws, q.count);
+    Carved cv = carve(ws, q.count, pos64);
+    if (pos64) {
+        const int64_t *pos = reinterpret_cast<const int64_t *>(B->pos[1]);
+        SPL_HIP(spl::launch_merge_bounds64(n, pos, B->nnz, q.size, cv.tiles, s),
+                "tile bounds launch");
+        LeafTimer tm(ctx, SPL_OP_SPMV, s);
+        SPL_HIP(spl::launch_spmv_flag64(B->vtype, p.items, n, pos, B->crd[1], B->vals, c->data,
+                                        a->data, cv.tiles, q.stride,
+                                        static_cast<double *>(cv.carry), s),
+                "SpMV tile launch");
+        tm.stop();
+        SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
+                                       static_cast<double *>(cv.carry), a->data, s),
+                "SpMV fix-up launch");
+        return SPL_OK;
+    }
     SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMV, s);

@@ -15,6 +15,7 @@ struct Tiles {
     int32_t *row;
     int32_t *pos;
     int64_t ntiles;
+    int64_t *pos64 = nullptr;  // in place of pos when the positions are int64
 };
 
 // ---- partition.hip -------------------------------------------------------
@@ -22,6 +23,9 @@ struct Tiles {
 int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size);
 // Fill `t` (row/pos arrays sized ntiles+1) for the split `kind` of the
 // Compressed level (rows, pos) with tile size `size`.
+// Merge split of a CSR with int64 positions: t.row and t.pos64.
+hipError_t launch_merge_bounds64(int64_t rows, const int64_t *pos, int64_t nnz, int64_t size,
+                                 const Tiles &t, hipStream_t s);
 hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_t nnz,
                               int64_t size, const Tiles &t, hipStream_t s);
 
@@ -36,6 +40,11 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos_b
 // exact_chunks: every piece of `t` is at most one chunk of 256 * items merged
 // items (merge split): the row-end flag leaf k_spmv_flag (variant 0) or the
 // row-end search leaf k_spmv_pipe (variant 1).
+// The row-end flag leaf over exact merge chunks of a CSR with int64
+// positions (tile bounds in t.row / t.pos64).
+hipError_t launch_spmv_flag64(int dtype, int items, int64_t n, const int64_t *pos,
+                              const int32_t *crd, const void *vals, const void *x, void *y,
+                              const Tiles &t, int64_t stride, double *carry, hipStream_t s);
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,
                              const int32_t *crd, const void *vals, const void *x, void *y,
                              const Tiles &t, int64_t stride, bool exact_chunks, int variant,

@@ -58,16 +58,17 @@ __global__ __launch_bounds__(kBlock) void k_nnz_bounds(int64_t rows, const int32
     trow[t] = static_cast<int32_t>(t == 0 ? 0 : rows_finished(pos, rows, p));
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const int32_t *pos,
+template <typename P, typename TP>
+__global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const P *pos,
                                                          int64_t nnz, int64_t M, int64_t ntiles,
-                                                         int32_t *trow, int32_t *tpos) {
+                                                         int32_t *trow, TP *tpos) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t > ntiles) return;
     int64_t total = rows + nnz;
     int64_t d = (t == ntiles || t * M > total) ? total : t * M;
     int64_t i = merge_search(d, rows, nnz, 0, [&](int64_t k) { return pos[k + 1]; });
     trow[t] = static_cast<int32_t>(i);
-    tpos[t] = static_cast<int32_t>(d - i);
+    tpos[t] = static_cast<TP>(d - i);
 }
 
 // The merge split by a sweep over the rows instead of a search per tile:
@@ -77,22 +78,23 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const int
 // ends before index d are those of rows 0 .. i-1).  The virtual row `rows`
 // owns the bounds at or past the end, (rows, nnz).  One lane per row; reading pos once costs
 // less than a 20-step dependent search per tile when rows are few.
-__global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const int32_t *pos,
+template <typename P, typename TP>
+__global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const P *pos,
                                                         int64_t nnz, int64_t M, int64_t ntiles,
-                                                        int32_t *trow, int32_t *tpos) {
+                                                        int32_t *trow, TP *tpos) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i > rows) return;
     if (i == rows) {  // every bound at or past the end: the last, and all when there are no items
         for (int64_t t = (rows + nnz + M - 1) / M; t <= ntiles; ++t) {
             trow[t] = static_cast<int32_t>(rows);
-            tpos[t] = static_cast<int32_t>(nnz);
+            tpos[t] = static_cast<TP>(nnz);
         }
         return;
     }
-    const int64_t lo = i + pos[i], hi = i + pos[i + 1];
+    const int64_t lo = i + static_cast<int64_t>(pos[i]), hi = i + static_cast<int64_t>(pos[i + 1]);
     for (int64_t t = (lo + M - 1) / M; t * M <= hi; ++t) {
         trow[t] = static_cast<int32_t>(i);
-        tpos[t] = static_cast<int32_t>(t * M - i);
+        tpos[t] = static_cast<TP>(t * M - i);
     }
 }
 
@@ -168,6 +170,18 @@ int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size) {
 // 4 (rows + 1) bytes); beyond, by one merge-path search per tile.
 constexpr int64_t kMergeSweepRows = 8000000;
 
+template <typename P, typename TP>
+hipError_t merge_bounds(int64_t rows, const P *pos, int64_t nnz, int64_t size, int64_t ntiles,
+                        int32_t *trow, TP *tpos, hipStream_t s) {
+    if (rows <= kMergeSweepRows)
+        k_merge_sweep<P, TP><<<dim3(static_cast<unsigned>(ceil_div(rows + 1, kBlock))), kBlock, 0,
+                               s>>>(rows, pos, nnz, size, ntiles, trow, tpos);
+    else
+        k_merge_bounds<P, TP><<<dim3(static_cast<unsigned>(ceil_div(ntiles + 1, kBlock))), kBlock,
+                                0, s>>>(rows, pos, nnz, size, ntiles, trow, tpos);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_t nnz,
                               int64_t size, const Tiles &t, hipStream_t s) {
     dim3 grid(static_cast<unsigned>((t.ntiles + 1 + kBlock - 1) / kBlock));
@@ -179,14 +193,14 @@ hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_
         k_nnz_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
         break;
     default:
-        if (rows <= kMergeSweepRows)
-            k_merge_sweep<<<dim3(static_cast<unsigned>(ceil_div(rows + 1, kBlock))), kBlock, 0, s>>>(
-                rows, pos, nnz, size, t.ntiles, t.row, t.pos);
-        else
-            k_merge_bounds<<<grid, kBlock, 0, s>>>(rows, pos, nnz, size, t.ntiles, t.row, t.pos);
-        break;
+        return merge_bounds(rows, pos, nnz, size, t.ntiles, t.row, t.pos, s);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_merge_bounds64(int64_t rows, const int64_t *pos, int64_t nnz, int64_t size,
+                                 const Tiles &t, hipStream_t s) {
+    return merge_bounds(rows, pos, nnz, size, t.ntiles, t.row, t.pos64, s);
 }
 
 }  // namespace spl

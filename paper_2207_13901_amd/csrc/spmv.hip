@@ -484,11 +484,16 @@ __device__ __forceinline__ double block_segmented_scan_dpp(double v, int key, in
 // an exclusive sum over the workgroup gives the rows finished before its
 // first item; its walk then needs no search and no row-end reads: a flagged
 // item finishes the open row, any other adds the next product.
-template <typename V, int ITEMS>
+//
+// P is the element type of pos and TP that of the tile positions (int32 or
+// int64).  Only the low 32 bits of a row end are loaded: its offset from the
+// chunk start is below 2^31, so the 32-bit difference of the low words is
+// exact.
+template <typename V, int ITEMS, typename P = int32_t, typename TP = int32_t>
 __global__ __launch_bounds__(kBlock) void k_spmv_flag(
-    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    int64_t n, const P *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
-    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
+    const int32_t *__restrict__ trow, const TP *__restrict__ tpos, int64_t npieces,
     int64_t stride, double *__restrict__ carry) {
     static_assert(ITEMS == 4 || ITEMS == 8, "flags are read as one 4- or 8-byte word");
     using Flags = typename std::conditional<ITEMS == 4, uint32_t, uint64_t>::type;
@@ -516,13 +521,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
     int e2[ITEMS], k2[ITEMS], e1[ITEMS];
     V v2[ITEMS], v1[ITEMS], x1[ITEMS];
     auto load = [&](int64_t bi, int64_t bp, int nr, int np) {
-        const auto rp = chunk_rsrc(pos + bi + 1, 4 * nr);
+        const auto rp = chunk_rsrc(pos + bi + 1, static_cast<int>(sizeof(P)) * nr);
         const auto rc = chunk_rsrc(crd + bp, 4 * np);
         const auto rv = chunk_rsrc(vals + bp, static_cast<int>(sizeof(V)) * np);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t k = static_cast<uint32_t>(tid + j * kBlock);
-            e2[j] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rp, k * 4, 0, 0));
+            e2[j] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(
+                rp, k * static_cast<uint32_t>(sizeof(P)), 0, 0));  // low word
             k2[j] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rc, k * 4, 0, kNtAux));
             v2[j] = chunk_load<V>(rv, k * static_cast<uint32_t>(sizeof(V)));
         }
@@ -543,7 +549,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int k = tid + j * kBlock;
-            s_flag[buf][k < nr ? k + static_cast<int>(e1[j] - bp) : kChunk] = 1;
+            const int rel = static_cast<int>(static_cast<uint32_t>(e1[j]) -
+                                             static_cast<uint32_t>(bp));
+            s_flag[buf][k < nr ? k + rel : kChunk] = 1;
             s_prod[buf][k < np ? k : kChunk] = to_f64(v1[j]) * to_f64(x1[j]);
         }
     };
@@ -695,6 +703,27 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos_b
                                          static_cast<const double *>(x), static_cast<double *>(y), s);
     return spmv_row_dispatch<float>(lanes, n, pos_b, pos_e, crd, static_cast<const float *>(vals),
                                     static_cast<const float *>(x), static_cast<float *>(y), s);
+}
+
+hipError_t launch_spmv_flag64(int dtype, int items, int64_t n, const int64_t *pos,
+                              const int32_t *crd, const void *vals, const void *x, void *y,
+                              const Tiles &t, int64_t stride, double *carry, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
+    auto go = [&](auto *v, auto *xx, auto *yy) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        if (items <= 4)
+            k_spmv_flag<V, 4, int64_t, int64_t><<<grid, kBlock, 0, s>>>(
+                n, pos, crd, v, xx, yy, t.row, t.pos64, t.ntiles, stride, carry);
+        else
+            k_spmv_flag<V, 8, int64_t, int64_t><<<grid, kBlock, 0, s>>>(
+                n, pos, crd, v, xx, yy, t.row, t.pos64, t.ntiles, stride, carry);
+        return hipGetLastError();
+    };
+    if (dtype == SPL_F64)
+        return go(static_cast<const double *>(vals), static_cast<const double *>(x),
+                  static_cast<double *>(y));
+    return go(static_cast<const float *>(vals), static_cast<const float *>(x),
+              static_cast<float *>(y));
 }
 
 hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos,

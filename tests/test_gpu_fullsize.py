@@ -181,3 +181,31 @@ def test_banded_weak_scaling_share_spmv_sampled():
                dict(kind="nnz", tile=4096, items_per_lane=8)):
         y = spl.spmv(B, c["x"], sched=spl.schedule(**sc))
         assert_close(host64(y[r]), ref, S, 1e-12, f"banded spmv {sc}")
+
+
+def test_spmv_int64_positions_past_2_31_sampled():
+    # the banded matrix at 62,000,000 rows: 2,169,999,694 nonzeros (26 GB in
+    # FP64 with int32 columns), so positions pass 2^31 and pos is int64
+    spl, tuning = _spl()
+    n = 62_000_000
+    c = configs.banded(device="cuda", n=n, pos_dtype=torch.int64)
+    nnz = int(c["crd"].numel())
+    assert nnz > 2**31
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    y = spl.spmv(B, c["x"])
+    rs = np.random.RandomState(3)
+    rows = np.unique(np.concatenate([rs.randint(0, n, 1500), [0, 1, n - 2, n - 1],
+                                     np.arange(61_400_000, 61_400_050)]))
+    pos = c["pos"].cpu().numpy()
+    assert pos[rows[-1]] > 2**31
+    lens = pos[rows + 1] - pos[rows]
+    idx = np.concatenate([np.arange(pos[r], pos[r + 1]) for r in rows])
+    it = torch.as_tensor(idx, device=c["crd"].device)
+    crd_s = c["crd"][it].cpu().numpy()
+    val_s = c["vals"][it].cpu().numpy()
+    pos_s = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ref, S = oracle.spmv(pos_s, crd_s, val_s, c["x"].cpu().numpy())
+    got = y[torch.as_tensor(rows, device=y.device)].cpu().numpy()
+    assert_close(got, ref, S, 1e-12, "int64 positions, sampled rows")
+    del B, c, y, it
+    torch.cuda.empty_cache()

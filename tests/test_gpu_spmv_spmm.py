@@ -123,6 +123,35 @@ def test_coord_partition_and_window_spmv(dtype):
                         sched=spl.schedule("merge"))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spmv_int64_positions(dtype):
+    # the same matrices with int64 pos: the merge split and the flag leaf
+    # read 8-byte row ends and int64 tile positions
+    spl = _spl()
+    cases = list(_edge_cases().values())
+    c2 = configs.config2(scale=0.002, with_dense=False)
+    cases.append((c2["pos"].numpy(), c2["crd"].numpy(), c2["vals"].numpy(), (c2["n"], c2["n"])))
+    scheds = [None, dict(kind="merge"), dict(kind="merge", tile=1024, items_per_lane=4),
+              dict(kind="merge", tile=8192, items_per_lane=4),
+              dict(kind="merge", tile=6000, items_per_lane=8)]
+    rs = np.random.RandomState(8)
+    for pos, crd, vals, shape in cases:
+        B = _csr(spl, pos, crd, vals, shape, dtype)
+        B64 = spl.CSR(B.pos.to(torch.int64), B.crd, B.vals, shape)
+        x = torch.as_tensor(rs.uniform(-1, 1, shape[1]), device=dev()).to(dtype)
+        ref, S = oracle.spmv(pos, crd, host64(B.vals), host64(x))
+        for sc in scheds:
+            y = spl.spmv(B64, x, sched=spl.schedule(**sc) if sc else None)
+            assert_close(host64(y), ref, S, RTOL[dtype], f"int64 pos {shape} {sc}")
+    x = torch.ones(B64.shape[1], dtype=dtype, device=dev())
+    for bad in (dict(kind="row"), dict(kind="nnz"), dict(kind="merge", variant=1),
+                dict(kind="learned")):
+        with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
+            spl.spmv(B64, x, sched=spl.schedule(**bad))
+    with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
+        spl.spmm(B64, torch.ones(B64.shape[1], 8, dtype=dtype, device=dev()))
+
+
 def test_merge_bounds_above_the_sweep_limit():
     # more than 8,000,000 rows: the merge split is found by a search per tile
     # (below, by a sweep over the rows); both must equal the oracle's split

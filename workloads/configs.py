@@ -131,9 +131,10 @@ def config4(device="cpu", scale=1.0, R=32, kind_vals="unit", with_dense=True):
     return out
 
 
-def banded(device="cpu", n=20_000_000, half_width=17, kind="sym"):
+def banded(device="cpu", n=20_000_000, half_width=17, kind="sym", pos_dtype=torch.int32):
     """Banded CSR (config 6): row i holds columns max(0, i - w) ..
-    min(n - 1, i + w); values and the vector in float64."""
+    min(n - 1, i + w); values and the vector in float64.  pos_dtype
+    torch.int64 keeps positions past 2^31 (n above about 61 million)."""
     dev = _dev(device)
     w = int(half_width)
     i = torch.arange(n, dtype=torch.int64, device=dev)
@@ -149,7 +150,7 @@ def banded(device="cpu", n=20_000_000, half_width=17, kind="sym"):
     del row, lo, deg
     vals = gen.values(gen.key_for(6, 1), nnz, dev, kind)
     x = gen.values(gen.key_for(6, 2), n, dev, kind)
-    return dict(n=n, m=n, pos=pos.to(torch.int32), crd=crd, vals=vals, x=x, half_width=w)
+    return dict(n=n, m=n, pos=pos.to(pos_dtype), crd=crd, vals=vals, x=x, half_width=w)
 
 
 def ddc(device="cpu", scale=1.0, R=32, I=46, with_dense=True):
