@@ -135,6 +135,28 @@ def measure_banded(dev, spl, tuning, torch):
     return out
 
 
+def measure_banded64(dev, spl, tuning, torch, n=62_000_000):
+    """The banded matrix at 62,000,000 rows (2,169,999,694 nonzeros, 26 GB in
+    FP64): positions pass 2^31, so pos is int64; merge schedules only."""
+    from workloads import configs
+    print("[bench] generating the 2.17e9-nonzero banded matrix", file=sys.stderr, flush=True)
+    c = configs.banded(device=dev, n=n, pos_dtype=torch.int64)
+    nnz = int(c["crd"].numel())
+    B = spl.CSR(c["pos"], c["crd"], c["vals"], (n, n))
+    x = c["x"]
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    cands = ([dict(kind="merge", tile=T, items_per_lane=4) for T in (4096, 16384)] +
+             [dict(kind="merge", tile=T, items_per_lane=8) for T in (8192, 32768)])
+    best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
+    ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
+    out = _rate(ms, 8 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)
+    out.update(schedule=best, n=n, nnz=nnz, pos="int64",
+               schedules_ms={json.dumps(c, sort_keys=True): round(t, 4) for c, t in res})
+    del B, c, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
     """The value-range partition of the power-law matrix's columns into
     eight equal blocks (one kernel), and the SpMV as the sum of the eight
@@ -318,6 +340,7 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
         res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
         res["ddc"] = measure_ddc(dev, spl, tuning, torch)
         res["coord_partition"] = measure_coord_partition(dev, spl, tuning, torch)
+        res["spmv_banded_int64_f64"] = measure_banded64(dev, spl, tuning, torch)
     res["workloads"] = {
         "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
         "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",
