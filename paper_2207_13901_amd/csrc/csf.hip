@@ -228,6 +228,15 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     __shared__ int s_done[G];
     __shared__ int s_a0[G];
     __shared__ int64_t s_next[2];
+    // cross-group combine: the tile's columns split over kParts parts of
+    // G / kParts groups each
+    constexpr int NC = W * VEC;
+    constexpr int kParts = kBlock / NC;
+    constexpr int kGroupsPerPart = G / kParts;
+    static_assert(kParts * NC == kBlock && kGroupsPerPart * kParts == G, "combine layout");
+    __shared__ Acc s_open[NC];  // the open row's partial entering the chunk
+    __shared__ Acc s_pb[kParts][NC];
+    __shared__ int s_pa[kParts];
 
     const int tid = threadIdx.x;
     const int g = tid / W, lane = tid % W;
@@ -237,9 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t piece = static_cast<int64_t>(blockIdx.x) * stride;
     const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
     int64_t ci = tslice[piece], cf = tfib[piece];
-    Acc open[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) open[v] = 0;
+    if (tid < NC) s_open[tid] = 0;
 
     while (piece < piece_end) {
         const int64_t next = chunk_end(pos1, tslice, tfib, piece, ci, cf, kChunk, s_next);
@@ -349,29 +356,45 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         }
         __syncthreads();
 
-        if (g == 0) {
-            for (int gg = 0; gg < G; ++gg) {
+        // Combine across groups, in group order: a group that finished a
+        // slice writes it as (partial entering the group) + its head and
+        // restarts the partial from its tail; any other group adds its tail.
+        // Each thread takes one column of one part: it composes its part's
+        // groups, then starts from the partials of the parts before it.
+        {
+            const int col = tid % NC, part = tid / NC;
+            const int64_t gcol = static_cast<int64_t>(blockIdx.y) * NC + col;
+            int pa = 1;
+            Acc pb = 0;
+            for (int k = 0; k < kGroupsPerPart; ++k) {
+                const int gg = part * kGroupsPerPart + k;
+                const Acc t = s_tail[gg][col];
+                pb = s_done[gg] > 0 ? t : pb + t;
+                pa = s_done[gg] > 0 ? 0 : pa;
+            }
+            s_pb[part][col] = pb;
+            if (col == 0) s_pa[part] = pa;
+            Acc o = s_open[col];
+            __syncthreads();
+            for (int q = 0; q < part; ++q) o = s_pa[q] ? o + s_pb[q][col] : s_pb[q][col];
+            for (int k = 0; k < kGroupsPerPart; ++k) {
+                const int gg = part * kGroupsPerPart + k;
                 if (s_done[gg] > 0) {
-                    Acc out[VEC];
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        out[v] = open[v] + s_head[gg][lane * VEC + v];
-                        open[v] = s_tail[gg][lane * VEC + v];
-                    }
-                    if (colok) store_row<VEC>(A + (ci + s_a0[gg]) * lda + col0, out);
+                    if (gcol < R) A[(ci + s_a0[gg]) * lda + gcol] = o + s_head[gg][col];
+                    o = s_tail[gg][col];
                 } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) open[v] += s_tail[gg][lane * VEC + v];
+                    o += s_tail[gg][col];
                 }
             }
+            if (part == kParts - 1) s_open[col] = o;
         }
         ci = ei;
         cf = ef;
         __syncthreads();
     }
-    if (g == 0 && colok) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) carry[static_cast<int64_t>(blockIdx.x) * R + col0 + v] = open[v];
+    if (tid < NC) {
+        const int64_t gcol = static_cast<int64_t>(blockIdx.y) * NC + tid;
+        if (gcol < R) carry[static_cast<int64_t>(blockIdx.x) * R + gcol] = s_open[tid];
     }
 }
 
