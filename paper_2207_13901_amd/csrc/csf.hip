@@ -249,8 +249,15 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     if (tid < NC) s_open[tid] = 0;
 
     while (piece < piece_end) {
-        const int64_t next = chunk_end(pos1, tslice, tfib, piece, ci, cf, kChunk, s_next);
-        const int64_t ei = s_next[0], ef = s_next[1];
+        // a piece that ends within this chunk needs no search, so no
+        // barrier (every thread sees the same bounds; the loop's closing
+        // barrier orders the reuse of the staging arrays)
+        int64_t ei = tslice[piece + 1], ef = tfib[piece + 1], next = piece + 1;
+        if (ei + ef - ci - cf > kChunk) {
+            next = chunk_end(pos1, tslice, tfib, piece, ci, cf, kChunk, s_next);
+            ei = s_next[0];
+            ef = s_next[1];
+        }
         piece = next;
         const int nr = static_cast<int>(ei - ci), nf = static_cast<int>(ef - cf);
         for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
