@@ -203,11 +203,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
 // lane reads back only what it wrote, so no barrier): the group walks its
 // positions in order, closing a fiber when the walk passes the fiber's end
 // (acc += C(j_f, :) * t, the C row read from the slab) and finishing every
-// slice that ends before the fiber it is about to close.  (Two variants
-// measured slower on the 1e8-nonzero tensor and are not kept: prefetching
-// the next chunk's slice ends, fibers and fiber starts behind the current
-// walk, 6.3 ms against 5.7 ms, and the same walk factored into a device
-// function with the LDS slabs in one struct, 6.4 ms.)
+// slice that ends before the fiber it is about to close.  The next chunk's
+// slice ends, fiber coordinates and fiber starts (one of each per thread)
+// are loaded right after this chunk's gathers are issued, and the groups'
+// heads and tails are combined by all threads at once (a column of a part
+// each), so a chunk costs one barrier-separated round of gathers.
 template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
@@ -247,6 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     const int64_t piece_end = piece + stride < npieces ? piece + stride : npieces;
     int64_t ci = tslice[piece], cf = tfib[piece];
     if (tid < NC) s_open[tid] = 0;
+    // this thread's share of the next chunk's slice ends, fiber coordinates
+    // and fiber starts, loaded behind the current chunk's gathers
+    int32_t pre_e = 0, pre_j = 0, pre_f = 0, pre_f2 = 0;
+    bool have = false;
 
     while (piece < piece_end) {
         // a piece that ends within this chunk needs no search, so no
@@ -260,9 +264,17 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         }
         piece = next;
         const int nr = static_cast<int>(ei - ci), nf = static_cast<int>(ef - cf);
-        for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
-        for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
-        for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+        if (have) {
+            if (tid < nr) s_end[tid] = pre_e;
+            if (tid < nf) s_j[tid] = pre_j;
+            if (tid <= nf) s_fp[tid] = pre_f;
+            if constexpr (kChunk >= kBlock)  // nf + 1 entries: one more than lanes
+                if (tid == 0 && nf == kBlock) s_fp[kBlock] = pre_f2;
+        } else {
+            for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
+            for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
+            for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+        }
         __syncthreads();
 
         const int total = nr + nf;
@@ -302,6 +314,21 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             for (int v = 0; v < VEC; ++v) dv[q][v] = 0;
             if (q < np && colok)
                 load_row<VEC>(D + static_cast<int64_t>(kq[q]) * ldd + col0, dv[q]);
+        }
+        // the next chunk's staging, when it is a whole piece (no search):
+        // issued after this chunk's gathers, it lands while they are used
+        have = false;
+        if (piece < piece_end) {
+            const int64_t nei = tslice[piece + 1], nef = tfib[piece + 1];
+            if (nei + nef - ei - ef <= kChunk) {
+                const int nnr = static_cast<int>(nei - ei), nnf = static_cast<int>(nef - ef);
+                if (tid < nnr) pre_e = pos1[ei + 1 + tid];
+                if (tid < nnf) pre_j = crd1[ef + tid];
+                if (tid <= nnf) pre_f = pos2[ef + tid];
+                if constexpr (kChunk >= kBlock)
+                    if (tid == 0 && nnf == kBlock) pre_f2 = pos2[ef + kBlock];
+                have = true;
+            }
         }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
