@@ -207,7 +207,12 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
 // slice ends, fiber coordinates and fiber starts (one of each per thread)
 // are loaded right after this chunk's gathers are issued, and the groups'
 // heads and tails are combined by all threads at once (a column of a part
-// each), so a chunk costs one barrier-separated round of gathers.
+// each), so a chunk costs one barrier-separated round of gathers.  With
+// BF16 factors the chunk's first 512 positions (k and value) are staged in
+// LDS with the chunk, so the D-row gathers wait on LDS rather than on a
+// load from HBM (7.2 -> 6.4 ms on the 1e8-nonzero tensor); with FP32 the
+// registers this needs would cost a wave per SIMD, so FP32 keeps the direct
+// loads.
 template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
@@ -218,7 +223,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int64_t stride, Acc *__restrict__ carry) {
     constexpr int G = kBlock / W;
     constexpr int kChunk = G * ITEMS;
-    constexpr int kPosCap = ITEMS + ITEMS / 2;  // keeps 3 waves per SIMD
+    // BF16 factors stage the chunk's leading positions in LDS (below); FP32
+    // keeps more positions per group in registers instead (both measured
+    // best that way at 3 waves per SIMD)
+    constexpr bool kStage = sizeof(FT) == 2;
+    constexpr int kPosCap = kStage ? ITEMS + ITEMS / 4 : ITEMS + ITEMS / 2;
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];
@@ -235,6 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     constexpr int kGroupsPerPart = G / kParts;
     static_assert(kParts * NC == kBlock && kGroupsPerPart * kParts == G, "combine layout");
     __shared__ Acc s_open[NC];  // the open row's partial entering the chunk
+    // the chunk's first kStagePos positions (k and value), staged with the
+    // chunk so that the D-row gathers wait on LDS, not on HBM
+    constexpr int kStagePos = kStage ? 2 * kBlock : 0;
+    __shared__ int32_t s_kq[kStage ? kStagePos : 1];
+    __shared__ Acc s_vq[kStage ? kStagePos : 1];
     __shared__ Acc s_pb[kParts][NC];
     __shared__ int s_pa[kParts];
 
@@ -250,6 +264,9 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     // this thread's share of the next chunk's slice ends, fiber coordinates
     // and fiber starts, loaded behind the current chunk's gathers
     int32_t pre_e = 0, pre_j = 0, pre_f = 0, pre_f2 = 0;
+    int32_t pre_k[2] = {0, 0};
+    V pre_v[2] = {};
+    int64_t pre_np = 0;
     bool have = false;
 
     while (piece < piece_end) {
@@ -270,10 +287,27 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             if (tid <= nf) s_fp[tid] = pre_f;
             if constexpr (kChunk >= kBlock)  // nf + 1 entries: one more than lanes
                 if (tid == 0 && nf == kBlock) s_fp[kBlock] = pre_f2;
+            if constexpr (kStage) {
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int k = tid + jj * kBlock;
+                    if (k < pre_np && k < kStagePos) {
+                        s_kq[k] = pre_k[jj];
+                        s_vq[k] = widen<Acc>(pre_v[jj]);
+                    }
+                }
+            }
         } else {
             for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
             for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
             for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+            if constexpr (kStage) {
+                const int64_t p0 = pos2[cf], npb = pos2[ef] - p0;
+                for (int k = tid; k < npb && k < kStagePos; k += kBlock) {
+                    s_kq[k] = crd2[p0 + k];
+                    s_vq[k] = widen<Acc>(vals[p0 + k]);
+                }
+            }
         }
         __syncthreads();
 
@@ -298,13 +332,20 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         }
         int kq[kPosCap];
         Acc vq[kPosCap];
+        // the group's first position within the chunk (staged positions)
+        const int64_t rel0 = kStage ? P0 - s_fp[0] : 0;
 #pragma unroll
         for (int q = 0; q < kPosCap; ++q) {
             kq[q] = 0;
             vq[q] = 0;
             if (q < np) {
-                kq[q] = load_stream(crd2 + P0 + q);
-                vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+                if (kStage && rel0 + q < kStagePos) {
+                    kq[q] = s_kq[rel0 + q];
+                    vq[q] = s_vq[rel0 + q];
+                } else {
+                    kq[q] = load_stream(crd2 + P0 + q);
+                    vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+                }
             }
         }
         Acc dv[kPosCap][VEC];
@@ -327,6 +368,18 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
                 if (tid <= nnf) pre_f = pos2[ef + tid];
                 if constexpr (kChunk >= kBlock)
                     if (tid == 0 && nnf == kBlock) pre_f2 = pos2[ef + kBlock];
+                if constexpr (kStage) {
+                    const int64_t pp0 = pos2[ef];
+                    pre_np = pos2[nef] - pp0;
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        const int kk = tid + jj * kBlock;
+                        if (kk < pre_np && kk < kStagePos) {
+                            pre_k[jj] = load_stream(crd2 + pp0 + kk);
+                            pre_v[jj] = load_stream(vals + pp0 + kk);
+                        }
+                    }
+                }
                 have = true;
             }
         }
@@ -373,9 +426,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         for (int q = kPosCap; q < np; ++q) {  // positions past the register cap
             while (P0 + q >= s_fp[f + 1]) close_fiber();
             if (colok) {
+                const bool staged = kStage && rel0 + q < kStagePos;
+                const int32_t kk = staged ? s_kq[rel0 + q] : load_stream(crd2 + P0 + q);
                 Acc d[VEC];
-                load_row<VEC>(D + static_cast<int64_t>(load_stream(crd2 + P0 + q)) * ldd + col0, d);
-                const Acc vv = widen<Acc>(load_stream(vals + P0 + q));
+                load_row<VEC>(D + static_cast<int64_t>(kk) * ldd + col0, d);
+                const Acc vv = staged ? s_vq[rel0 + q] : widen<Acc>(load_stream(vals + P0 + q));
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) t[v] += vv * d[v];
             }
