@@ -203,6 +203,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     __shared__ Acc s_tail[G][W * VEC];
     __shared__ int s_done[G];
     __shared__ int s_a0[G];
+    // cross-group combine: the tile's columns split over kParts parts of
+    // G / kParts groups each
+    constexpr int NC = W * VEC;
+    constexpr int kParts = kBlock / NC;
+    constexpr int kGroupsPerPart = G / kParts;
+    static_assert(kParts * NC == kBlock && kGroupsPerPart * kParts == G, "combine layout");
+    __shared__ Acc s_open[NC];  // the open row's partial entering the chunk
+    __shared__ Acc s_pb[kParts][NC];
+    __shared__ int s_pa[kParts];
 
     const int tid = threadIdx.x;
     const int g = tid / W, lane = tid % W;
@@ -247,9 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     int nr = static_cast<int>(ei - ci), np = static_cast<int>(ep - cp);
     fetch(ci, cp, nr, np);
     stash(0, nr, np);
-    Acc open[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) open[v] = 0;
+    if (tid < NC) s_open[tid] = 0;
     int buf = 0;
     for (int64_t c = p0; c < pend; ++c) {
         __syncthreads();  // buffer `buf` holds chunk c; the previous pass is done
@@ -308,21 +315,38 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
             s_a0[g] = a0;
         }
         __syncthreads();
-        if (g == 0) {
-            for (int gg = 0; gg < G; ++gg) {
+        // Combine across groups, in group order: a group that finished a row
+        // writes it as (partial entering the group) + its head and restarts
+        // the partial from its tail; any other group adds its tail.  Each
+        // thread takes one column of one part: it composes its part's
+        // groups, then starts from the partials of the parts before it.
+        {
+            const int cc = tid % NC, part = tid / NC;
+            const int64_t gcol = static_cast<int64_t>(blockIdx.y) * NC + cc;
+            int pa = 1;
+            Acc pb = 0;
+            for (int k = 0; k < kGroupsPerPart; ++k) {
+                const int gg = part * kGroupsPerPart + k;
+                const Acc t = s_tail[gg][cc];
+                pb = s_done[gg] > 0 ? t : pb + t;
+                pa = s_done[gg] > 0 ? 0 : pa;
+            }
+            s_pb[part][cc] = pb;
+            if (cc == 0) s_pa[part] = pa;
+            Acc o = s_open[cc];
+            __syncthreads();
+            for (int q = 0; q < part; ++q) o = s_pa[q] ? o + s_pb[q][cc] : s_pb[q][cc];
+            for (int k = 0; k < kGroupsPerPart; ++k) {
+                const int gg = part * kGroupsPerPart + k;
                 if (s_done[gg] > 0) {
-                    Acc out[VEC];
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        out[v] = open[v] + s_head[gg][lane * VEC + v];
-                        open[v] = s_tail[gg][lane * VEC + v];
-                    }
-                    if (colok) store_row<VEC>(Out + (ci + s_a0[gg]) * ldo + col0, out);
+                    if (gcol < N)
+                        store_stream(Out + (ci + s_a0[gg]) * ldo + gcol, narrow<OT>(o + s_head[gg][cc]));
+                    o = s_tail[gg][cc];
                 } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) open[v] += s_tail[gg][lane * VEC + v];
+                    o += s_tail[gg][cc];
                 }
             }
+            if (part == kParts - 1) s_open[cc] = o;
         }
         if (more) stash(buf ^ 1, nnr, nnp);
         ci = ei;
@@ -335,9 +359,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         np = nnp;
         buf ^= 1;
     }
-    if (g == 0 && colok) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) carry[static_cast<int64_t>(blockIdx.x) * N + col0 + v] = open[v];
+    __syncthreads();  // the last part's s_open
+    if (tid < NC) {
+        const int64_t gcol = static_cast<int64_t>(blockIdx.y) * NC + tid;
+        if (gcol < N) carry[static_cast<int64_t>(blockIdx.x) * N + gcol] = s_open[tid];
     }
 }
 
