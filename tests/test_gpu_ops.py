@@ -449,3 +449,24 @@ def test_ddc_errors():
     bad = spl.DDC(B.pos2, torch.flip(B.crd2, [0]).contiguous(), B.vals, B.shape)
     with pytest.raises(spl.SpleafError, match="INVALID"):
         spl.validate(bad)
+
+
+def test_csf_leaves_deterministic():
+    # fixed reduction orders everywhere (no floating-point atomics): a second
+    # call gives the same bits
+    spl = _spl()
+    c = _numpy(configs.config4(scale=0.001, R=32))
+    for dtype in (torch.float32, torch.bfloat16):
+        B = _csf(spl, c, dtype)
+        C = _t(c["C"], torch.float64).to(torch.float32).to(dtype)
+        D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
+        for sc in MTTKRP_SCHEDULES:
+            a1 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc)).clone()
+            a2 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+            assert torch.equal(a1, a2), (dtype, sc)
+    B = _csf(spl, c, torch.float32)
+    cv = _t(np.linspace(-1, 1, c["K"]), torch.float64).to(torch.float32)
+    for sc in TTV_SCHEDULES:
+        a1 = spl.spttv(B, cv, sched=spl.schedule(**sc)).clone()
+        a2 = spl.spttv(B, cv, sched=spl.schedule(**sc))
+        assert torch.equal(a1, a2), sc
