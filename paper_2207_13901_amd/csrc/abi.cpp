@@ -507,8 +507,8 @@ constexpr int64_t kInnerParts = 2048;
 // pattern partials or the general co-iteration's per-workgroup partials.
 size_t inner_ws(const spl_sparse *B) {
     const int64_t units = B->order == 2 ? B->nnz : B->nfibers;
-    return align_up(static_cast<size_t>(std::max(kInnerParts, spl::inner_general_parts(units))) *
-                    sizeof(double));
+    return align_up(std::max(static_cast<size_t>(kInnerParts) * sizeof(double),
+                             spl::inner_general_ws(units)));
 }
 
 size_t spadd3_ws(int64_t n) {
@@ -1270,7 +1270,7 @@ spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                     B->vtype, order, B->dims[0], o3 ? B->nfibers : B->nnz, B->pos[1], B->crd[1],
                     o3 ? B->pos[2] : nullptr, o3 ? B->crd[2] : nullptr, B->vals, C->pos[1],
                     C->crd[1], o3 ? C->pos[2] : nullptr, o3 ? C->crd[2] : nullptr, C->vals,
-                    static_cast<double *>(ws), out, s),
+                    ws, out, s),
                 "inner product launch");
     }
     tm.stop();

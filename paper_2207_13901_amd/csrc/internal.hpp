@@ -98,14 +98,16 @@ hipError_t launch_inner_final(int64_t nparts, const double *part, double *out, h
 
 // ---- inner.hip -----------------------------------------------------------
 // Inner product of operands with different patterns (order 2: units are B's
-// positions, n rows; order 3: units are B's fibers, n slices); `part` holds
-// inner_general_parts(units) doubles.
+// positions, n rows; order 3: units are B's fibers, n slices); the workspace
+// `ws` holds inner_general_ws(units) bytes (per-workgroup partials and range
+// bounds).
 int64_t inner_general_parts(int64_t units);
+size_t inner_general_ws(int64_t units);
 hipError_t launch_inner_general(int vtype, int order, int64_t n, int64_t units,
                                 const int32_t *bpos, const int32_t *bcrd, const int32_t *bpos2,
                                 const int32_t *bcrd2, const void *bv, const int32_t *cpos,
                                 const int32_t *ccrd, const int32_t *cpos2, const int32_t *ccrd2,
-                                const void *cv, double *part, double *out, hipStream_t s);
+                                const void *cv, void *ws, double *out, hipStream_t s);
 
 // ---- sddmm.hip -----------------------------------------------------------
 int64_t sddmm_chunk();

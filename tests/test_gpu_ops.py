@@ -348,6 +348,55 @@ def test_inner_product_general_patterns(dtype):
     assert float(spl.inner(Z, A1).item()) == 0.0 and float(spl.inner(A1, Z).item()) == 0.0
 
 
+def _rows_csr(rows, ncols, rs, dtype):
+    """CSR from a list of sorted column lists, uniform[-1, 1] values."""
+    pos = np.zeros(len(rows) + 1, np.int64)
+    pos[1:] = np.cumsum([len(r) for r in rows])
+    crd = np.array([c for r in rows for c in r], np.int32)
+    vals = rs.uniform(-1, 1, len(crd))
+    return (pos.astype(np.int32), crd, vals)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inner_general_staging_limits(dtype):
+    """The co-iteration's LDS staging and its HBM-search fallback agree with the
+    oracle: a range of 2048 units over more parents than the workgroup stages,
+    a C segment longer than the staged coordinates, and a long C segment whose
+    matching part is short enough to stage (clipped at both ends)."""
+    spl = _spl()
+    rs = np.random.RandomState(33)
+    cases = []
+    # one unit per parent: every 2048-unit range spans 2048 parents
+    n, m = 6000, 300
+    b_rows = [[int(rs.randint(m))] for _ in range(n)]
+    c_rows = [sorted(rs.choice(m, size=rs.randint(0, 40), replace=False).tolist()) for _ in range(n)]
+    for i in range(0, n, 3):  # make a third of them match
+        if b_rows[i][0] not in c_rows[i]:
+            c_rows[i] = sorted(c_rows[i] + b_rows[i])
+    cases.append((b_rows, c_rows, m))
+    # B: the first and the last column of a row; C: the full row of 10,000
+    m = 10000
+    b_rows = [[0, m - 1], [5, 7], [], [m - 2]]
+    c_rows = [list(range(m)), list(range(0, m, 2)), list(range(m)), list(range(1, m, 3))]
+    cases.append((b_rows, c_rows, m))
+    # B: a middle window of a long row; C: the full row (the staged part is clipped)
+    b_rows = [list(range(4000, 4100)), list(range(0, 3000, 7))]
+    c_rows = [list(range(m)), list(range(m))]
+    cases.append((b_rows, c_rows, m))
+    for b_rows, c_rows, m in cases:
+        bh, ch = _rows_csr(b_rows, m, rs, dtype), _rows_csr(c_rows, m, rs, dtype)
+        n = len(b_rows)
+        B = spl.CSR(_t(bh[0]), _t(bh[1]), _t(bh[2], torch.float64).to(dtype), (n, m))
+        C = spl.CSR(_t(ch[0]), _t(ch[1]), _t(ch[2], torch.float64).to(dtype), (n, m))
+        bh = (bh[0], bh[1], None, None, host64(B.vals))
+        ch = (ch[0], ch[1], None, None, host64(C.vals))
+        ref, S = oracle.inner(bh, ch)
+        assert_close(host64(spl.inner(B, C)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "inner general CSR staging")
+        assert_close(host64(spl.inner(C, B)), np.array([ref]), np.array([S]), RTOL[dtype],
+                     "inner general CSR staging, swapped")
+
+
 # ------------------------------------------- (Dense, Dense, Compressed) -----
 
 def _ddc(spl, c, dtype, vals_key="vals"):
