@@ -32,12 +32,14 @@ constexpr int kParents = 1024;   // parents staged per workgroup
 constexpr int kCStage = 4096;    // C coordinates staged per workgroup
 constexpr int kUnitIters = 8;    // units per lane
 
-// Largest r in [lo, hi) with pos[r] <= u (the parent holding unit u).
-template <typename P>
-__device__ __forceinline__ int64_t parent_of(const P &pos, int64_t lo, int64_t hi, int64_t u) {
+// Largest r in [lo, hi) with pos[r] <= u (the parent holding unit u); I is
+// the index type (32-bit where the indices are LDS offsets, fewer VALU
+// instructions a step).
+template <typename I, typename P>
+__device__ __forceinline__ I parent_of(const P &pos, I lo, I hi, I u) {
     while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (static_cast<int64_t>(pos(mid)) <= u)
+        const I mid = (lo + hi) >> 1;
+        if (static_cast<I>(pos(mid)) <= u)
             lo = mid;
         else
             hi = mid;
@@ -61,10 +63,10 @@ __device__ __forceinline__ int64_t bound_sorted(const int32_t *__restrict__ crd,
 }
 
 // Position of coordinate j in the sorted crd[lo, hi), or -1.
-template <typename C>
-__device__ __forceinline__ int64_t find_sorted(const C &crd, int64_t lo, int64_t hi, int32_t j) {
+template <typename I, typename C>
+__device__ __forceinline__ I find_sorted(const C &crd, I lo, I hi, int32_t j) {
     while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
+        const I mid = (lo + hi) >> 1;
         const int32_t v = crd(mid);
         if (v == j) return mid;
         if (v < j)
@@ -93,11 +95,11 @@ __global__ __launch_bounds__(kBlock) void k_inner_bounds(int64_t n, int64_t unit
     auto gpos = [&](int64_t r) { return bpos[r]; };
     int64_t ra = 0, ca = 0, rb = 0, cb = 0;
     if (ub < units) {
-        ra = parent_of(gpos, 0, n, ub);
+        ra = parent_of<int64_t>(gpos, 0, n, ub);
         ca = bound_sorted<false>(ccrd, cpos[ra], cpos[ra + 1], bcrd[ub]);
     }
     if (ub > 0) {
-        rb = parent_of(gpos, 0, n, ub - 1);
+        rb = parent_of<int64_t>(gpos, 0, n, ub - 1);
         cb = bound_sorted<true>(ccrd, cpos[rb], cpos[rb + 1], bcrd[ub - 1]);
     }
     bnd[4 * b] = ra;
@@ -116,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_general(
     __shared__ int32_t s_pos[kParents + 1];   // B's parent pos entries of the range
     __shared__ int32_t s_cpos[kParents + 1];  // C's
     __shared__ int32_t s_ccrd[kCStage];       // C's coordinates that can match
-    __shared__ double s_sum[kBlock];
+    __shared__ double s_sum[kBlock / kWave];
+    static_assert(kBlock / kWave == 4, "four waves per workgroup");
     const int64_t u0 = static_cast<int64_t>(blockIdx.x) * (kBlock * kUnitIters);
     const int64_t u1 = u0 + kBlock * kUnitIters < units ? u0 + kBlock * kUnitIters : units;
     auto gpos = [&](int64_t r) { return bpos[r]; };
@@ -133,45 +136,59 @@ __global__ __launch_bounds__(kBlock) void k_inner_general(
     }
     __syncthreads();
 
+    // Unit and position indices fit in 32 bits (they index arrays whose
+    // sizes are int32 pos entries), and so do the staged LDS offsets.
     double acc = 0.0;
-    int64_t rk = 0;  // staged parent index of the lane's previous unit (units ascend)
+    int32_t jv[kUnitIters];  // the lane's coordinates, loaded together
+    // (bounds compared in 64 bits: the last range may end past 2^31 - 1)
+#pragma unroll
     for (int it = 0; it < kUnitIters; ++it) {
         const int64_t u = u0 + it * kBlock + threadIdx.x;
-        if (u >= u1) break;
-        const int32_t j = bcrd[u];
-        int64_t g;
+        jv[it] = u < u1 ? bcrd[u] : 0;
+    }
+    const int32_t cnt32 = static_cast<int32_t>(cnt);
+    const int32_t c0s = static_cast<int32_t>(c0), c1s = static_cast<int32_t>(c1);
+    int32_t rk = 0;  // staged parent index of the lane's previous unit (units ascend)
+#pragma unroll
+    for (int it = 0; it < kUnitIters; ++it) {
+        const int64_t u64 = u0 + it * kBlock + threadIdx.x;
+        if (u64 >= u1) break;
+        const int32_t u = static_cast<int32_t>(u64);
+        const int32_t j = jv[it];
+        int32_t g;
         if (staged) {
-            rk = parent_of([&](int64_t k) { return s_pos[k]; }, rk, cnt, u);
+            rk = parent_of<int32_t>([&](int32_t k) { return s_pos[k]; }, rk, cnt32, u);
             // C's positions of this parent, clipped to the staged range
-            const int64_t lo = s_cpos[rk] > c0 ? s_cpos[rk] : c0;
-            const int64_t hi = s_cpos[rk + 1] < c1 ? s_cpos[rk + 1] : c1;
-            g = find_sorted([&](int64_t k) { return s_ccrd[k]; }, lo - c0, hi - c0, j);
-            if (g >= 0) g += c0;
+            const int32_t lo = s_cpos[rk] > c0s ? s_cpos[rk] : c0s;
+            const int32_t hi = s_cpos[rk + 1] < c1s ? s_cpos[rk + 1] : c1s;
+            g = find_sorted<int32_t>([&](int32_t k) { return s_ccrd[k]; }, lo - c0s, hi - c0s, j);
+            if (g >= 0) g += c0s;
         } else {
-            const int64_t r = parent_of(gpos, r0, r0 + cnt, u);
-            g = find_sorted([&](int64_t k) { return ccrd[k]; }, cpos[r], cpos[r + 1], j);
+            const int64_t r = parent_of<int64_t>(gpos, r0, r0 + cnt, u);
+            g = static_cast<int32_t>(
+                find_sorted<int64_t>([&](int64_t k) { return ccrd[k]; }, cpos[r], cpos[r + 1], j));
         }
         if (g < 0) continue;
         if (ORDER == 2) {
             acc += to_f64(bv[u]) * to_f64(cv[g]);
         } else {
-            int64_t p = bpos2[u], pe = bpos2[u + 1];
-            int64_t q = cpos2[g], qe = cpos2[g + 1];
+            int32_t p = bpos2[u], q = cpos2[g];
+            const int32_t pe = bpos2[u + 1], qe = cpos2[g + 1];
             while (p < pe && q < qe) {
+                // values loaded with the coordinates (one round of loads a step)
                 const int32_t kb = bcrd2[p], kc = ccrd2[q];
-                if (kb == kc) acc += to_f64(bv[p++]) * to_f64(cv[q++]);
-                else if (kb < kc) ++p;
-                else ++q;
+                const V vb = bv[p], vc = cv[q];
+                if (kb == kc) acc += to_f64(vb) * to_f64(vc);
+                p += kb <= kc ? 1 : 0;
+                q += kc <= kb ? 1 : 0;
             }
         }
     }
-    s_sum[threadIdx.x] = acc;
+    // fixed order: a butterfly in each wave, then the four wave sums in order
+    acc = group_sum<kWave>(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_sum[threadIdx.x / kWave] = acc;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = s_sum[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = ((s_sum[0] + s_sum[1]) + s_sum[2]) + s_sum[3];
 }
 
 }  // namespace
