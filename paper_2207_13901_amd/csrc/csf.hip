@@ -516,8 +516,18 @@ __global__ __launch_bounds__(kBlock) void k_inner_partial(int64_t nnz, const V *
 __global__ __launch_bounds__(kBlock) void k_inner_final(int64_t nparts,
                                                         const double *__restrict__ part,
                                                         double *__restrict__ out) {
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];
+    // four independent chains per thread (their loads overlap), combined in
+    // a fixed order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kBlock < nparts; i += 4 * kBlock) {
+        a0 += part[i];
+        a1 += part[i + kBlock];
+        a2 += part[i + 2 * kBlock];
+        a3 += part[i + 3 * kBlock];
+    }
+    for (; i < nparts; i += kBlock) a0 += part[i];
+    const double acc = (a0 + a1) + (a2 + a3);
     __shared__ double s[kBlock];
     s[threadIdx.x] = acc;
     __syncthreads();

@@ -1,7 +1,7 @@
 // SpMV leaf  a(i) = B(i,j) * c(j)  for CSR B (paper Sec. VI-A, leaf loop of
 // Fig. 8b), on one GPU.
 //
-// Two kernel families, one per partition kind:
+// The kernels, by partition kind:
 //
 //  * k_spmv_row<L>: row split.  A group of L lanes owns one row (a universe
 //    partition of the rows into blocks of 256/L per workgroup, image to the
