@@ -173,7 +173,9 @@ def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
     y = torch.empty(n, dtype=torch.float64, device=dev)
     ms_p = tuning.time_call(lambda: spl.coord_partition(B, bounds, out), reps=10, warmup=3)
     spl.coord_partition(B, bounds, out)
-    lanes = [dict(kind="row", lanes_per_row=L) for L in (1, 2, 4, 8)]
+    lanes = [dict(kind="row", lanes_per_row=L) for L in (1, 2, 4, 8)] + \
+        [dict(kind="merge", tile=T, items_per_lane=it)
+         for T, it in ((1024, 4), (4096, 4), (2048, 8), (8192, 8))]
 
     def windows(sc):
         for col in range(ncolors):

@@ -266,9 +266,15 @@ spl_status spl_coord_partition(spl_context *ctx, const spl_sparse *B, int32_t nc
  * B.vals[p] * c(B.crd[p]) — for one color of spl_coord_partition, the
  * product of B's column block with c.  B CSR n x m; begin, end: device
  * int32[n] with pos[i] <= begin[i] <= end[i] <= pos[i+1] (not checked: they
- * are read as row bounds); c vector m; a vector n, every entry written.
- * dtypes as spl_spmv.  Schedule: ROW only (lanes_per_row; default by the
- * mean row length of B), so no workspace. */
+ * are read as row bounds; a window with end < begin counts as empty); c
+ * vector m; a vector n, every entry written.  dtypes as spl_spmv.
+ * Schedules: MERGE (default; tile, items_per_lane 4 or 8, variant 0): the
+ * window lengths are scanned into the positions of a virtual CSR on the
+ * device, split by the merge path and summed with the flag leaf's walk and
+ * carries, so long windows cost no more than short ones; its workspace
+ * (n + 1 int32, scan and tile bounds, sized for B->nnz positions) comes from
+ * the context's pool.  ROW (lanes_per_row; default by the mean row length of
+ * B): no workspace.  NNZ gives SPL_ERR_ARG. */
 spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t *begin,
                            const int32_t *end, const spl_dense *c, spl_dense *a,
                            const spl_schedule *sched, spl_stream stream);

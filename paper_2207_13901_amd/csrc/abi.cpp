@@ -1108,18 +1108,49 @@ spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t 
         return fail(ctx, SPL_ERR_DTYPE, "SpMV needs vals, c and a all F64 or all F32");
     Plan p;
     SPL_CHECK(resolve_spmv(ctx, B, sched, p));
-    if (sched && sched->kind != SPL_SCHED_DEFAULT && p.kind != SPL_ROW)
-        return fail(ctx, SPL_ERR_ARG, "a windowed SpMV runs the ROW schedule only");
+    if (p.kind == SPL_NNZ || p.variant != 0)
+        return fail(ctx, SPL_ERR_ARG, "a windowed SpMV runs the ROW or MERGE schedule (variant 0)");
     const int64_t n = B->dims[0];
     if (n == 0) return SPL_OK;
     if (!begin || !end) return fail(ctx, SPL_ERR_ARG, "NULL window bounds");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.kind == SPL_ROW) {
+        LeafTimer tm(ctx, SPL_OP_SPMV, s);
+        SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, begin, end, B->crd[1], B->vals,
+                                     c->data, a->data, s),
+                "windowed SpMV launch");
+        tm.stop();
+        return SPL_OK;
+    }
+    // Merge split over the windows: their lengths are scanned into virtual
+    // positions on the device; the window total is at most nnz, so the tile
+    // count is sized for nnz and the bounds read the total on the device.
+    const Pieces q = pieces_for(p, n, B->nnz, spmv_chunk(p));
+    const int64_t scan_tiles = spl::spadd3_scan_tiles(n);
+    const size_t vpos_bytes = align_up(static_cast<size_t>(n + 1) * 4);
+    const size_t scan_bytes = align_up(static_cast<size_t>(scan_tiles + 1) * 8);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, nullptr, 0, vpos_bytes + scan_bytes + tiled_ws(q, 1, sizeof(double)),
+                            &ws));
+    char *wp = static_cast<char *>(ws);
+    int32_t *vpos = reinterpret_cast<int32_t *>(wp);
+    int64_t *tile_sum = reinterpret_cast<int64_t *>(wp + vpos_bytes);
+    Carved cv = carve(wp + vpos_bytes + scan_bytes, q.count);
+    SPL_HIP(spl::launch_window_offsets(n, begin, end, vpos, tile_sum, tile_sum + scan_tiles, s),
+            "window offsets launch");
+    SPL_HIP(spl::launch_tile_bounds(SPL_MERGE, n, vpos, /*total on the device*/ -1, q.size,
+                                    cv.tiles, s),
+            "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMV, s);
-    SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, n, begin, end, B->crd[1], B->vals, c->data,
-                                 a->data, s),
+    SPL_HIP(spl::launch_spmv_window_merge(B->vtype, p.items, n, vpos, begin, B->crd[1], B->vals,
+                                          c->data, a->data, cv.tiles, q.stride,
+                                          static_cast<double *>(cv.carry), s),
             "windowed SpMV launch");
     tm.stop();
+    SPL_HIP(spl::launch_spmv_fixup(B->vtype, n, cv.tiles, q.stride,
+                                   static_cast<double *>(cv.carry), a->data, s),
+            "windowed SpMV fix-up launch");
     return SPL_OK;
     SPL_GUARD_END
 }

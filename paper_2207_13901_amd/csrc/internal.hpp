@@ -50,6 +50,12 @@ hipError_t launch_spmv_tiles(int dtype, int items, int64_t n, const int32_t *pos
                              const Tiles &t, int64_t stride, bool exact_chunks, int variant,
                              double *carry, hipStream_t s);
 // Adds workgroup carries into the rows left open (after the leaf).
+// Merge split over position windows [begin[i], end[i]): vpos holds the
+// scanned window lengths (n + 1 entries, from launch_window_offsets).
+hipError_t launch_spmv_window_merge(int dtype, int items, int64_t n, const int32_t *vpos,
+                                    const int32_t *begin, const int32_t *crd, const void *vals,
+                                    const void *x, void *y, const Tiles &t, int64_t stride,
+                                    double *carry, hipStream_t s);
 hipError_t launch_spmv_fixup(int dtype, int64_t n, const Tiles &t, int64_t stride,
                              const double *carry, void *y, hipStream_t s);
 
@@ -123,6 +129,10 @@ hipError_t launch_sddmm(int vtype, int ftype, int variant, int vec_lanes, int64_
 
 // ---- spadd3.hip ----------------------------------------------------------
 int64_t spadd3_scan_tiles(int64_t n);
+// vpos[0] = 0, vpos[i + 1] = sum over r <= i of max(end[r] - begin[r], 0);
+// tile_sum holds spadd3_scan_tiles(n) entries; the sum goes to *total.
+hipError_t launch_window_offsets(int64_t n, const int32_t *begin, const int32_t *end,
+                                 int32_t *vpos, int64_t *tile_sum, int64_t *total, hipStream_t s);
 hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
                                   const int32_t *cp, const int32_t *cc, const int32_t *dp,
                                   const int32_t *dc, int32_t *apos, int64_t *tile_sum,

@@ -16,6 +16,9 @@
 //    so that leading empty rows belong to it.
 //  - Merge split: tile t starts at the point t*M of the merged sequence
 //    (a search per tile, or one sweep over the rows when they are few).
+//    A negative nnz means the position total is read from pos[rows] on the
+//    device (positions scanned on the device; the tile count passed in is
+//    then an upper bound, and every tile past the end starts at the end).
 #include <algorithm>
 
 #include "device.hpp"
@@ -64,6 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const P *
                                                          int32_t *trow, TP *tpos) {
     int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t > ntiles) return;
+    if (nnz < 0) nnz = static_cast<int64_t>(pos[rows]);  // the total is on the device
     int64_t total = rows + nnz;
     int64_t d = (t == ntiles || t * M > total) ? total : t * M;
     int64_t i = merge_search(d, rows, nnz, 0, [&](int64_t k) { return pos[k + 1]; });
@@ -75,22 +79,24 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const P *
 // row i (i < rows) owns the merged indices i + pos[i] .. i + pos[i+1] (its
 // positions, then its end), so every tile start d = t M in that range has
 // trow = i and tpos = d - i (the merge-path search gives the same i: the row
-// ends before index d are those of rows 0 .. i-1).  The virtual row `rows`
-// owns the bounds at or past the end, (rows, nnz).  One lane per row; reading pos once costs
-// less than a 20-step dependent search per tile when rows are few.
+// ends before index d are those of rows 0 .. i-1).  The bounds at or past
+// the end are (rows, nnz).  One lane per row; reading pos once costs less
+// than a 20-step dependent search per tile when rows are few.
 template <typename P, typename TP>
 __global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const P *pos,
                                                         int64_t nnz, int64_t M, int64_t ntiles,
                                                         int32_t *trow, TP *tpos) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i > rows) return;
-    if (i == rows) {  // every bound at or past the end: the last, and all when there are no items
-        for (int64_t t = (rows + nnz + M - 1) / M; t <= ntiles; ++t) {
-            trow[t] = static_cast<int32_t>(rows);
-            tpos[t] = static_cast<TP>(nnz);
-        }
-        return;
+    if (nnz < 0) nnz = static_cast<int64_t>(pos[rows]);  // the total is on the device
+    // every bound at or past the end (the last one, all of them when there
+    // are no items, many when the tile count is an upper bound), spread over
+    // all threads
+    const int64_t nthreads = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = (rows + nnz + M - 1) / M + i; t <= ntiles; t += nthreads) {
+        trow[t] = static_cast<int32_t>(rows);
+        tpos[t] = static_cast<TP>(nnz);
     }
+    if (i >= rows) return;
     const int64_t lo = i + static_cast<int64_t>(pos[i]), hi = i + static_cast<int64_t>(pos[i + 1]);
     for (int64_t t = (lo + M - 1) / M; t * M <= hi; ++t) {
         trow[t] = static_cast<int32_t>(i);

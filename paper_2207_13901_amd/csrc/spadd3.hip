@@ -239,9 +239,37 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_apply(int64_t n, int32_t *
     }
 }
 
+// Window lengths for the windowed merge split: vpos[0] = 0 and
+// vpos[i + 1] = end[i] - begin[i] (0 if negative); scanned in place after.
+__global__ __launch_bounds__(kBlock) void k_window_len(int64_t n, const int32_t *__restrict__ begin,
+                                                       const int32_t *__restrict__ end,
+                                                       int32_t *__restrict__ vpos) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i == 0) vpos[0] = 0;
+    if (i < n) {
+        const int32_t len = end[i] - begin[i];
+        vpos[i + 1] = len > 0 ? len : 0;
+    }
+}
+
 }  // namespace
 
 int64_t spadd3_scan_tiles(int64_t n) { return ceil_div(n > 0 ? n : 1, kScanTile); }
+
+hipError_t launch_window_offsets(int64_t n, const int32_t *begin, const int32_t *end,
+                                 int32_t *vpos, int64_t *tile_sum, int64_t *total, hipStream_t s) {
+    k_window_len<<<dim3(static_cast<unsigned>(ceil_div(n > 0 ? n : 1, kBlock))), kBlock, 0, s>>>(
+        n, begin, end, vpos);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = spadd3_scan_tiles(n);
+    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, vpos + 1, tile_sum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_prefix<<<1, kBlock, 0, s>>>(nt, tile_sum, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, vpos + 1, tile_sum);
+    return hipGetLastError();
+}
 
 hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
                                   const int32_t *cp, const int32_t *cc, const int32_t *dp,

@@ -624,6 +624,109 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
     if (tid == 0) carry[blockIdx.x] = open;
 }
 
+// Merge-split leaf over position windows: row i contributes its positions
+// [begin[i], end[i]) (the windows of one color of a coordinate-value
+// partition).  The rows and the window positions are merged as for a CSR
+// whose pos is vpos, the scan of the window lengths (virtual positions);
+// virtual position q of row r is the stored position q + begin[r] - vpos[r].
+// Per chunk the row ends (as flags, as in k_spmv_flag) and the offsets of
+// the chunk's rows are staged in LDS; each position finds its row by a
+// binary search over the staged row ends, then loads its coordinate and
+// value and gathers x.  The walk, the scans and the carries are those of
+// k_spmv_flag; no software pipeline.
+template <typename V, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_spmv_window_flag(
+    int64_t n, const int32_t *__restrict__ vpos, const int32_t *__restrict__ begin,
+    const int32_t *__restrict__ crd, const V *__restrict__ vals, const V *__restrict__ x,
+    V *__restrict__ y, const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos,
+    int64_t npieces, int64_t stride, double *__restrict__ carry) {
+    static_assert(ITEMS == 4 || ITEMS == 8, "flags are read as one 4- or 8-byte word");
+    using Flags = typename std::conditional<ITEMS == 4, uint32_t, uint64_t>::type;
+    constexpr int kChunk = kBlock * ITEMS;
+    __shared__ double s_prod[kChunk + 1];
+    __shared__ double s_out[kChunk + 1];  // finished rows; slot kChunk is a spare
+    __shared__ __align__(8) uint8_t s_flag[kChunk + 8];
+    __shared__ int32_t s_vend[kChunk];     // virtual ends of the rows finished in the chunk
+    __shared__ int32_t s_off[kChunk + 1];  // begin - vpos of the chunk's rows bi .. bi + nr
+    __shared__ __align__(16) int s_wave_total[kBlock / kWave];
+    __shared__ int s_first_key[kBlock / kWave], s_last_key[kBlock / kWave];
+    __shared__ double s_last_val[kBlock / kWave];
+    __shared__ double s_open;
+
+    const int tid = threadIdx.x;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
+    Flags &flag_word = reinterpret_cast<Flags *>(s_flag)[tid];
+    flag_word = 0;
+    double open = 0.0;
+    for (int64_t c = p0; c < pend; ++c) {
+        const int64_t bi = trow[c], bp = tpos[c];
+        const int nr = static_cast<int>(trow[c + 1] - bi), np = static_cast<int>(tpos[c + 1] - bp);
+        // chunks past the end (the grid is sized for all positions, the
+        // windows hold fewer) are empty: the same for every thread
+        if (nr + np == 0) continue;
+        __syncthreads();  // the previous chunk is done with every staging array
+        for (int k = tid; k < nr; k += kBlock) {
+            const int32_t e = vpos[bi + 1 + k];
+            s_vend[k] = e;
+            s_flag[k + static_cast<int>(e - bp)] = 1;
+        }
+        for (int k = tid; k <= nr; k += kBlock)
+            if (bi + k < n) s_off[k] = begin[bi + k] - vpos[bi + k];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < np) {
+                const int32_t q = static_cast<int32_t>(bp) + k;
+                int lo = 0, hi = nr;  // rows of the chunk finished at or before q
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_vend[mid] <= q)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                const int32_t at = q + s_off[lo];
+                s_prod[k] = to_f64(vals[at]) * to_f64(x[crd[at]]);
+            }
+        }
+        __syncthreads();
+        const int total = nr + np;
+        const int d0 = min(tid * ITEMS, total);
+        const int steps = min(d0 + ITEMS, total) - d0;
+        const Flags fl = flag_word;
+        flag_word = 0;  // cleared for the next chunk
+        int a = block_exclusive_sum(static_cast<int>(__builtin_popcountll(fl)), s_wave_total);
+        int b = d0 - a;
+        double acc = tid == 0 ? open : 0.0;
+#pragma unroll
+        for (int st = 0; st < ITEMS; ++st) {
+            const bool fin = (fl >> (8 * st)) & 1;
+            const bool add = !fin && st < steps;
+            const double pv = s_prod[b];  // b <= np <= kChunk
+            s_out[fin ? a : kChunk] = acc;
+            acc = (fin ? 0.0 : acc) + (add ? pv : 0.0);
+            a += fin ? 1 : 0;
+            b += add ? 1 : 0;
+        }
+        double v = block_segmented_scan_dpp(acc, a, s_first_key, s_last_key, s_last_val);
+        int next_key = __shfl_down(a, 1);
+        const int lane = tid & (kWave - 1), wave = tid / kWave;
+        if (lane == kWave - 1) next_key = wave + 1 < kBlock / kWave ? s_first_key[wave + 1] : -1;
+        if (next_key != a) {
+            if (a < nr)
+                s_out[a] += v;
+            else
+                s_open = v;
+        }
+        __syncthreads();
+        for (int k = tid; k < nr; k += kBlock) store_stream(y + bi + k, static_cast<V>(s_out[k]));
+        open = s_open;
+    }
+    if (tid == 0) carry[blockIdx.x] = open;
+}
+
 template <typename V>
 hipError_t spmv_row_dispatch(int lanes, int64_t n, const int32_t *pos_b, const int32_t *pos_e,
                              const int32_t *crd, const V *vals, const V *x, V *y, hipStream_t s) {
@@ -703,6 +806,28 @@ hipError_t launch_spmv_row(int dtype, int lanes, int64_t n, const int32_t *pos_b
                                          static_cast<const double *>(x), static_cast<double *>(y), s);
     return spmv_row_dispatch<float>(lanes, n, pos_b, pos_e, crd, static_cast<const float *>(vals),
                                     static_cast<const float *>(x), static_cast<float *>(y), s);
+}
+
+hipError_t launch_spmv_window_merge(int dtype, int items, int64_t n, const int32_t *vpos,
+                                    const int32_t *begin, const int32_t *crd, const void *vals,
+                                    const void *x, void *y, const Tiles &t, int64_t stride,
+                                    double *carry, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
+    auto go = [&](auto *v, auto *xx, auto *yy) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        if (items <= 4)
+            k_spmv_window_flag<V, 4><<<grid, kBlock, 0, s>>>(n, vpos, begin, crd, v, xx, yy, t.row,
+                                                             t.pos, t.ntiles, stride, carry);
+        else
+            k_spmv_window_flag<V, 8><<<grid, kBlock, 0, s>>>(n, vpos, begin, crd, v, xx, yy, t.row,
+                                                             t.pos, t.ntiles, stride, carry);
+        return hipGetLastError();
+    };
+    if (dtype == SPL_F64)
+        return go(static_cast<const double *>(vals), static_cast<const double *>(x),
+                  static_cast<double *>(y));
+    return go(static_cast<const float *>(vals), static_cast<const float *>(x),
+              static_cast<float *>(y));
 }
 
 hipError_t launch_spmv_flag64(int dtype, int items, int64_t n, const int64_t *pos,

@@ -112,15 +112,18 @@ def test_coord_partition_and_window_spmv(dtype):
             for c in range(len(bounds) - 1):
                 ra, S = oracle.spmv_window(ref[c], ref[c + 1], crd, host64(B.vals), host64(x))
                 for sc in (None, dict(kind="row", lanes_per_row=1), dict(kind="row", lanes_per_row=8),
-                           dict(kind="row", lanes_per_row=64)):
+                           dict(kind="row", lanes_per_row=64),
+                           dict(kind="merge", tile=1024, items_per_lane=4),
+                           dict(kind="merge", tile=256 * 8 * 3, items_per_lane=8)):
                     a = spl.spmv_window(B, out[c], out[c + 1], x,
                                         sched=spl.schedule(**sc) if sc else None)
                     assert_close(host64(a), ra, S, RTOL[dtype], f"window {c} {bounds} {sc}")
-    with pytest.raises(spl.SpleafError, match="ROW"):
-        B = _csr(spl, *cases[-1][:3], cases[-1][3], torch.float64)
-        o = spl.coord_partition(B, torch.tensor([0, 10], dtype=torch.int32, device=dev()))
-        spl.spmv_window(B, o[0], o[1], torch.ones(B.shape[1], dtype=torch.float64, device=dev()),
-                        sched=spl.schedule("merge"))
+    B = _csr(spl, *cases[-1][:3], cases[-1][3], torch.float64)
+    o = spl.coord_partition(B, torch.tensor([0, 10], dtype=torch.int32, device=dev()))
+    for bad in (spl.schedule("nnz"), spl.schedule("merge", variant=1)):
+        with pytest.raises(spl.SpleafError, match="ROW or MERGE"):
+            spl.spmv_window(B, o[0], o[1],
+                            torch.ones(B.shape[1], dtype=torch.float64, device=dev()), sched=bad)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
