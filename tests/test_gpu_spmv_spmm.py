@@ -173,6 +173,19 @@ def test_merge_bounds_above_the_sweep_limit():
             rr, rp = oracle.merge_split(pos.astype(np.int32), size)
             assert np.array_equal(tr.cpu().numpy(), rr), (n, size)
             assert np.array_equal(tp.cpu().numpy(), rp), (n, size)
+        # the windowed product's merge split (bounds reading the window total
+        # on the device): every row without its first entry when it has two
+        vals = rs.uniform(-1, 1, nnz)
+        Bv = _csr(spl, pos.astype(np.int32), crd, vals, (n, 1), torch.float64)
+        begin = (pos[:-1] + (deg >= 2)).astype(np.int32)
+        end = pos[1:].astype(np.int32)
+        x = torch.tensor([1.5], dtype=torch.float64, device=dev())
+        ref, S = oracle.spmv_window(begin, end, crd, vals, np.array([1.5]))
+        bt, et = torch.as_tensor(begin, device=dev()), torch.as_tensor(end, device=dev())
+        for sc in (dict(kind="merge", tile=1024, items_per_lane=4),
+                   dict(kind="merge", tile=8192, items_per_lane=8)):
+            a = spl.spmv_window(Bv, bt, et, x, sched=spl.schedule(**sc))
+            assert_close(host64(a), ref, S, RTOL[torch.float64], f"window {n} {sc}")
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
