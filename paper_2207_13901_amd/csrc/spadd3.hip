@@ -166,15 +166,26 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const
     }
 }
 
-// Block sums of x[0..n) in tiles of kScanTile.
+// Element i of the scanned sequence: x[i], or with window bounds the window
+// length max(end[i] - begin[i], 0).
+__device__ __forceinline__ int32_t scan_value(const int32_t *x, const int32_t *begin,
+                                              const int32_t *end, int64_t i) {
+    if (!begin) return x[i];
+    const int32_t len = end[i] - begin[i];
+    return len > 0 ? len : 0;
+}
+
+// Block sums of the sequence's elements [0, n) in tiles of kScanTile.
 __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(int64_t n, const int32_t *x,
+                                                           const int32_t *begin,
+                                                           const int32_t *end,
                                                            int64_t *tile_sum) {
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     int64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t i = base + j * kBlock + threadIdx.x;
-        if (i < n) acc += x[i];
+        if (i < n) acc += scan_value(x, begin, end, i);
     }
     __shared__ int64_t s[kBlock];
     s[threadIdx.x] = acc;
@@ -209,20 +220,37 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_prefix(int64_t ntiles, int
     if (threadIdx.x == 0) *total = carry;
 }
 
-// In place: x[i] <- tile prefix + inclusive scan within the tile, i.e. with
-// x = counts at apos + 1 this leaves apos[i+1] = sum of counts[0..i].
+// x[i] <- tile prefix + inclusive scan within the tile, i.e. with x =
+// counts at apos + 1 this leaves apos[i+1] = sum of counts[0..i] (in place;
+// with window bounds the values are the window lengths instead of x).  The
+// tile goes through LDS so that the loads and stores are coalesced; each
+// thread scans 16 consecutive elements there (padded: element e at
+// e + e / 16, so the threads' runs fall in different banks).
 __global__ __launch_bounds__(kBlock) void k_scan_tile_apply(int64_t n, int32_t *x,
-                                                            const int64_t *tile_sum) {
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
-    int64_t v[kScanItems];
+                                                            const int32_t *begin,
+                                                            const int32_t *end,
+                                                            const int64_t *tile_sum,
+                                                            int32_t *head) {
+    if (head && blockIdx.x == 0 && threadIdx.x == 0) *head = 0;  // the leading 0 of a pos array
+    constexpr int kPad = kScanTile + kScanTile / kScanItems;
+    __shared__ int64_t s_v[kPad];
+    __shared__ int64_t s[kBlock];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int e = j * kBlock + threadIdx.x;
+        const int64_t i = base + e;
+        s_v[e + e / kScanItems] = i < n ? scan_value(x, begin, end, i) : 0;
+    }
+    __syncthreads();
+    const int e0 = threadIdx.x * kScanItems;
+    const int p0 = e0 + e0 / kScanItems;  // this thread's run, unpadded inside
     int64_t run = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + j;
-        run += i < n ? x[i] : 0;
-        v[j] = run;
+        run += s_v[p0 + j];
+        s_v[p0 + j] = run;
     }
-    __shared__ int64_t s[kBlock];
     s[threadIdx.x] = run;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {
@@ -233,22 +261,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_apply(int64_t n, int32_t *
     }
     const int64_t before = tile_sum[blockIdx.x] + s[threadIdx.x] - run;
 #pragma unroll
+    for (int j = 0; j < kScanItems; ++j) s_v[p0 + j] += before;
+    __syncthreads();
+#pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t i = base + j;
-        if (i < n) x[i] = static_cast<int32_t>(before + v[j]);
-    }
-}
-
-// Window lengths for the windowed merge split: vpos[0] = 0 and
-// vpos[i + 1] = end[i] - begin[i] (0 if negative); scanned in place after.
-__global__ __launch_bounds__(kBlock) void k_window_len(int64_t n, const int32_t *__restrict__ begin,
-                                                       const int32_t *__restrict__ end,
-                                                       int32_t *__restrict__ vpos) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i == 0) vpos[0] = 0;
-    if (i < n) {
-        const int32_t len = end[i] - begin[i];
-        vpos[i + 1] = len > 0 ? len : 0;
+        const int e = j * kBlock + threadIdx.x;
+        const int64_t i = base + e;
+        if (i < n) x[i] = static_cast<int32_t>(s_v[e + e / kScanItems]);
     }
 }
 
@@ -258,16 +277,16 @@ int64_t spadd3_scan_tiles(int64_t n) { return ceil_div(n > 0 ? n : 1, kScanTile)
 
 hipError_t launch_window_offsets(int64_t n, const int32_t *begin, const int32_t *end,
                                  int32_t *vpos, int64_t *tile_sum, int64_t *total, hipStream_t s) {
-    k_window_len<<<dim3(static_cast<unsigned>(ceil_div(n > 0 ? n : 1, kBlock))), kBlock, 0, s>>>(
-        n, begin, end, vpos);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // vpos[0] = 0 and vpos[1..n] the inclusive scan of the window lengths
     const int64_t nt = spadd3_scan_tiles(n);
-    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, vpos + 1, tile_sum);
+    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, nullptr, begin, end,
+                                                                        tile_sum);
+    hipError_t e;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_scan_tile_prefix<<<1, kBlock, 0, s>>>(nt, tile_sum, total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, vpos + 1, tile_sum);
+    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, vpos + 1, begin, end,
+                                                                         tile_sum, vpos);
     return hipGetLastError();
 }
 
@@ -281,11 +300,13 @@ hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *b
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nt = spadd3_scan_tiles(n);
-    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, tile_sum);
+    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, nullptr,
+                                                                        nullptr, tile_sum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_scan_tile_prefix<<<1, kBlock, 0, s>>>(nt, tile_sum, total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, tile_sum);
+    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, nullptr,
+                                                                         nullptr, tile_sum, nullptr);
     return hipGetLastError();
 }
 
