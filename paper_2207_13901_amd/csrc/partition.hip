@@ -110,26 +110,44 @@ __global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const P *p
 // coordinate lies in [bounds[c], bounds[c+1]) are [out[c][i], out[c+1][i]),
 // where out[c][i] is the first position of parent i with coordinate at
 // least bounds[c] (coordinates are sorted within a parent).  One lane per
-// (bound, parent) pair, a binary search inside the parent's segment; lanes
-// of a wave share the bound, so the writes of one bound are coalesced.
+// parent runs the binary searches of up to kSplitBatch bounds in lockstep
+// inside its segment, so their loads are in flight together; the writes of
+// one bound are coalesced over the lanes.
+constexpr int kSplitBatch = 16;
+
 __global__ __launch_bounds__(kBlock) void k_coord_split(int64_t rows, const int32_t *__restrict__ pos,
                                                         const int32_t *__restrict__ crd,
                                                         int64_t nbounds,
                                                         const int32_t *__restrict__ bounds,
                                                         int32_t *__restrict__ out) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= nbounds * rows) return;
-    const int64_t c = k / rows, i = k - c * rows;
-    const int32_t b = bounds[c];
-    int64_t lo = pos[i], hi = pos[i + 1];
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (crd[mid] < b)
-            lo = mid + 1;
-        else
-            hi = mid;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= rows) return;
+    const int32_t lo0 = pos[i], hi0 = pos[i + 1];
+    for (int64_t c0 = 0; c0 < nbounds; c0 += kSplitBatch) {
+        int32_t lo[kSplitBatch], hi[kSplitBatch], b[kSplitBatch];
+#pragma unroll
+        for (int k = 0; k < kSplitBatch; ++k) {
+            const bool live = c0 + k < nbounds;
+            b[k] = live ? bounds[c0 + k] : 0;
+            lo[k] = lo0;
+            hi[k] = live ? hi0 : lo0;
+        }
+        for (int32_t len = hi0 - lo0; len > 0; len >>= 1) {  // one halving per step
+#pragma unroll
+            for (int k = 0; k < kSplitBatch; ++k) {
+                if (lo[k] < hi[k]) {
+                    const int32_t mid = lo[k] + ((hi[k] - lo[k]) >> 1);
+                    if (crd[mid] < b[k])
+                        lo[k] = mid + 1;
+                    else
+                        hi[k] = mid;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSplitBatch; ++k)
+            if (c0 + k < nbounds) out[(c0 + k) * rows + i] = lo[k];
     }
-    out[k] = static_cast<int32_t>(lo);
 }
 
 // The pos and crd arrays a Dense level of extent J under I parents would
@@ -151,9 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_level(int64_t I, int64_t J,
 
 hipError_t launch_coord_split(int64_t rows, const int32_t *pos, const int32_t *crd, int64_t nbounds,
                               const int32_t *bounds, int32_t *out, hipStream_t s) {
-    const int64_t lanes = nbounds * rows;
-    if (lanes == 0) return hipSuccess;
-    k_coord_split<<<dim3(static_cast<unsigned>(ceil_div(lanes, kBlock))), kBlock, 0, s>>>(
+    if (nbounds == 0 || rows == 0) return hipSuccess;
+    k_coord_split<<<dim3(static_cast<unsigned>(ceil_div(rows, kBlock))), kBlock, 0, s>>>(
         rows, pos, crd, nbounds, bounds, out);
     return hipGetLastError();
 }
