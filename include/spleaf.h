@@ -317,9 +317,12 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * 32 or 64 rank columns per lane group.  sched->variant: 0 = each lane reads
  * and writes 4 consecutive rank columns with one vector access when R,
  * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
- * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 8
- * (otherwise one column per lane); 1 = one column per lane.  The workspace
- * query returns the one-column-per-lane size, enough for both.  A
+ * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 4 or
+ * 8 (otherwise one column per lane); 1 = one column per lane.
+ * items_per_lane: 8 (default) or 16 for either leaf; 4 only with the
+ * 4-column lanes (SPL_ERR_ARG when they do not apply): half the registers
+ * and LDS of 8, so more waves per SIMD.  The workspace query returns the
+ * one-column-per-lane size, enough for both.  A
  * (Dense, Dense, Compressed) B is accepted: its middle level's pos/crd
  * (I + 1 and I * J int32) are written into the workspace, counted by the
  * query, and the leaf runs as for CSF. */

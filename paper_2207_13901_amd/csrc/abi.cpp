@@ -440,11 +440,11 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
         return fail(ctx, SPL_ERR_ARG, "MTTKRP col_tile must be 16, 32 or 64");
     p.col_tile = ct;
     p.items = s->items_per_lane ? s->items_per_lane : 8;
-    if (p.items != 8 && p.items != 16)
-        return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 8 or 16");
+    if (p.items != 4 && p.items != 8 && p.items != 16)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 4, 8 or 16");
     // four leaf chunks per workgroup by default (vector-lane chunks when
-    // the operands allow them: col_tile 32 or 64 with 8 items)
-    const int64_t chunk = (256 / (p.items == 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
+    // the operands allow them: col_tile 32 or 64 with 4 or 8 items)
+    const int64_t chunk = (256 / (p.items <= 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
     if (s->variant != 0 && s->variant != 1)
@@ -460,7 +460,8 @@ int64_t mttkrp_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.it
 // and items_per_lane 8; otherwise one column per lane.
 int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_dense *A) {
     constexpr int v = 4;
-    if (p.variant != 0 || p.items != 8 || (p.col_tile != 32 && p.col_tile != 64)) return 1;
+    if (p.variant != 0 || (p.items != 8 && p.items != 4) || (p.col_tile != 32 && p.col_tile != 64))
+        return 1;
     const int64_t R = C->dims[1];
     const size_t fb = v * dtype_bytes(C->dtype);
     const bool ok = R % v == 0 && C->ld % v == 0 && D->ld % v == 0 && A->ld % v == 0 &&
@@ -1224,6 +1225,10 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     if (I == 0 || R == 0) return SPL_OK;
     // the workspace query assumed one column per lane: the larger size
     p.vec = mttkrp_vec(p, C, D, A);
+    if (p.items == 4 && p.vec == 1)
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP items_per_lane 4 needs 4-column lanes (variant 0, col_tile 32 or 64, "
+                    "R and every ld multiples of 4, 16-byte aligned factors)");
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
                             dense_middle_ws(B) + mttkrp_ws(B, R, p), &ws));

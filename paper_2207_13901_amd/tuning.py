@@ -29,6 +29,10 @@ SPMM_CANDIDATES: List[Dict] = (
 
 
 MTTKRP_CANDIDATES: List[Dict] = [
+    # 4 items per lane group: the 4-column-lane leaf only (R and every ld
+    # multiples of 4); more waves per SIMD than with 8
+    dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
+    dict(kind="merge", tile=1024, col_tile=32, items_per_lane=4),
     dict(kind="merge", tile=512, col_tile=32, items_per_lane=16),
     dict(kind="merge", tile=256, col_tile=32, items_per_lane=8),
     dict(kind="merge", tile=1024, col_tile=32, items_per_lane=8),

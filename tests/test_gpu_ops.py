@@ -31,6 +31,10 @@ MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=
                     dict(kind="nnz", tile=700, col_tile=32, items_per_lane=8),
                     dict(kind="merge", tile=2048, col_tile=32, items_per_lane=8),
                     dict(kind="merge", tile=512, col_tile=32, items_per_lane=8, variant=1)]
+# 4 items per lane group: the 4-column-lane leaf only (R and every ld multiples of 4)
+MTTKRP_VEC4 = [dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
+               dict(kind="merge", tile=1, col_tile=64, items_per_lane=4),
+               dict(kind="merge", tile=3000, col_tile=32, items_per_lane=4)]
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
                    dict(kind="merge", tile=512)]
 
@@ -99,10 +103,13 @@ def test_mttkrp(dtype, R):
         D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
         ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
                                host64(C), host64(D))
-        for sc in MTTKRP_SCHEDULES:
+        for sc in MTTKRP_SCHEDULES + (MTTKRP_VEC4 if R % 4 == 0 else []):
             A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
             assert A.dtype == torch.float32
             assert_close(host64(A), ref, S, 1e-5, f"mttkrp {dtype} R={R} {sc}")
+        if R % 4:
+            with pytest.raises(spl.SpleafError, match="items_per_lane 4"):
+                spl.mttkrp(B, C, D, sched=spl.schedule(**MTTKRP_VEC4[0]))
 
 
 def test_mttkrp_integer_values_bit_exact():
@@ -114,7 +121,7 @@ def test_mttkrp_integer_values_bit_exact():
     B = _csf(spl, c, torch.float32)
     ref, _ = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], c["vals"],
                            host64(C), host64(D))
-    for sc in MTTKRP_SCHEDULES:
+    for sc in MTTKRP_SCHEDULES + MTTKRP_VEC4:
         A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
         assert np.array_equal(host64(A), ref), sc
 
@@ -445,7 +452,7 @@ def test_ddc_mttkrp(dtype):
         D = _t(Dn, torch.float64).to(torch.float32).to(dtype)
         ref, S = oracle.mttkrp_ddc(c["I"], c["J"], c["pos2"], c["crd2"], host64(B.vals),
                                    host64(C), host64(D))
-        for sc in MTTKRP_SCHEDULES:
+        for sc in MTTKRP_SCHEDULES + (MTTKRP_VEC4 if R % 4 == 0 else []):
             A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
             assert_close(host64(A), ref, S, 1e-5, f"ddc mttkrp {dtype} {sc} I={c['I']}")
         # a caller workspace sized by the query (it holds the expanded level)
@@ -509,7 +516,7 @@ def test_csf_leaves_deterministic():
         B = _csf(spl, c, dtype)
         C = _t(c["C"], torch.float64).to(torch.float32).to(dtype)
         D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
-        for sc in MTTKRP_SCHEDULES:
+        for sc in MTTKRP_SCHEDULES + MTTKRP_VEC4:
             a1 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc)).clone()
             a2 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
             assert torch.equal(a1, a2), (dtype, sc)
