@@ -34,6 +34,11 @@
 //    ends staged as flags in the merged sequence, so that no lane searches
 //    or reads row ends (see below).
 //
+//  * k_spmv_window_flag: the flag leaf over position windows (one color of
+//    a coordinate-value partition), whose lengths are scanned into the
+//    positions of a virtual CSR; each position maps back to its stored
+//    position through the chunk's row offsets staged in LDS.
+//
 // Accumulation is in double for both double and float data (a float output
 // is rounded once from the double sum, then once more if a carry lands on it).
 #include <type_traits>
