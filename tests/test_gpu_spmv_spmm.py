@@ -118,6 +118,10 @@ def test_coord_partition_and_window_spmv(dtype):
                     a = spl.spmv_window(B, out[c], out[c + 1], x,
                                         sched=spl.schedule(**sc) if sc else None)
                     assert_close(host64(a), ra, S, RTOL[dtype], f"window {c} {bounds} {sc}")
+                    # fixed reduction orders: a second call gives the same bits
+                    a2 = spl.spmv_window(B, out[c], out[c + 1], x,
+                                         sched=spl.schedule(**sc) if sc else None)
+                    assert torch.equal(a, a2), (c, bounds, sc)
     B = _csr(spl, *cases[-1][:3], cases[-1][3], torch.float64)
     o = spl.coord_partition(B, torch.tensor([0, 10], dtype=torch.int32, device=dev()))
     for bad in (spl.schedule("nnz"), spl.schedule("merge", variant=1)):
