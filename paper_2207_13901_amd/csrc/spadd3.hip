@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
 // in the windows a long row fills alone.  The inputs are read directly:
 // staging them as well would halve the workgroups per CU, which costs more
 // than the repeated line fetches it saves.
-constexpr int kFillCap = 4096;
+constexpr int kFillCap = 2048;
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const V *bv,
