@@ -29,7 +29,7 @@ namespace spl {
 namespace {
 
 constexpr int kParents = 1024;   // parents staged per workgroup
-constexpr int kCStage = 4096;    // C coordinates staged per workgroup
+constexpr int kCStage = 2560;    // C coordinates staged per workgroup
 constexpr int kUnitIters = 8;    // units per lane
 
 // Largest r in [lo, hi) with pos[r] <= u (the parent holding unit u); I is
