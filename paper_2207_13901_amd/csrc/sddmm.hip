@@ -12,7 +12,7 @@
 //    a 32-lane butterfly.  FP64, FP32, or BF16 factors with FP32
 //    accumulation.
 //  * k_sddmm_vec: the same with vector lanes (16-byte factor accesses) and
-//    8, 16 or 32 lanes per position, four positions per lane group in
+//    8, 16 or 32 lanes per position, two positions per lane group in
 //    flight.
 //  * k_sddmm_mfma: BF16 factors on the matrix cores.  A wave takes 16
 //    positions; v_mfma_f32_16x16x32_bf16 multiplies the 16 gathered C rows
@@ -236,9 +236,11 @@ hipError_t sddmm_vec(int lanes, dim3 grid, int64_t K, const int32_t *pos, const 
         return hipGetLastError();
     };
     using Acc = V;  // FP64 or FP32 accumulation, as the values
-    // positions per lane group in flight (8 measured slower for FP32: 1.28
-    // against 0.97 ms at K = 128, fewer waves per SIMD)
-    constexpr int kP = 4;
+    // positions per lane group in flight: 2 (fewer registers, more waves per
+    // SIMD) measured best at K = 128 on 8e6 positions: FP32 0.874 ms, BF16
+    // 0.433 ms, against 0.928 / 0.529 with 4, 1.08 / 0.51 with 1 and 1.28
+    // (FP32) with 8
+    constexpr int kP = 2;
     if (lanes == 32) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 32, VEC, kP>);
     if (lanes == 16) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 16, VEC, kP>);
     if (lanes == 8) return go(k_sddmm_vec<V, FT, Acc, kSddmmChunk, 8, VEC, kP>);
