@@ -491,8 +491,12 @@ spl_status resolve_sddmm(spl_context *ctx, const spl_schedule *s, Plan &p) {
     p.kind = s->kind == SPL_SCHED_DEFAULT ? SPL_MERGE : s->kind;
     if (p.kind != SPL_ROW && p.kind != SPL_NNZ && p.kind != SPL_MERGE)
         return fail(ctx, SPL_ERR_ARG, "unknown schedule kind %d", s->kind);
+    // default merge tile: one chunk per workgroup for the vector leaf (more
+    // workgroups in flight: FP32 0.87 against 1.04 ms with four chunks at
+    // K = 128), four for the matrix-core leaf
+    const int64_t merge_tile = (s->variant == 1 ? 4 : 1) * spl::sddmm_chunk();
     p.tile = s->tile ? s->tile
-                     : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 1024 : 4 * spl::sddmm_chunk());
+                     : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 1024 : merge_tile);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
     p.items = s->variant;
     return SPL_OK;
