@@ -193,6 +193,25 @@ spl_status spl_tile_bounds(spl_context *ctx, const spl_sparse *B,
                            int32_t *tile_pos, int64_t capacity,
                            int64_t *ntiles, spl_stream stream);
 
+/* The fused non-zero partition of a CSF tensor (Dense, Compressed,
+ * Compressed) that SpMTTKRP's SPL_NNZ schedule runs on: the (i,j,k)
+ * positions are fused and cut into blocks of T positions (Sec. II-B,
+ * coordinate fusion and the non-zero partition), each block boundary is
+ * moved back to the start of the fiber that holds it so that every fiber
+ * lies in one tile, and slices follow by preimage through pos[1]
+ * (Sec. III-A; Table I).  For tile t (0 < t < ntiles), tile_fiber[t] is the
+ * fiber holding position t*T and tile_slice[t] the slice holding that
+ * fiber; tile t covers the fibers [tile_fiber[t], tile_fiber[t+1]), that
+ * is the positions [pos[2][tile_fiber[t]], pos[2][tile_fiber[t+1]]), and
+ * finishes the slices [tile_slice[t], tile_slice[t+1]).  Entry 0 is
+ * (0, 0) and entry ntiles is (dims[0], nfibers).  ntiles = ceil(nnz / T),
+ * at least 1.  tile_slice and tile_fiber: device int32 arrays of `capacity`
+ * entries (capacity >= ntiles + 1, else SPL_ERR_ARG; *ntiles, host, is
+ * written first either way).  A Dense middle level gives SPL_ERR_FORMAT. */
+spl_status spl_csf_tile_bounds(spl_context *ctx, const spl_sparse *B, int64_t T,
+                               int32_t *tile_slice, int32_t *tile_fiber, int64_t capacity,
+                               int64_t *ntiles, spl_stream stream);
+
 /* Check pos/crd contents on the device: pos[0] = 0, non-decreasing pos,
  * last pos = child count (nnz or nfibers), every crd in [0, extent),
  * strictly increasing within each segment.  Returns SPL_OK or
@@ -231,7 +250,11 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
 
 /* SpMV  a(i) = B(i,j) * c(j)   (Sec. VI-A; the leaf of Fig. 8b).
  * B CSR n x m; c vector m; a vector n.  dtypes: vals, c, a all F64, or all
- * F32 (products and sums in F64, rounded once per output).  Schedules: ROW,
+ * F32 (products and sums in F64; an F32 output is rounded from the F64
+ * sum once, except a row that spans tiles of the NNZ or MERGE split: the
+ * tile that finishes it stores its rounded partial, and the carry fix-up
+ * adds the other tiles' F64 carries to that value and rounds a second
+ * time).  Schedules: ROW,
  * NNZ, MERGE (default MERGE), and SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE
  * (below).  sched->variant (MERGE only; both walk chunks of
  * 256 * items_per_lane merged items): 0 = the row ends are staged as flags
@@ -281,7 +304,9 @@ spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t 
 
 /* SpMM  A(i,j) = B(i,k) * C(k,j)   (Sec. VI-A).
  * B CSR n x m; C dense m x N; A dense n x N.  dtypes (vals, C, A): all F64;
- * all F32; or vals and C BF16 with A F32 (F32 accumulation).  Schedules:
+ * all F32; or vals and C BF16 with A F32 (F32 accumulation; under the
+ * NNZ and MERGE splits a row that spans tiles is the finishing tile's
+ * partial plus the other tiles' carries, added by the fix-up).  Schedules:
  * ROW, NNZ, MERGE (default MERGE); col_tile 8..64 columns per lane group.
  * sched->variant (MERGE): 0 = each lane reads and writes 4 F32, 2 F64 or 4
  * BF16 consecutive columns with one vector access when N, C->ld, A->ld and
@@ -299,7 +324,8 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
  * (pattern-preserving output, Sec. V-B): A shares B's first two levels
  * (A.pos = B.pos[1], A.crd = B.crd[1]) and only its values are written,
  * one per fiber, into the vector A of length B->nfibers.  dtypes: vals, c, A
- * all F64, or all F32 (F64 sums).  The schedule applies to the fiber level
+ * all F64, or all F32 (F64 sums, rounded as for spl_spmv: twice for a
+ * fiber that spans tiles).  The schedule applies to the fiber level
  * (fibers play the role of SpMV rows): ROW, NNZ or MERGE (default), with
  * sched->variant as for spl_spmv.  For a (Dense, Dense, Compressed) B the
  * fibers are all I * J pairs (i,j), so A is the dense I x J matrix, row-major

@@ -26,7 +26,7 @@ __all__ = [
     "validate", "op_parse", "op_tin", "workspace_query", "workspace", "SpleafError",
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
-    "schedule_dict", "coord_partition", "spmv_window", "DDC",
+    "schedule_dict", "coord_partition", "spmv_window", "DDC", "csf_tile_bounds",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -308,6 +308,22 @@ def tile_bounds(B, sched, ctx: Optional[Context] = None):
                                       tr.data_ptr(), tp.data_ptr(), cap, ctypes.byref(nt),
                                       stream), "spl_tile_bounds")
     return tr[:nt.value + 1], tp[:nt.value + 1]
+
+
+def csf_tile_bounds(B: CSF, T: int, ctx: Optional[Context] = None):
+    """The fiber-aligned non-zero partition of a CSF tensor in blocks of T
+    positions: returns (tile_slice, tile_fiber) int32 tensors of ntiles + 1
+    (tile t covers positions [pos2[tile_fiber[t]], pos2[tile_fiber[t+1]]))."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    s = B.struct()
+    cap = s.nnz // max(T, 1) + 3
+    ts = torch.empty(cap, dtype=torch.int32, device=B.pos2.device)
+    tf = torch.empty(cap, dtype=torch.int32, device=B.pos2.device)
+    nt = ctypes.c_int64()
+    ctx.check(ctx.lib.spl_csf_tile_bounds(ctx.h, ctypes.byref(s), T, ts.data_ptr(),
+                                          tf.data_ptr(), cap, ctypes.byref(nt), stream),
+              "spl_csf_tile_bounds")
+    return ts[:nt.value + 1], tf[:nt.value + 1]
 
 
 def validate(B, ctx: Optional[Context] = None) -> None:

@@ -76,6 +76,7 @@ SIGNATURES = {
     "spl_op_parse": (_I32, [ctypes.c_char_p, ctypes.POINTER(_I32)]),
     "spl_workspace_query": (_I32, [_P, _I32, _SP, _I64, _SCH, ctypes.POINTER(_SZ)]),
     "spl_tile_bounds": (_I32, [_P, _SP, _SCH, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
+    "spl_csf_tile_bounds": (_I32, [_P, _SP, _I64, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "spl_validate": (_I32, [_P, _SP, _P]),
     "spl_timing_enable": (_I32, [_P, ctypes.c_int]),
     "spl_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),

@@ -898,6 +898,30 @@ spl_status spl_tile_bounds(spl_context *ctx, const spl_sparse *B, const spl_sche
     SPL_GUARD_END
 }
 
+spl_status spl_csf_tile_bounds(spl_context *ctx, const spl_sparse *B, int64_t T,
+                               int32_t *tile_slice, int32_t *tile_fiber, int64_t capacity,
+                               int64_t *ntiles, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 3));
+    if (dense_middle(B))
+        return fail(ctx, SPL_ERR_FORMAT, "CSF tile bounds need a Compressed middle level");
+    if (!tile_slice || !tile_fiber || !ntiles) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    if (T < 1) return fail(ctx, SPL_ERR_ARG, "T must be positive");
+    const int64_t nt = spl::tile_count(SPL_NNZ, 0, B->nnz, T);
+    *ntiles = nt;
+    if (capacity < nt + 1)
+        return fail(ctx, SPL_ERR_ARG, "capacity %lld < %lld tile bounds",
+                    static_cast<long long>(capacity), static_cast<long long>(nt + 1));
+    SPL_CHECK(set_device(ctx));
+    Tiles t{tile_slice, tile_fiber, nt};
+    SPL_HIP(spl::launch_csf_nnz_bounds(B->dims[0], B->pos[1], B->nfibers, B->pos[2], B->nnz, T, t,
+                                       static_cast<hipStream_t>(stream)),
+            "CSF bounds launch");
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
 spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream) {
     SPL_GUARD_BEGIN
     if (!ctx) return SPL_ERR_ARG;

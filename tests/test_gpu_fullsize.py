@@ -136,6 +136,20 @@ def test_config4_csf_ops():
     ref, S = oracle.spttv(h["pos1"], h["pos2"], h["crd2"], host64(vals32), host64(cv))
     assert_close(host64(A), ref, S, 1e-5, "spttv full size")
     del A, ref, S
+    # the fiber-aligned non-zero split bounds on sampled tiles, each checked
+    # by the oracle's preimage counts (the fiber holding position t*T, the
+    # slice holding that fiber)
+    for T in (2048, 65536):
+        ts, tf = spl.csf_tile_bounds(B, T)
+        ts, tf = ts.cpu().numpy(), tf.cpu().numpy()
+        nt = len(tf) - 1
+        assert nt == -(-int(h["crd2"].size) // T)
+        assert (ts[-1], tf[-1]) == (I, h["crd1"].size)
+        assert np.all(np.diff(tf) >= 0) and np.all(np.diff(ts) >= 0)
+        for t in np.unique(np.random.RandomState(T).randint(1, nt, 12)):
+            f = oracle.rows_finished_at(h["pos2"], int(t) * T)
+            assert tf[t] == f, (T, t)
+            assert ts[t] == oracle.rows_finished_at(h["pos1"], f), (T, t)
     # MTTKRP on sampled slices, FP32 and BF16
     rows = _sample_rows(h["pos1"], k=300, seed=3)
     for dt in (torch.float32, torch.bfloat16):

@@ -35,8 +35,11 @@ MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=
 MTTKRP_VEC4 = [dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
                dict(kind="merge", tile=1, col_tile=64, items_per_lane=4),
                dict(kind="merge", tile=3000, col_tile=32, items_per_lane=4)]
+# merge tiles of 2048 and 5000 items give the vector-ALU leaves several chunks
+# per workgroup (their default is one)
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
-                   dict(kind="merge", tile=512)]
+                   dict(kind="merge", tile=512), dict(kind="merge", tile=2048),
+                   dict(kind="merge", tile=5000)]
 
 
 def _spl():
@@ -526,3 +529,36 @@ def test_csf_leaves_deterministic():
         a1 = spl.spttv(B, cv, sched=spl.schedule(**sc)).clone()
         a2 = spl.spttv(B, cv, sched=spl.schedule(**sc))
         assert torch.equal(a1, a2), sc
+
+
+def test_csf_tile_bounds_bit_exact():
+    """The fiber-aligned non-zero split of a CSF tensor (the MTTKRP NNZ
+    schedule's bounds) equals the oracle's bit for bit: empty slices,
+    fibers longer than T, T = 1 and T past nnz."""
+    spl = _spl()
+    big = _numpy(configs.config4(scale=0.001, with_dense=False))
+    for c, Ts in ((_tiny_csf(3), (1, 2, 3, 7, 16, 64, 1000)),
+                  (big, (1000, 2048, 4099, 100000))):
+        B = _csf(spl, c, torch.float32)
+        nnz = len(c["crd2"])
+        assert np.diff(c["pos2"]).max() > 3   # some fiber is longer than the smallest T
+        for T in Ts + (nnz, nnz + 5):
+            ts, tf = spl.csf_tile_bounds(B, T)
+            rs_, rf, rp = oracle.csf_split(c["pos1"], c["pos2"], T)
+            gf = tf.cpu().numpy()
+            assert np.array_equal(ts.cpu().numpy(), rs_), T
+            assert np.array_equal(gf, rf), T
+            assert np.array_equal(c["pos2"][gf], rp), T
+
+
+def test_csf_tile_bounds_errors():
+    spl = _spl()
+    c = _tiny_csf(4)
+    B = _csf(spl, c, torch.float32)
+    with pytest.raises(spl.SpleafError):
+        spl.csf_tile_bounds(B, 0)
+    rs = np.random.RandomState(2)
+    pos2, crd2, v = tiny.ddc(rs, 3, 4, 20, 0.3)
+    Bd = spl.DDC(_t(pos2), _t(crd2), _t(v, torch.float64).float(), (3, 4, 20))
+    with pytest.raises(spl.SpleafError):
+        spl.csf_tile_bounds(Bd, 8)

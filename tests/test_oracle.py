@@ -466,18 +466,52 @@ def test_pieces_reassemble_whole_spmv(seed):
         assert np.array_equal(y, whole)
 
 
-def test_csf_split():
-    rs = np.random.RandomState(13)
-    p1, c1, p2, c2, v = tiny.csf(rs, 9, 6, 8, 0.5, empty_slices={2, 8})
+def _owner(pos):
+    """owner[q] = the parent entry whose segment [pos[e], pos[e+1]) holds
+    child q: the expansion of a Compressed level, written independently of
+    the counting the split functions do."""
+    owner = np.full(int(pos[-1]), -1, np.int64)
+    for e in range(len(pos) - 1):
+        owner[int(pos[e]):int(pos[e + 1])] = e
+    return owner
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_csf_split_against_set_definitions(seed):
+    """The fused (i,j,k) non-zero partition of a CSF tensor (Sec. II-B
+    fusion, then blocks of T positions), snapped to fibers and carried to
+    slices (Sec. III-A image and preimage, Table I), checked against the
+    set definitions by brute force: the boundary of block t is the first
+    position of the fiber that holds position t*T, and its slice is the
+    slice that holds that fiber; the tiles' positions partition [0, nnz)
+    into whole fibers; the fibers and slices named by a tile's positions
+    (preimages) lie in its own range."""
+    rs = np.random.RandomState(900 + seed)
+    I, J, K = int(rs.randint(1, 12)), int(rs.randint(1, 7)), int(rs.randint(1, 40))
+    empty = set(rs.choice(I, size=rs.randint(0, I), replace=False).tolist())
+    p1, c1, p2, c2, v = tiny.csf(rs, I, J, K, rs.uniform(0.05, 0.9), empty_slices=empty)
     F, nnz = int(p1[-1]), int(p2[-1])
-    for T in (1, 3, 10, 1000):
+    fib_of = _owner(p2)     # position -> fiber
+    sl_of = _owner(p1)      # fiber -> slice
+    for T in sorted({1, 2, 3, 5, 17, max(nnz, 1), nnz + 7}):
         ts, tf, tp = oracle.csf_split(p1, p2, T)
-        assert ts[0] == tf[0] == tp[0] == 0
-        assert (ts[-1], tf[-1], tp[-1]) == (9, F, nnz)
-        for t in range(len(tf)):
-            assert tp[t] == p2[tf[t]]                 # fiber aligned
-            if 0 < t < len(tf) - 1:
-                # first fiber not finished at position t*T
-                assert oracle.rows_finished_at(p2, t * T) == tf[t]
-                assert oracle.rows_finished_at(p1, tf[t]) == ts[t]
-        assert np.all(np.diff(tf) >= 0) and np.all(np.diff(ts) >= 0)
+        nt = len(tf) - 1
+        assert nt == max(1, -(-nnz // T))
+        assert (ts[0], tf[0], tp[0]) == (0, 0, 0)
+        assert (ts[-1], tf[-1], tp[-1]) == (I, F, nnz)
+        assert np.all(np.diff(tp) >= 0) and np.all(np.diff(tf) >= 0) and np.all(np.diff(ts) >= 0)
+        for t in range(1, nt):
+            f = int(fib_of[t * T])
+            assert tf[t] == f
+            assert tp[t] == int(np.flatnonzero(fib_of == f)[0])
+            assert ts[t] == int(sl_of[f])
+        tile_of = np.full(nnz, -1)
+        for t in range(nt):
+            tile_of[tp[t]:tp[t + 1]] = t
+            fibs = set(fib_of[tp[t]:tp[t + 1]].tolist())
+            assert fibs <= set(range(tf[t], tf[t + 1]))
+            slices = set(sl_of[f] for f in fibs)
+            assert slices <= set(range(ts[t], ts[t + 1] + 1))
+        assert np.all(tile_of >= 0)                     # every position covered once
+        for f in range(F):                              # fiber aligned
+            assert len(set(tile_of[p2[f]:p2[f + 1]].tolist())) <= 1
