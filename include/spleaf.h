@@ -269,6 +269,27 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
                     spl_dense *a, const spl_schedule *sched, void *workspace,
                     size_t workspace_bytes, spl_stream stream);
 
+/* SpMV that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, dtypes, schedules (ROW, NNZ, MERGE and
+ * their fields) and kernels as spl_spmv, with the same results bit for bit;
+ * the tile bounds and carries live in a static device array of 16 MiB
+ * (each GPU the library runs on holds one until the process ends; its
+ * address is looked up once per device by spl_context_create), so the call
+ * calls no hipMalloc/hipFree and takes no workspace.  Limits and errors:
+ * SPL_ERR_WORKSPACE when spl_workspace_query reports more than 16 MiB for
+ * this matrix and schedule (with the default MERGE schedule that is
+ * n + nnz beyond about 2e9 merged items; a longer tile needs less);
+ * SPL_ERR_UNSUPPORTED for SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE (they use
+ * the context's workspace); SPL_ERR_HIP when the scratch lookup failed on
+ * this device.  Leaf timing (spl_timing_enable) does not record this call.
+ * Every call on one GPU shares that GPU's scratch and leaves its contents
+ * behind (every entry the kernels read is written first in the same call,
+ * so nothing needs clearing): calls that overlap on one GPU -- on two
+ * streams, or from two host threads -- race and give undefined results. */
+spl_status spl_spmv_noalloc(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
+                            spl_dense *a, const spl_schedule *sched, spl_stream stream);
+
 /* Universe partition of B's Compressed level by coordinate value ranges,
  * carried to the rows by a preimage (Sec. III-A; Table I: a Compressed
  * level's universe partition colors each stored coordinate by the value

@@ -27,6 +27,7 @@ __all__ = [
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
     "schedule_dict", "coord_partition", "spmv_window", "DDC", "csf_tile_bounds",
+    "spmv_noalloc",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -244,6 +245,20 @@ def spmv(B: CSR, c: torch.Tensor, a: Optional[torch.Tensor] = None, sched=None,
                                ctypes.byref(_dense(a)),
                                ctypes.byref(sched) if sched else None,
                                _ptr(ws), nb, stream), "spl_spmv")
+    return a
+
+
+def spmv_noalloc(B: CSR, c: torch.Tensor, a: torch.Tensor, sched=None,
+                 ctx: Optional[Context] = None) -> torch.Tensor:
+    """a(i) = B(i,j) * c(j) through spl_spmv_noalloc: the library allocates
+    nothing (tile bounds and carries in its static device scratch), so `a`
+    must be given."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    s = B.struct()
+    ctx.check(ctx.lib.spl_spmv_noalloc(ctx.h, ctypes.byref(s), ctypes.byref(_dense(c)),
+                                       ctypes.byref(_dense(a)),
+                                       ctypes.byref(sched) if sched else None, stream),
+              "spl_spmv_noalloc")
     return a
 
 

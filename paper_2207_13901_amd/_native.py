@@ -82,6 +82,7 @@ SIGNATURES = {
     "spl_timing_read": (_I32, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "spl_probe": (_I32, [_P, ctypes.c_int, _P, _I64, _I64, _I64, _P, _I64, _P]),
     "spl_spmv": (_I32, [_P, _SP, _DP, _DP, _SCH, _P, _SZ, _P]),
+    "spl_spmv_noalloc": (_I32, [_P, _SP, _DP, _DP, _SCH, _P]),
     "spl_coord_partition": (_I32, [_P, _SP, _I32, _P, _P, _P]),
     "spl_spmv_window": (_I32, [_P, _SP, _P, _P, _DP, _DP, _SCH, _P]),
     "spl_spmm": (_I32, [_P, _SP, _DP, _DP, _SCH, _P, _SZ, _P]),

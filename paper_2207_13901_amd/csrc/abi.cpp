@@ -42,6 +42,7 @@ struct spl_context {
         int step = 0;
     };
     Selector sel[2];
+    hipError_t scratch_status = hipSuccess;  // spl::scratch_init on `device`
 };
 
 namespace {
@@ -710,6 +711,9 @@ spl_status spl_context_create(int device, spl_context **out) {
         delete ctx;
         return SPL_ERR_HIP;
     }
+    // device address of this GPU's static scratch (spl_spmv_noalloc); a
+    // failure is kept and reported by that call only
+    ctx->scratch_status = spl::scratch_init(device);
     *out = ctx;
     return SPL_OK;
     SPL_GUARD_END
@@ -1052,6 +1056,35 @@ spl_status spl_spmv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, s
                                    static_cast<double *>(cv.carry), a->data, s),
             "SpMV fix-up launch");
     return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_spmv_noalloc(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
+                            spl_dense *a, const spl_schedule *sched, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (selection_kind(sched))
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "spl_spmv_noalloc: learned and autotuned schedules need the context's "
+                    "workspace; pass a ROW, NNZ or MERGE schedule");
+    if (ctx->scratch_status != hipSuccess)
+        return hip_fail(ctx, ctx->scratch_status, "spl_spmv_noalloc: static scratch lookup");
+    void *ptr = spl::scratch_ptr(ctx->device);
+    if (!ptr) return fail(ctx, SPL_ERR_HIP, "spl_spmv_noalloc: no static scratch on this device");
+    size_t need = 0;
+    SPL_CHECK(spl_workspace_query(ctx, SPL_OP_SPMV, B, 1, sched, &need));
+    if (need > spl::kScratchBytes)
+        return fail(ctx, SPL_ERR_WORKSPACE,
+                    "spl_spmv_noalloc: this matrix and schedule need %zu bytes of tile bounds "
+                    "and carries; the static scratch holds %zu (use spl_spmv with a workspace, "
+                    "or a longer tile)",
+                    need, spl::kScratchBytes);
+    // leaf timing would create events: off for this call
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    const spl_status st = spl_spmv(ctx, B, c, a, sched, ptr, spl::kScratchBytes, stream);
+    ctx->timing = timing;
+    return st;
     SPL_GUARD_END
 }
 

@@ -166,4 +166,13 @@ hipError_t launch_validate_level(int64_t parents, const int32_t *pos, const int3
                                  int64_t children, int64_t extent, int64_t *flags,
                                  hipStream_t s);
 
+// ---- scratch.hip ---------------------------------------------------------
+// Bytes of the static device scratch behind spl_spmv_noalloc.
+constexpr size_t kScratchBytes = static_cast<size_t>(16) << 20;
+// Look up the scratch's device address on `device` (which must be current)
+// once; later calls return the first call's status.
+hipError_t scratch_init(int device);
+// The address scratch_init found for `device`, or nullptr.
+void *scratch_ptr(int device);
+
 }  // namespace spl
