@@ -246,15 +246,42 @@ def measure_ddc(dev, spl, tuning, torch):
     return out
 
 
-def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
+OPS = ("sddmm", "spadd3", "spttv", "mttkrp", "inner", "banded", "ddc", "coord", "banded64")
+
+
+def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True, only=None):
     """Every other leaf at its full workload: SDDMM and SpAdd3 on the three
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
     200,000^3 CSF tensor with 1e8 nonzeros.  SpTTV and SpMTTKRP run with the
     autotuned schedule unless `fixed` gives one ({"spttv": {...},
     "mttkrp": {...}}).  Median of 10 timed calls after
-    3 warm-up calls, inputs resident in HBM."""
+    3 warm-up calls, inputs resident in HBM.  `only`: a subset of OPS."""
     from workloads import configs
+    want = set(only) if only else set(OPS if next_rows else OPS[:5])
     res = {}
+    if want & {"sddmm", "spadd3"}:
+        _ops_config3(dev, spl, tuning, torch, configs, want, res)
+    if want & {"spttv", "mttkrp", "inner"}:
+        _ops_config4(dev, spl, tuning, torch, configs, want, res, fixed or {})
+    if "banded" in want:
+        res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
+    if "ddc" in want:
+        res["ddc"] = measure_ddc(dev, spl, tuning, torch)
+    if "coord" in want:
+        res["coord_partition"] = measure_coord_partition(dev, spl, tuning, torch)
+    if "banded64" in want:
+        res["spmv_banded_int64_f64"] = measure_banded64(dev, spl, tuning, torch)
+    res["workloads"] = {
+        "spadd3_sddmm": "3 CSR 1000000x1000000, Poisson(8) rows, 30% shared rows, K=128",
+        "csf": "CSF 200000^3, 100000000 nnz, power-law slices, R=32",
+        "banded": "CSR 20000000^2, rows i-17..i+17 (699999694 nnz), FP64",
+    }
+    return res
+
+
+def _ops_config3(dev, spl, tuning, torch, configs, want, res):
+    """SDDMM (FP32, BF16 on the vector ALUs, BF16 on the matrix cores) and
+    SpAdd3 on the three 1,000,000-row CSR matrices."""
     print("[bench] generating the 1e6-row SpAdd3/SDDMM operands", file=sys.stderr, flush=True)
     c3 = configs.config3(device=dev)
     n = c3["n"]
@@ -263,8 +290,9 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
            for k in "BCD"]
     B = ops[0]
     nnzB = B.crd.numel()
-    for name, fdt, variant in (("sddmm_f32", torch.float32, 0), ("sddmm_bf16_valu", torch.bfloat16, 0),
-                               ("sddmm_bf16_mfma", torch.bfloat16, 1)):
+    sddmm_forms = (("sddmm_f32", torch.float32, 0), ("sddmm_bf16_valu", torch.bfloat16, 0),
+                   ("sddmm_bf16_mfma", torch.bfloat16, 1))
+    for name, fdt, variant in sddmm_forms if "sddmm" in want else ():
         C = c3["Cd"].to(torch.float32).to(fdt)
         D = c3["Dd"].to(torch.float32).to(fdt)
         A = torch.empty(nnzB, dtype=torch.float32, device=dev)
@@ -274,17 +302,23 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
         nbytes = 4 * (n + 1) + 8 * nnzB + K * n * esz * 2 + 4 * nnzB
         res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1))
         del C, D, A
-    ms = tuning.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
-    out = spl.spadd3(*ops)
-    nnzA = out.crd.numel()
-    nnzs = sum(o.crd.numel() for o in ops)
-    nbytes = (3 * 4 * (n + 1) + 4 * nnzs + 4 * (n + 1)) + \
-             (3 * 4 * (n + 1) + 8 * nnzs + 4 * (n + 1) + 8 * nnzA)
-    res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA)
-    res["spadd3_f32"]["nnz_out"] = nnzA
-    del ops, B, out, c3
+    if "spadd3" in want:
+        ms = tuning.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
+        out = spl.spadd3(*ops)
+        nnzA = out.crd.numel()
+        nnzs = sum(o.crd.numel() for o in ops)
+        nbytes = (3 * 4 * (n + 1) + 4 * nnzs + 4 * (n + 1)) + \
+                 (3 * 4 * (n + 1) + 8 * nnzs + 4 * (n + 1) + 8 * nnzA)
+        res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA)
+        res["spadd3_f32"]["nnz_out"] = nnzA
+        del out
+    del ops, B, c3
     torch.cuda.empty_cache()
 
+
+def _ops_config4(dev, spl, tuning, torch, configs, want, res, fixed):
+    """SpTTV, SpMTTKRP (FP32 and BF16) and the inner products on the CSF
+    tensor of 200,000^3 with 1e8 nonzeros."""
     print("[bench] generating the 1e8-nonzero CSF tensor", file=sys.stderr, flush=True)
     c4 = configs.config4(device=dev)
     I, J, Kd = c4["I"], c4["J"], c4["K"]
@@ -294,20 +328,21 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
     B32 = spl.CSF(c4["pos1"], c4["crd1"], c4["pos2"], c4["crd2"], c4["vals"].to(torch.float32),
                   (I, J, Kd))
     cv = c4["c"].to(torch.float32)
-    At = torch.empty(F, dtype=torch.float32, device=dev)
-    # SpTTV is the SpMV leaf on the fiber level: the same candidate schedules
-    fixed = fixed or {}
-    if "spttv" in fixed:
-        best_t = fixed["spttv"]
-    else:
-        best_t, _ = tuning.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
-                                    TTV_CANDIDATES, reps=5)
-    st = spl.schedule(**best_t)
-    ms = tuning.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
-    res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
-    res["spttv_f32"]["schedule"] = best_t
-    del At
-    for name, dt in (("mttkrp_f32", torch.float32), ("mttkrp_bf16_f32acc", torch.bfloat16)):
+    if "spttv" in want:
+        At = torch.empty(F, dtype=torch.float32, device=dev)
+        # SpTTV is the SpMV leaf on the fiber level: the same candidate schedules
+        if "spttv" in fixed:
+            best_t = fixed["spttv"]
+        else:
+            best_t, _ = tuning.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
+                                        TTV_CANDIDATES, reps=5)
+        st = spl.schedule(**best_t)
+        ms = tuning.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
+        res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+        res["spttv_f32"]["schedule"] = best_t
+        del At
+    mttkrp_forms = (("mttkrp_f32", torch.float32), ("mttkrp_bf16_f32acc", torch.bfloat16))
+    for name, dt in mttkrp_forms if "mttkrp" in want else ():
         Bt = B32.with_vals(B32.vals.to(dt))
         C = c4["C"].to(torch.float32).to(dt)
         D = c4["D"].to(torch.float32).to(dt)
@@ -324,30 +359,142 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True):
         res[name] = _rate(ms, nbytes, 2 * R * (nnz + F))
         res[name]["schedule"] = best_k
         del Bt, C, D, M
-    B64 = B32.with_vals(c4["vals"])
-    C64 = B32.with_vals(c4["vals2"])
-    a = torch.empty(1, dtype=torch.float64, device=dev)
-    ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
-    res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
-    # the co-iteration of two patterns: the same coordinates in other arrays,
-    # so every fiber is looked up and every position matched
-    Cg = spl.CSF(c4["pos1"].clone(), c4["crd1"].clone(), c4["pos2"].clone(), c4["crd2"].clone(),
-                 c4["vals2"], (I, J, Kd))
-    ms = tuning.time_call(lambda: spl.inner(B64, Cg, a), reps=10, warmup=3)
-    res["inner_general_f64"] = _rate(ms, 2 * (4 * (I + 1) + 4 * F + 4 * (F + 1) + 12 * nnz),
-                                     2 * nnz)
-    del B64, C64, B32, Cg, c4
+    if "inner" in want:
+        B64 = B32.with_vals(c4["vals"])
+        C64 = B32.with_vals(c4["vals2"])
+        a = torch.empty(1, dtype=torch.float64, device=dev)
+        ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
+        res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
+        # the co-iteration of two patterns: the same coordinates in other
+        # arrays, so every fiber is looked up and every position matched
+        Cg = spl.CSF(c4["pos1"].clone(), c4["crd1"].clone(), c4["pos2"].clone(),
+                     c4["crd2"].clone(), c4["vals2"], (I, J, Kd))
+        ms = tuning.time_call(lambda: spl.inner(B64, Cg, a), reps=10, warmup=3)
+        res["inner_general_f64"] = _rate(
+            ms, 2 * (4 * (I + 1) + 4 * F + 4 * (F + 1) + 12 * nnz), 2 * nnz)
+        del B64, C64, Cg
+    del B32, c4
     torch.cuda.empty_cache()
-    if next_rows:
-        res["spmv_banded_f64"] = measure_banded(dev, spl, tuning, torch)
-        res["ddc"] = measure_ddc(dev, spl, tuning, torch)
-        res["coord_partition"] = measure_coord_partition(dev, spl, tuning, torch)
-        res["spmv_banded_int64_f64"] = measure_banded64(dev, spl, tuning, torch)
-    res["workloads"] = {
-        "spadd3_sddmm": f"3 CSR {n}x{n}, Poisson(8) rows, 30% shared rows, K={K}",
-        "csf": f"CSF {I}^3, {nnz} nnz, {F} fibers, R={R}",
-        "banded": "CSR 20000000^2, rows i-17..i+17 (699999694 nnz), FP64",
-    }
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_openmp(oracle, pos, crd, c2, N, torch):
+    """The CPU comparison of the whole step: double-precision SpMV and SpMM
+    loops with OpenMP over rows (dynamic, 1,024 rows a chunk) on every core
+    OpenMP is given, over the full matrix (FP64 values and operands); one
+    warm-up, median of 5."""
+    import numpy as np
+    base = oracle.CpuBaseline()
+    vals = np.ascontiguousarray(c2["vals"].cpu().numpy())
+    x = np.ascontiguousarray(c2["x"].cpu().numpy())
+    D = np.ascontiguousarray(c2["B"].cpu().numpy())
+    n = len(pos) - 1
+    y = np.empty(n)
+    A = np.empty((n, N))
+    times = []
+    for rep in range(6):
+        t0 = time.perf_counter()
+        base.spmv(pos, crd, vals, x, y)
+        base.spmm(pos, crd, vals, D, A)
+        if rep:
+            times.append(time.perf_counter() - t0)
+    t = sorted(times)[len(times) // 2]
+    nnz = int(pos[-1])
+    return {"value": round((2.0 * nnz + 2.0 * nnz * N) / t / 1e9, 3), "unit": "GFLOP/s",
+            "ms_per_step": round(1e3 * t, 2), "cores": base.threads(), "kind": "openmp_fp64",
+            "cpu_model": cpu_model(),
+            "sample": "the whole step (SpMV + SpMM N=32) over all rows, FP64, 1 warm-up, "
+                      "median of 5"}
+
+
+def precision_statement(dev, spl, torch, oracle, c2, B32, B16, D32, D16):
+    """Error of each BF16 result (FP32 accumulation) against the oracle on
+    (i) the BF16-rounded inputs and (ii) the original FP32 inputs, and of
+    the FP32 form against the oracle on its inputs, on sampled output rows
+    of the full workloads: SpMM on the power-law matrix, SDDMM (vector ALUs
+    and matrix cores) on the 1,000,000-row matrix, SpMTTKRP on the CSF
+    tensor.  Statistics: max and median |err| / S, ||err||_2 / ||ref||_2."""
+    import numpy as np
+    from workloads import configs
+
+    def h64(t):
+        return t.detach().to("cpu").to(torch.float64).numpy()
+
+    def sample(pos, k, heavy, seed):
+        deg = np.diff(pos)
+        rs = np.random.RandomState(seed)
+        return np.unique(np.concatenate([rs.choice(len(deg), k, replace=False),
+                                         np.argsort(deg)[-heavy:], [0, len(deg) - 1]]))
+
+    res = {}
+    pos, crd = c2["pos"].cpu().numpy(), c2["crd"].cpu().numpy()
+    rows = sample(pos, 400, 20, 1)
+    rt = torch.as_tensor(rows, device=dev)
+    ref32, S32 = oracle.spmm(pos, crd, h64(B32.vals), h64(D32), rows=rows)
+    ref16, S16 = oracle.spmm(pos, crd, h64(B16.vals), h64(D16), rows=rows)
+    got32 = h64(spl.spmm(B32, D32)[rt])
+    got16 = h64(spl.spmm(B16, D16)[rt])
+    res["spmm"] = {"fp32": oracle.error_statement(got32, ref32, S32),
+                   "bf16_vs_bf16_inputs": oracle.error_statement(got16, ref16, S16),
+                   "bf16_vs_fp32_inputs": oracle.error_statement(got16, ref32, S32),
+                   "rows_sampled": int(rows.size)}
+
+    c3 = configs.config3(device=dev)
+    n = c3["n"]
+    Bm = c3["B"]
+    hpos, hcrd = Bm["pos"].cpu().numpy(), Bm["crd"].cpu().numpy()
+    B = spl.CSR(Bm["pos"], Bm["crd"], Bm["vals"].to(torch.float32), (n, n))
+    rows = sample(hpos, 3000, 20, 2)
+    sub_pos = np.concatenate([[0], np.cumsum(np.diff(hpos)[rows])]).astype(np.int32)
+    sel = np.concatenate([np.arange(hpos[r], hpos[r + 1]) for r in rows])
+    rt = torch.as_tensor(rows, device=dev)
+    C32, Dd32 = c3["Cd"].to(torch.float32), c3["Dd"].to(torch.float32)
+    C16, Dd16 = C32.to(torch.bfloat16), Dd32.to(torch.bfloat16)
+    bv = h64(B.vals)[sel]
+    ref32, S32 = oracle.sddmm(sub_pos, hcrd[sel], bv, h64(C32[rt]), h64(Dd32))
+    ref16, S16 = oracle.sddmm(sub_pos, hcrd[sel], bv, h64(C16[rt]), h64(Dd16))
+    res["sddmm"] = {"fp32": oracle.error_statement(h64(spl.sddmm(B, C32, Dd32))[sel], ref32, S32),
+                    "positions_sampled": int(sel.size)}
+    for name, variant in (("bf16_valu", 0), ("bf16_mfma", 1)):
+        got = h64(spl.sddmm(B, C16, Dd16, sched=spl.schedule(variant=variant)))[sel]
+        res["sddmm"][name + "_vs_bf16_inputs"] = oracle.error_statement(got, ref16, S16)
+        res["sddmm"][name + "_vs_fp32_inputs"] = oracle.error_statement(got, ref32, S32)
+    del B, C32, Dd32, C16, Dd16, c3
+    torch.cuda.empty_cache()
+
+    c4 = configs.config4(device=dev)
+    h = {k: c4[k].cpu().numpy() for k in ("pos1", "crd1", "pos2", "crd2")}
+    I, J, Kd = c4["I"], c4["J"], c4["K"]
+    v32 = c4["vals"].to(torch.float32)
+    T32 = spl.CSF(c4["pos1"], c4["crd1"], c4["pos2"], c4["crd2"], v32, (I, J, Kd))
+    T16 = T32.with_vals(v32.to(torch.bfloat16))
+    F32, G32 = c4["C"].to(torch.float32), c4["D"].to(torch.float32)
+    F16, G16 = F32.to(torch.bfloat16), G32.to(torch.bfloat16)
+    rows = sample(h["pos1"], 200, 10, 3)
+    rt = torch.as_tensor(rows, device=dev)
+    ref32, S32 = oracle.mttkrp(h["pos1"], h["crd1"], h["pos2"], h["crd2"], h64(v32), h64(F32),
+                               h64(G32), rows=rows)
+    ref16, S16 = oracle.mttkrp(h["pos1"], h["crd1"], h["pos2"], h["crd2"], h64(T16.vals),
+                               h64(F16), h64(G16), rows=rows)
+    got32 = h64(spl.mttkrp(T32, F32, G32)[rt])
+    got16 = h64(spl.mttkrp(T16, F16, G16)[rt])
+    res["mttkrp"] = {"fp32": oracle.error_statement(got32, ref32, S32),
+                     "bf16_vs_bf16_inputs": oracle.error_statement(got16, ref16, S16),
+                     "bf16_vs_fp32_inputs": oracle.error_statement(got16, ref32, S32),
+                     "slices_sampled": int(rows.size)}
+    del T32, T16, F32, G32, F16, G16, c4
+    torch.cuda.empty_cache()
+    res["note"] = ("BF16 operands: SpMM vals and C; SDDMM C and D; MTTKRP vals, C and D; "
+                   "round to nearest even from FP32; default schedules")
     return res
 
 
@@ -374,6 +521,8 @@ def main():
                     help="leave out the banded and (Dense, Dense, Compressed) workloads")
     ap.add_argument("--ops-only", action="store_true",
                     help="only the SDDMM/SpAdd3/SpTTV/SpMTTKRP/inner-product measurements")
+    ap.add_argument("--only", type=str, default=None,
+                    help="with --ops-only: comma-separated subset of " + ",".join(OPS))
     ap.add_argument("--calibrate", action="store_true",
                     help="run a 1 GiB device copy first (counter scale reference)")
     args = ap.parse_args()
@@ -405,8 +554,11 @@ def main():
         op, js = item.split("=", 1)
         fixed[op] = json.loads(js)
     if args.ops_only:
+        only = args.only.split(",") if args.only else None
+        if only and not set(only) <= set(OPS):
+            ap.error(f"--only takes names from {','.join(OPS)}")
         print(json.dumps({"ops": measure_other_ops(dev, spl, tuning, torch, fixed,
-                                                   not args.no_next)}),
+                                                   not args.no_next, only)}),
               flush=True)
         return
     t0 = time.time()
@@ -497,6 +649,36 @@ def main():
     flops = 2.0 * nnz + 2.0 * nnz * N_COLS
     gflops = flops / (ms_per_step * 1e-3) / 1e9
 
+    # the same step in FP64 (the only precision the paper's example states),
+    # with its own autotuned schedules, under the same protocol
+    fp64_step = None
+    if not args.profile and not args.no_variants:
+        bv, _ = tuning.search(lambda s: (lambda: spl.spmv(B64, x64, y64, sched=s)),
+                              tuning.SPMV_CANDIDATES, reps=reps)
+        bm, _ = tuning.search(lambda s: (lambda: spl.spmm(B64, D64, A64, sched=s)),
+                              tuning.SPMM_CANDIDATES, reps=reps)
+        sv64, sm64 = spl.schedule(**bv), spl.schedule(**bm)
+        wv64 = spl.workspace(N.OP_SPMV, B64, 1, sv64)
+        wm64 = spl.workspace(N.OP_SPMM, B64, N_COLS, sm64)
+
+        def step64():
+            spl.spmv(B64, x64, y64, sched=sv64, ws=wv64)
+            spl.spmm(B64, D64, A64, sched=sm64, ws=wm64)
+
+        for _ in range(args.warmup):
+            step64()
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        for _ in range(args.steps):
+            step64()
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t64) / args.steps
+        fp64_step = {"ms_per_step": round(ms64, 4),
+                     "GFLOP_s": round((2.0 * nnz + 2.0 * nnz * N_COLS) / (ms64 * 1e-3) / 1e9, 2),
+                     "schedule_spmv": bv, "schedule_spmm": bm,
+                     "protocol": f"{args.warmup} warm-up then {args.steps} timed steps"}
+        del wv64, wm64
+
     # per-launch spread of the two leaf kernels (untimed loop after the
     # timed steps, one read-back per step), warm and with the 256 MB MALL
     # flushed by a 1 GiB write before each step
@@ -558,6 +740,7 @@ def main():
             "avg_launch_ms": round(spmm_ms, 5),
             "launches": lm,
         },
+        "fp64_step": fp64_step,
         "kernels": {
             "spmv_f32": {"avg_ms": round(spmv_ms, 5), "launches": lv,
                          "GB_s": round(bytes_v32 / (spmv_ms * 1e-3) / 1e9, 1),
@@ -575,6 +758,13 @@ def main():
         },
     }
 
+    if spread:
+        # the same kernel with the 256 MB MALL flushed before each launch
+        cold = spread["spmm"]["cold"]["median_ms"]
+        ach = bytes_m32 / (cold * 1e-3) / 1e9
+        out["roofline"]["mall_flushed"] = {"median_launch_ms": cold, "achieved": round(ach, 1),
+                                           "frac": round(ach / HBM_PEAK_GBS, 4)}
+
     if learned_out is not None:
         out["learned"] = learned_out
 
@@ -582,15 +772,26 @@ def main():
         var = {}
         bv64, bm64 = algorithmic_bytes(n, n, nnz, N_COLS, 8, 8, 8)
         _, bm16 = algorithmic_bytes(n, n, nnz, N_COLS, 2, 2, 4)
+        # BF16 values and dense rows (FP32 accumulation and output) with
+        # their own autotuned schedule
+        best16, res16 = tuning.search(lambda s: (lambda: spl.spmm(B16, D16, A32, sched=s)),
+                                      tuning.SPMM_BF16_CANDIDATES, reps=reps)
+        sm16 = spl.schedule(**best16)
         for name, fn, nbytes, fl in (
             ("spmv_f64", lambda: spl.spmv(B64, x64, y64, sched=sv), bv64, 2 * nnz),
             ("spmm_f64", lambda: spl.spmm(B64, D64, A64, sched=sm), bm64, 2 * nnz * N_COLS),
-            ("spmm_bf16_f32acc", lambda: spl.spmm(B16, D16, A32, sched=sm), bm16, 2 * nnz * N_COLS),
+            ("spmm_bf16_f32acc", lambda: spl.spmm(B16, D16, A32, sched=sm16), bm16,
+             2 * nnz * N_COLS),
         ):
             ms = tuning.time_call(fn, reps=10, warmup=3)
             var[name] = {"ms": round(ms, 5), "GFLOP_s": round(fl / (ms * 1e-3) / 1e9, 2),
                          "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        var["spmm_bf16_f32acc"]["schedule"] = best16
+        var["spmm_bf16_f32acc"]["schedules_ms"] = {json.dumps(c, sort_keys=True): round(t, 4)
+                                                   for c, t in res16}
+        var["spmm_bf16_f32acc"]["vs_fp32_autotuned"] = round(
+            min(t for _, t in res_m) / var["spmm_bf16_f32acc"]["ms"], 3)
         # the paper's fixed rules: SpMV row split, SpMM non-zero split
         rule_v = min((t for c, t in res_v if c["kind"] == "row"))
         rule_m = min((t for c, t in res_m if c["kind"] == "nnz"))
@@ -653,10 +854,16 @@ def main():
             "unit": "GFLOP/s",
             "cores": 1,
             "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": (f"SpMV over all {n} rows ({nnz} nnz, {t2 - t1:.2f}s) + SpMM N=32 over "
                        f"rows 0..{rows_m} ({int(pos[rows_m])} nnz, {t3 - t2:.2f}s); "
                        "single-threaded long-double C loops"),
         }
+        out["cpu_openmp_fp64"] = cpu_openmp(oracle, pos, crd, c2, N_COLS, torch)
+        print("[bench] precision statement", file=sys.stderr, flush=True)
+        out["precision"] = precision_statement(dev, spl, torch, oracle, c2, B32,
+                                               csr(torch.bfloat16), D32,
+                                               D32.to(torch.bfloat16))
     if args.profile:
         out["sources_digest"] = sources_digest(SPMM_SOURCES)
     print(json.dumps(out), flush=True)

@@ -329,11 +329,12 @@ spl_status spl_spmv_window(spl_context *ctx, const spl_sparse *B, const int32_t 
  * NNZ and MERGE splits a row that spans tiles is the finishing tile's
  * partial plus the other tiles' carries, added by the fix-up).  Schedules:
  * ROW, NNZ, MERGE (default MERGE); col_tile 8..64 columns per lane group.
- * sched->variant (MERGE): 0 = each lane reads and writes 4 F32, 2 F64 or 4
- * BF16 consecutive columns with one vector access when N, C->ld, A->ld and
- * the C and A pointers are multiples of that, col_tile leaves 8 to 32
- * lanes per group and items_per_lane is 8 or 16 (otherwise one column per
- * lane); 1 = one column per lane.
+ * sched->variant (MERGE): 0 = each lane reads and writes 4 F32, 2 F64 or 8
+ * BF16 consecutive columns (16 bytes of C) with one vector access when N,
+ * C->ld, A->ld and the C and A pointers are multiples of that, col_tile
+ * leaves 4 to 32 lanes per group and items_per_lane is 8 or 16 (otherwise
+ * one column per lane); 1 = one column per lane; 2 (BF16 only) = as 0 with
+ * 4 BF16 columns (8 bytes) per lane.
  * The workspace query returns the one-column-per-lane size, enough for
  * both.  SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE as for spl_spmv. */
 spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
@@ -365,7 +366,11 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * and writes 4 consecutive rank columns with one vector access when R,
  * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
  * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 4 or
- * 8 (otherwise one column per lane); 1 = one column per lane.
+ * 8 (otherwise one column per lane) -- with BF16 factors 8 rank columns
+ * (16 bytes) per lane instead when R and every ld are multiples of 8, C and
+ * D 16-byte aligned and (col_tile, items_per_lane) is (32, 4), (64, 4) or
+ * (64, 8); 1 = one column per lane; 2 (BF16 only, else SPL_ERR_ARG) = 4
+ * BF16 rank columns (8 bytes) per lane.
  * items_per_lane: 8 (default) or 16 for either leaf; 4 only with the
  * 4-column lanes (SPL_ERR_ARG when they do not apply): half the registers
  * and LDS of 8, so more waves per SIMD.  The workspace query returns the
@@ -428,6 +433,73 @@ spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_
 spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                               const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
                               void *A_vals, const spl_schedule *sched, spl_stream stream);
+
+/* ------------------------------------------- general index-notation leaves */
+
+/* One tensor of an index-notation statement, bound by name: exactly one of
+ * `sparse` (formats (D,C), (D,C,C) or (D,D,C), int32 positions) and `dense`
+ * (a vector or row-major matrix) is set.  All pointers inside are device
+ * pointers owned by the caller; `name` is a host string. */
+typedef struct spl_tin_operand {
+    const char *name;
+    const spl_sparse *sparse;
+    const spl_dense *dense;
+} spl_tin_operand;
+
+/* General statements of tensor index notation (Sec. II-A), beyond the seven
+ * fixed ones, evaluated by leaves the library generates (Sec. IV-C) and
+ * compiles at run time for gfx950 (hiprtc; the first call for a statement
+ * and set of operand formats compiles, later calls reuse the context's
+ * cache).
+ *
+ * Statement form: `Out(i,j) = T1 + T2 - ...` (or `Out(i) = ...`, or a scalar
+ * `out = ...`), each term a product of tensor accesses such as B(i,j,k) or
+ * c(k); every term uses the same index variables; variables not on the
+ * left are summed.  Semantics: Out = sum over the summed variables of the
+ * signed sum of the terms' products, an absent sparse entry counting as 0.
+ * Loop nest: one thread per coordinate of the outermost index, which must
+ * index every sparse operand first (their Dense first level) and be the
+ * output's first index; the other variables follow in an order concordant
+ * with every sparse operand's levels (Sec. IV-C), sparse-level variables
+ * before dense-only ones.  A variable indexed by Compressed levels is
+ * iterated by merging their sorted coordinates: the intersection within a
+ * product, the union across a sum (co-iteration); a variable some term
+ * reaches through no Compressed level is iterated over its whole extent.
+ * Sums run in F64 in a fixed order (deterministic).  Values: every operand
+ * and the output F64, or every one F32 (a scalar output is always F64).
+ *
+ * Outputs (`out`, named as the statement's left side):
+ *   dense vector or matrix: every entry written (assignment semantics);
+ *   scalar: a dense F64 vector of one entry;
+ *   CSR matrix (Dense, Compressed): assembled in two phases (Sec. V-B):
+ *     spl_tin_symbolic writes out->pos (A_pos, n+1 entries) and the count
+ *     of stored entries (the coordinates where the statement's
+ *     intersection/union structure holds, kept even when the value is 0),
+ *     then spl_tin_eval with out->sparse->pos[1] = A_pos writes crd (sorted
+ *     per row) and vals.
+ * Errors: SPL_ERR_ARG (syntax, unbound or misnamed tensors), SPL_ERR_SHAPE
+ * (extents disagree), SPL_ERR_FORMAT / SPL_ERR_DTYPE (operand formats or
+ * value types), SPL_ERR_UNSUPPORTED (a statement outside this form: an
+ * output whose first index is not the sparse operands' first, level orders
+ * with no common loop order, terms over different variables, repeated
+ * variables in one access), SPL_ERR_HIP (compilation or launch).
+ * Workspace: NULL for the context's pool, else at least
+ * spl_tin_workspace_query bytes. */
+spl_status spl_tin_workspace_query(spl_context *ctx, const char *tin, int nops,
+                                   const spl_tin_operand *ops, const spl_tin_operand *out,
+                                   size_t *bytes);
+spl_status spl_tin_symbolic(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                            const spl_tin_operand *out, int32_t *A_pos, int64_t *nnz_out,
+                            void *workspace, size_t workspace_bytes, spl_stream stream);
+spl_status spl_tin_eval(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                        const spl_tin_operand *out, void *workspace, size_t workspace_bytes,
+                        spl_stream stream);
+/* The HIP source generated for a statement and these operand formats
+ * (host buffer `buf` of `cap` bytes, NUL-terminated, truncated if short;
+ * *len receives the full length).  Compiles nothing and touches no GPU;
+ * ctx may be NULL (errors then carry no detail). */
+spl_status spl_tin_source(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                          const spl_tin_operand *out, char *buf, size_t cap, size_t *len);
 
 /* ------------------------------------------------- learned schedule choice */
 

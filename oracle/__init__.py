@@ -29,16 +29,26 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.c_int64
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (-O2, no fast-math)."""
-    stale = (not os.path.exists(_LIB)
-             or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+_OMP_SRC = os.path.join(_HERE, "cpu_baseline.c")
+_OMP_LIB = os.path.join(_HERE, "libcpu_baseline.so")
+
+
+def _gcc(src, lib, force, extra=()):
+    stale = (not os.path.exists(lib)
+             or os.path.getmtime(lib) < os.path.getmtime(src))
     if force or stale:
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+        tmp = lib + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-Wall", *extra, "-shared", "-fPIC",
+                               "-o", tmp, src])
+        os.replace(tmp, lib)
+    return lib
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so and the OpenMP CPU baseline into
+    libcpu_baseline.so with gcc (-O2, no fast-math)."""
+    _gcc(_OMP_SRC, _OMP_LIB, force, ("-fopenmp",))
+    return _gcc(_SRC, _LIB, force)
 
 
 _lib = None
@@ -352,3 +362,48 @@ def rows_finished_at(pos, p):
     """Number of rows whose segment ends at or before position p."""
     pos_a, pp = _i32(pos)
     return int(_load().orc_rows_finished_at(_i64(len(pos_a) - 1), pp, _i64(p)))
+
+
+def error_statement(got, ref, S):
+    """Error of a result against an oracle reference, entrywise normwise:
+    max and median of |got - ref| / S over the entries with S > 0 (S the
+    oracle's sum of |term|), and ||got - ref||_2 / ||ref||_2 (0 when both are
+    0).  Only statistics of the comparison: no arithmetic of the method."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    S = np.asarray(S, dtype=np.float64).ravel()
+    err = np.abs(got - ref)
+    pos = S > 0
+    rel = err[pos] / S[pos] if pos.any() else np.zeros(1)
+    nref = float(np.linalg.norm(ref))
+    nerr = float(np.linalg.norm(got - ref))
+    return {"max_err_over_S": float(rel.max()), "median_err_over_S": float(np.median(rel)),
+            "rel_l2": nerr / nref if nref > 0 else (0.0 if nerr == 0 else float("inf")),
+            "entries": int(got.size)}
+
+
+class CpuBaseline:
+    """The benchmark's CPU comparison: double-precision SpMV and SpMM loops
+    with OpenMP over rows (dynamic, 1,024 rows a chunk), not the oracle."""
+
+    def __init__(self):
+        build()
+        lib = ctypes.CDLL(_OMP_LIB)
+        lib.cpu_threads.restype = ctypes.c_int
+        self.lib = lib
+
+    def threads(self) -> int:
+        return int(self.lib.cpu_threads())
+
+    def spmv(self, pos, crd, vals, c, a):
+        n = len(pos) - 1
+        self.lib.cpu_spmv(_i64(n), pos.ctypes.data_as(_i32p), crd.ctypes.data_as(_i32p),
+                          vals.ctypes.data_as(_f64p), c.ctypes.data_as(_f64p),
+                          a.ctypes.data_as(_f64p))
+
+    def spmm(self, pos, crd, vals, C, A):
+        n = len(pos) - 1
+        self.lib.cpu_spmm(_i64(n), _i64(C.shape[1]), pos.ctypes.data_as(_i32p),
+                          crd.ctypes.data_as(_i32p), vals.ctypes.data_as(_f64p),
+                          C.ctypes.data_as(_f64p), _i64(C.shape[1]), A.ctypes.data_as(_f64p),
+                          _i64(A.shape[1]))

@@ -27,7 +27,7 @@ __all__ = [
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
     "schedule_dict", "coord_partition", "spmv_window", "DDC", "csf_tile_bounds",
-    "spmv_noalloc",
+    "spmv_noalloc", "tin", "tin_source",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -479,6 +479,114 @@ def spadd3(B: CSR, C: CSR, D: CSR, sched=None, ctx: Optional[Context] = None) ->
                                          _ptr(avals), _sched_ptr(sched), stream),
               "spl_spadd3_numeric")
     return CSR(apos, acrd, avals, B.shape)
+
+
+# -------------------------------------------- general index-notation leaves
+
+class _TinCall:
+    """Marshals one index-notation call: operands by name (CSR/CSF/DDC or a
+    dense torch vector/matrix), the output binding, and the structs that must
+    outlive the call."""
+
+    def __init__(self, stmt: str, operands: dict, out_name: str, out):
+        self.stmt = stmt.encode()
+        self.keep = []
+        arr = (N.SplTinOperand * max(1, len(operands)))()
+        for k, (name, t) in enumerate(operands.items()):
+            arr[k] = self._bind(name, t)
+        self.ops, self.nops = arr, len(operands)
+        self.out = self._bind(out_name, out)
+
+    def _bind(self, name, t):
+        op = N.SplTinOperand()
+        op.name = name.encode()
+        self.keep.append(op.name)
+        if isinstance(t, (CSR, CSF, DDC)):
+            s = t.struct()
+            self.keep.append(s)
+            op.sparse = ctypes.pointer(s)
+        else:
+            d = _dense(t)
+            self.keep.append(d)
+            op.dense = ctypes.pointer(d)
+        return op
+
+
+def _lhs_name(stmt: str) -> str:
+    head = stmt.split("=", 1)[0]
+    return head.split("(", 1)[0].strip()
+
+
+def tin_source(stmt: str, out, ctx: Optional[Context] = None, **operands) -> str:
+    """The HIP source the library generates for `stmt` with these operand
+    formats (nothing is compiled or run; no GPU needed without `ctx`)."""
+    lib = N.load()
+    h = ctx.h if ctx else None
+    call = _TinCall(stmt, operands, _lhs_name(stmt), out)
+    n = ctypes.c_size_t()
+
+    def check(st):
+        if st != N.OK:
+            detail = lib.spl_last_error(h).decode() if h else ""
+            raise SpleafError(st, f"spl_tin_source: {detail}")
+
+    check(lib.spl_tin_source(h, call.stmt, call.nops, call.ops, ctypes.byref(call.out), None, 0,
+                             ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    check(lib.spl_tin_source(h, call.stmt, call.nops, call.ops, ctypes.byref(call.out), buf,
+                             n.value + 1, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tin(stmt: str, out=None, shape=None, ctx: Optional[Context] = None, **operands):
+    """Evaluate an index-notation statement with a generated leaf.
+
+    out: a dense torch tensor (every entry written), or None with `shape`
+    given for a CSR output (assembled in two phases and returned), or None
+    with a scalar left side (returns a float64 tensor of one entry).
+    Operands are passed by the names the statement uses."""
+    first = next(iter(operands.values()))
+    vals = first.vals if isinstance(first, (CSR, CSF, DDC)) else first
+    ctx, stream = _ctx_stream(vals, ctx)
+    dev = vals.device
+    name = _lhs_name(stmt)
+    lhs = stmt.split("=", 1)[0]
+    scalar = "(" not in lhs or lhs[lhs.index("(") + 1:].strip().startswith(")")
+    if out is None and scalar:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    if out is not None:
+        call = _TinCall(stmt, operands, name, out)
+        nb = ctypes.c_size_t()
+        ctx.check(ctx.lib.spl_tin_workspace_query(ctx.h, call.stmt, call.nops, call.ops,
+                                                  ctypes.byref(call.out), ctypes.byref(nb)),
+                  "spl_tin_workspace_query")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev) if nb.value else None
+        ctx.check(ctx.lib.spl_tin_eval(ctx.h, call.stmt, call.nops, call.ops,
+                                       ctypes.byref(call.out), _ptr(ws), nb.value, stream),
+                  "spl_tin_eval")
+        return out
+    if shape is None:
+        raise ValueError("a sparse output needs its shape")
+    n = shape[0]
+    apos = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    empty = torch.empty(0, dtype=torch.int32, device=dev)
+    A = CSR(apos, empty, torch.empty(0, dtype=vals.dtype, device=dev), tuple(shape))
+    call = _TinCall(stmt, operands, name, A)
+    nb = ctypes.c_size_t()
+    ctx.check(ctx.lib.spl_tin_workspace_query(ctx.h, call.stmt, call.nops, call.ops,
+                                              ctypes.byref(call.out), ctypes.byref(nb)),
+              "spl_tin_workspace_query")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev) if nb.value else None
+    nnz = ctypes.c_int64()
+    ctx.check(ctx.lib.spl_tin_symbolic(ctx.h, call.stmt, call.nops, call.ops,
+                                       ctypes.byref(call.out), apos.data_ptr(), ctypes.byref(nnz),
+                                       _ptr(ws), nb.value, stream), "spl_tin_symbolic")
+    A = CSR(apos, torch.empty(nnz.value, dtype=torch.int32, device=dev),
+            torch.empty(nnz.value, dtype=vals.dtype, device=dev), tuple(shape))
+    call = _TinCall(stmt, operands, name, A)
+    ctx.check(ctx.lib.spl_tin_eval(ctx.h, call.stmt, call.nops, call.ops, ctypes.byref(call.out),
+                                   _ptr(ws), nb.value, stream), "spl_tin_eval")
+    return A
 
 
 # ------------------------------------------------------- schedule selection

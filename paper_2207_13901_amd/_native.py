@@ -57,6 +57,14 @@ class SplSchedule(ctypes.Structure):
     ]
 
 
+class SplTinOperand(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char_p),
+        ("sparse", ctypes.POINTER(SplSparse)),
+        ("dense", ctypes.POINTER(SplDense)),
+    ]
+
+
 _P = ctypes.c_void_p
 _SP = ctypes.POINTER(SplSparse)
 _DP = ctypes.POINTER(SplDense)
@@ -105,6 +113,17 @@ SIGNATURES = {
     "spl_mlp_save": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _SCH, _P, _P]),
     "spl_mlp_predict": (_I32, [_P, _I32, _SP, _SCH, _P]),
     "spl_mlp_train_step": (_I32, [_P, _I32, _P, _P, _I64, ctypes.c_float, _P, _P]),
+    "spl_tin_workspace_query": (_I32, [_P, ctypes.c_char_p, ctypes.c_int,
+                                       ctypes.POINTER(SplTinOperand),
+                                       ctypes.POINTER(SplTinOperand), ctypes.POINTER(_SZ)]),
+    "spl_tin_symbolic": (_I32, [_P, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(SplTinOperand),
+                                ctypes.POINTER(SplTinOperand), _P, ctypes.POINTER(_I64), _P, _SZ,
+                                _P]),
+    "spl_tin_eval": (_I32, [_P, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(SplTinOperand),
+                            ctypes.POINTER(SplTinOperand), _P, _SZ, _P]),
+    "spl_tin_source": (_I32, [_P, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(SplTinOperand),
+                              ctypes.POINTER(SplTinOperand), ctypes.c_char_p, _SZ,
+                              ctypes.POINTER(_SZ)]),
 }
 
 _lib = None

@@ -12,8 +12,12 @@
 #include <string>
 #include <vector>
 
+#include <map>
+#include <memory>
+
 #include "internal.hpp"
 #include "spleaf.h"
+#include "tin.hpp"
 
 struct spl_context {
     int device = 0;
@@ -43,6 +47,8 @@ struct spl_context {
     };
     Selector sel[2];
     hipError_t scratch_status = hipSuccess;  // spl::scratch_init on `device`
+    // generated leaves of index-notation statements, by statement and formats
+    std::map<std::string, std::unique_ptr<spl::tin::Program>> tin_cache;
 };
 
 namespace {
@@ -185,7 +191,6 @@ spl_status resolve_spmv(spl_context *ctx, const spl_sparse *B, const spl_schedul
 
 spl_status resolve_spmm(spl_context *ctx, const spl_sparse *B, int64_t N, const spl_schedule *s,
                         Plan &p) {
-    (void)B;
     spl_schedule d{};
     if (!s) s = &d;
     p.kind = s->kind == SPL_SCHED_DEFAULT ? SPL_MERGE : s->kind;
@@ -204,8 +209,12 @@ spl_status resolve_spmm(spl_context *ctx, const spl_sparse *B, int64_t N, const 
         return fail(ctx, SPL_ERR_ARG, "SpMM items_per_lane must be 8, 16 or 32");
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 256 / ct : 4 * (256 / ct) * p.items);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
-    if (s->variant != 0 && s->variant != 1)
-        return fail(ctx, SPL_ERR_ARG, "SpMM variant must be 0 (default) or 1 (4-byte lanes)");
+    if (s->variant < 0 || s->variant > 2)
+        return fail(ctx, SPL_ERR_ARG,
+                    "SpMM variant must be 0 (16-byte lanes), 1 (one column per lane) or 2 "
+                    "(8-byte BF16 lanes)");
+    if (s->variant == 2 && B->vtype != SPL_BF16)
+        return fail(ctx, SPL_ERR_ARG, "SpMM variant 2 (8-byte lanes) is for BF16 values");
     p.variant = s->variant;
     return SPL_OK;
 }
@@ -348,17 +357,18 @@ int64_t spmm_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.item
 
 size_t dtype_bytes(int dt) { return dt == SPL_F64 ? 8 : dt == SPL_F32 ? 4 : 2; }
 
-// Vector lanes for the merge-split SpMM leaf (variant 0): each lane reads
-// and writes spl::spmm_vec_width columns with one vector access, when the
-// columns, leading dimensions and pointers allow it and a lane group still
-// has 8 to 32 lanes and walks 8 or 16 items; otherwise one column per lane.
+// Vector lanes for the merge-split SpMM leaf: each lane reads and writes v
+// columns with one vector access (variant 0: spl::spmm_vec_width, 16 bytes;
+// variant 2: 4 BF16 columns, 8 bytes), when the columns, leading dimensions
+// and pointers allow it and a lane group still has 4 to 32 lanes and walks
+// 8 or 16 items; otherwise one column per lane.
 int spmm_vec(const Plan &p, int vtype, const spl_dense *C, const spl_dense *A) {
-    if (p.kind != SPL_MERGE || p.variant != 0 || p.items > 16) return 1;
-    const int v = spl::spmm_vec_width(vtype);
+    if (p.kind != SPL_MERGE || p.variant == 1 || p.items > 16) return 1;
+    const int v = p.variant == 2 ? 4 : spl::spmm_vec_width(vtype);
     const int64_t lanes = p.col_tile / v;
     const int64_t N = C->dims[1];
     const size_t cb = v * dtype_bytes(C->dtype), ab = v * dtype_bytes(A->dtype);
-    const bool ok = lanes >= 8 && lanes <= 32 && N % v == 0 && C->ld % v == 0 &&
+    const bool ok = lanes >= 4 && lanes <= 32 && N % v == 0 && C->ld % v == 0 &&
                     A->ld % v == 0 && reinterpret_cast<uintptr_t>(C->data) % cb == 0 &&
                     reinterpret_cast<uintptr_t>(A->data) % ab == 0;
     return ok ? v : 1;
@@ -448,28 +458,35 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     const int64_t chunk = (256 / (p.items <= 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
-    if (s->variant != 0 && s->variant != 1)
-        return fail(ctx, SPL_ERR_ARG, "MTTKRP variant must be 0 (default) or 1 (4-byte lanes)");
+    if (s->variant < 0 || s->variant > 2)
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP variant must be 0 (vector lanes), 1 (one column per lane) or 2 "
+                    "(8-byte BF16 lanes)");
     p.variant = s->variant;
     return SPL_OK;
 }
 
 int64_t mttkrp_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.items; }
 
-// Vector lanes for the MTTKRP leaf (variant 0): 4 rank columns per lane when
-// R, the leading dimensions and the pointers allow it, col_tile is 32 or 64
-// and items_per_lane 8; otherwise one column per lane.
+// Vector lanes for the MTTKRP leaf: v rank columns per lane when R, the
+// leading dimensions and the pointers allow it, col_tile is 32 or 64 and
+// items_per_lane 4 or 8; otherwise one column per lane.  v = 4 (16-byte
+// FP32 rows, 8-byte BF16 rows; BF16 variant 2), or for BF16 under variant 0
+// v = 8 (16-byte rows) with (col_tile, items) (32, 4), (64, 4) or (64, 8).
 int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_dense *A) {
-    constexpr int v = 4;
-    if (p.variant != 0 || (p.items != 8 && p.items != 4) || (p.col_tile != 32 && p.col_tile != 64))
+    if (p.variant == 1 || (p.items != 8 && p.items != 4) || (p.col_tile != 32 && p.col_tile != 64))
         return 1;
     const int64_t R = C->dims[1];
-    const size_t fb = v * dtype_bytes(C->dtype);
-    const bool ok = R % v == 0 && C->ld % v == 0 && D->ld % v == 0 && A->ld % v == 0 &&
-                    reinterpret_cast<uintptr_t>(C->data) % fb == 0 &&
-                    reinterpret_cast<uintptr_t>(D->data) % fb == 0 &&
-                    reinterpret_cast<uintptr_t>(A->data) % 16 == 0;
-    return ok ? v : 1;
+    auto fits = [&](int v) {
+        const size_t fb = v * dtype_bytes(C->dtype);
+        return R % v == 0 && C->ld % v == 0 && D->ld % v == 0 && A->ld % v == 0 &&
+               reinterpret_cast<uintptr_t>(C->data) % fb == 0 &&
+               reinterpret_cast<uintptr_t>(D->data) % fb == 0 &&
+               reinterpret_cast<uintptr_t>(A->data) % 16 == 0;
+    };
+    const bool bf = C->dtype == SPL_BF16;
+    if (bf && p.variant == 0 && (p.items == 4 || p.col_tile == 64) && fits(8)) return 8;
+    return fits(4) ? 4 : 1;
 }
 
 // MTTKRP pieces live in (slice, fiber) coordinates.
@@ -673,6 +690,50 @@ spl_status select_schedule(spl_context *ctx, spl_op op, const spl_sparse *B, con
     return SPL_OK;
 }
 
+// Bindings of one index-notation call, its plan for this call's operands,
+// and the compiled leaves for those formats (from the context's cache, or
+// generated and compiled now when `compile` is set).
+spl_status tin_prepare(spl_context *ctx, const char *stmt, int nops, const spl_tin_operand *ops,
+                       const spl_tin_operand *out, std::vector<spl::tin::Binding> &b,
+                       spl::tin::Binding &ob, spl::tin::Program &prog,
+                       spl::tin::Program **compiled) {
+    if (!stmt || !out || nops < 0 || (nops > 0 && !ops))
+        return fail(ctx, SPL_ERR_ARG, "NULL statement, operand list or output");
+    b.resize(static_cast<size_t>(nops));
+    for (int k = 0; k < nops; ++k) {
+        if (!ops[k].name) return fail(ctx, SPL_ERR_ARG, "operand %d has no name", k);
+        b[k].name = ops[k].name;
+        b[k].sparse = ops[k].sparse;
+        b[k].dense = ops[k].dense;
+    }
+    if (!out->name) return fail(ctx, SPL_ERR_ARG, "the output has no name");
+    ob.name = out->name;
+    ob.sparse = out->sparse;
+    ob.dense = out->dense;
+    std::string err;
+    spl_status st = spl::tin::plan(stmt, b, ob, prog, err);
+    if (st != SPL_OK) return fail(ctx, st, "%s", err.c_str());
+    if (!compiled) return SPL_OK;
+    auto it = ctx->tin_cache.find(prog.key);
+    if (it == ctx->tin_cache.end()) {
+        SPL_CHECK(set_device(ctx));
+        std::unique_ptr<spl::tin::Program> c(new spl::tin::Program(prog));
+        st = spl::tin::compile(*c, err);
+        if (st != SPL_OK) return fail(ctx, st, "%s", err.c_str());
+        it = ctx->tin_cache.emplace(prog.key, std::move(c)).first;
+    }
+    *compiled = it->second.get();
+    return SPL_OK;
+}
+
+hipError_t tin_launch(hipFunction_t f, int64_t rows, std::vector<unsigned long long> &slots,
+                      hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    void *args[] = {slots.data()};
+    return hipModuleLaunchKernel(f, static_cast<unsigned>((rows + 255) / 256), 1, 1, 256, 1, 1,
+                                 0, s, args, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -733,6 +794,7 @@ spl_status spl_context_destroy(spl_context *ctx) {
     for (auto &sl : ctx->sel)
         for (float *b : {sl.params, sl.norm, sl.m, sl.v, sl.scratch})
             if (b) (void)hipFree(b);
+    ctx->tin_cache.clear();  // unloads the generated modules on this device
     delete ctx;
     return SPL_OK;
     SPL_GUARD_END
@@ -1280,6 +1342,8 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                     "MTTKRP dtypes (vals, C, D, A) must be (F32,F32,F32,F32) or (BF16,BF16,BF16,F32)");
     Plan p;
     SPL_CHECK(resolve_mttkrp(ctx, R, sched, p));
+    if (p.variant == 2 && B->vtype != SPL_BF16)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP variant 2 (8-byte lanes) is for BF16 factors");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t I = B->dims[0];
@@ -1507,6 +1571,115 @@ spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_s
                                        A_crd, A_vals, s),
             "SpAdd3 numeric launch");
     tm.stop();
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_tin_workspace_query(spl_context *ctx, const char *tin, int nops,
+                                   const spl_tin_operand *ops, const spl_tin_operand *out,
+                                   size_t *bytes) {
+    SPL_GUARD_BEGIN
+    if (!ctx || !bytes) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    std::vector<spl::tin::Binding> b;
+    spl::tin::Binding ob;
+    spl::tin::Program prog;
+    SPL_CHECK(tin_prepare(ctx, tin, nops, ops, out, b, ob, prog, nullptr));
+    *bytes = spl::tin::workspace_bytes(prog, prog.out_kind == spl::tin::kOutCsr);
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_tin_source(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                          const spl_tin_operand *out, char *buf, size_t cap, size_t *len) {
+    SPL_GUARD_BEGIN
+    std::vector<spl::tin::Binding> b;
+    spl::tin::Binding ob;
+    spl::tin::Program prog;
+    SPL_CHECK(tin_prepare(ctx, tin, nops, ops, out, b, ob, prog, nullptr));
+    if (len) *len = prog.source.size();
+    if (buf && cap) {
+        const size_t n = std::min(cap - 1, prog.source.size());
+        std::memcpy(buf, prog.source.data(), n);
+        buf[n] = '\0';
+    }
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_tin_symbolic(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                            const spl_tin_operand *out, int32_t *A_pos, int64_t *nnz_out,
+                            void *workspace, size_t workspace_bytes, spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    if (!A_pos || !nnz_out) return fail(ctx, SPL_ERR_ARG, "NULL output");
+    std::vector<spl::tin::Binding> b;
+    spl::tin::Binding ob;
+    spl::tin::Program prog, *cp = nullptr;
+    SPL_CHECK(tin_prepare(ctx, tin, nops, ops, out, b, ob, prog, &cp));
+    if (prog.out_kind != spl::tin::kOutCsr)
+        return fail(ctx, SPL_ERR_ARG, "the symbolic phase is for sparse (CSR) outputs");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spl::tin::workspace_bytes(prog, true),
+                            &ws));
+    int64_t *tile_sum = static_cast<int64_t *>(ws);
+    int64_t *total = reinterpret_cast<int64_t *>(
+        static_cast<char *>(ws) + align_up(static_cast<size_t>(spl::spadd3_scan_tiles(prog.rows)) * 8));
+    std::vector<unsigned long long> slots;
+    spl::tin::fill_slots(prog, b, ob, A_pos, nullptr, nullptr, slots);
+    SPL_HIP(tin_launch(cp->f_count, prog.rows, slots, s), "generated count launch");
+    SPL_HIP(spl::launch_pos_scan(prog.rows, A_pos, tile_sum, total, s), "scan launch");
+    int64_t host_total = 0;
+    SPL_HIP(hipMemcpyAsync(&host_total, total, sizeof host_total, hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync");
+    SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (host_total > kIndexMax)
+        return fail(ctx, SPL_ERR_SHAPE, "output nnz %lld exceeds int32 positions",
+                    static_cast<long long>(host_total));
+    *nnz_out = host_total;
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_tin_eval(spl_context *ctx, const char *tin, int nops, const spl_tin_operand *ops,
+                        const spl_tin_operand *out, void *workspace, size_t workspace_bytes,
+                        spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    std::vector<spl::tin::Binding> b;
+    spl::tin::Binding ob;
+    spl::tin::Program prog, *cp = nullptr;
+    SPL_CHECK(tin_prepare(ctx, tin, nops, ops, out, b, ob, prog, &cp));
+    if (prog.out_kind == spl::tin::kOutCsr) {
+        if (!out->sparse->pos[1] || (out->sparse->nnz > 0 && (!out->sparse->crd[1] ||
+                                                               !out->sparse->vals)))
+            return fail(ctx, SPL_ERR_ARG, "a sparse output needs pos (from spl_tin_symbolic), "
+                                          "crd and vals");
+    } else if (!out->dense->data) {
+        return fail(ctx, SPL_ERR_ARG, "the output has no data");
+    }
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spl::tin::workspace_bytes(prog, false),
+                            &ws));
+    char *wp = static_cast<char *>(ws);
+    void *partials = nullptr, *scratch = nullptr;
+    if (prog.out_kind == spl::tin::kOutScalar) {
+        partials = wp;
+        wp += align_up(static_cast<size_t>(prog.rows) * 8);
+    }
+    if (prog.scratch_rows) scratch = wp;
+    std::vector<unsigned long long> slots;
+    const int32_t *apos = prog.out_kind == spl::tin::kOutCsr ? out->sparse->pos[1] : nullptr;
+    spl::tin::fill_slots(prog, b, ob, apos, partials, scratch, slots);
+    hipFunction_t f = prog.out_kind == spl::tin::kOutCsr ? cp->f_fill : cp->f_eval;
+    SPL_HIP(tin_launch(f, prog.rows, slots, s), "generated leaf launch");
+    if (prog.out_kind == spl::tin::kOutScalar)
+        SPL_HIP(spl::launch_inner_final(prog.rows, static_cast<const double *>(partials),
+                                        static_cast<double *>(out->dense->data), s),
+                "final reduction launch");
     return SPL_OK;
     SPL_GUARD_END
 }

@@ -31,6 +31,8 @@ namespace {
 
 // Rank columns per lane of k_mttkrp_vec (16-byte FP32, 8-byte BF16 rows).
 constexpr int kMttkrpVec = 4;
+// rank columns per lane of BF16 factors read 16 bytes at a time
+constexpr int kMttkrpVecWide = 8;
 
 __device__ __forceinline__ int64_t finished_at(const int32_t *pos, int64_t rows, int64_t p) {
     int64_t lo = 0, hi = rows;
@@ -233,7 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];
-    __shared__ Acc s_c[G][ITEMS][W * VEC];  // C rows of each group's fibers
+    // C rows of each group's fibers, as loaded (BF16 stays packed)
+    __shared__ RowVec<VEC, FT> s_c[G][ITEMS][W];
     __shared__ Acc s_head[G][W * VEC];
     __shared__ Acc s_tail[G][W * VEC];
     __shared__ int s_done[G];
@@ -324,13 +327,12 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         const int np = static_cast<int>(s_fp[b1] - P0);
 
         // every C-row and D-row gather of the group before any is used
-        Acc cv[ITEMS][VEC];
+        // (BF16 rows stay packed until they are read)
+        RowVec<VEC, FT> cv[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) cv[k][v] = 0;
-            if (b0 + k < b1 && colok)
-                load_row<VEC>(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0, cv[k]);
+            cv[k].zero();
+            if (b0 + k < b1 && colok) cv[k].load(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0);
         }
         int kq[kPosCap];
         Acc vq[kPosCap];
@@ -350,13 +352,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
                 }
             }
         }
-        Acc dv[kPosCap][VEC];
+        RowVec<VEC, FT> dv[kPosCap];
 #pragma unroll
         for (int q = 0; q < kPosCap; ++q) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) dv[q][v] = 0;
-            if (q < np && colok)
-                load_row<VEC>(D + static_cast<int64_t>(kq[q]) * ldd + col0, dv[q]);
+            dv[q].zero();
+            if (q < np && colok) dv[q].load(D + static_cast<int64_t>(kq[q]) * ldd + col0);
         }
         // the next chunk's staging, when it is a whole piece (no search):
         // issued after this chunk's gathers, it lands while they are used
@@ -386,10 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             }
         }
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) s_c[g][k][lane * VEC + v] = cv[k][v];
-        }
+        for (int k = 0; k < ITEMS; ++k) s_c[g][k][lane] = cv[k];
 
         Acc acc[VEC], t[VEC];
 #pragma unroll
@@ -409,10 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         };
         auto close_fiber = [&]() {
             while (a < a1 && s_end[a] <= cf + f) finish(a++);
-            const Acc *crow = &s_c[g][f - b0][lane * VEC];
+            const RowVec<VEC, FT> crow = s_c[g][f - b0][lane];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                acc[v] += crow[v] * t[v];
+                acc[v] += static_cast<Acc>(crow.at(v)) * t[v];
                 t[v] = 0;
             }
             ++f;
@@ -422,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             if (q < np) {
                 while (P0 + q >= s_fp[f + 1]) close_fiber();
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) t[v] += vq[q] * dv[q][v];
+                for (int v = 0; v < VEC; ++v) t[v] += vq[q] * static_cast<Acc>(dv[q].at(v));
             }
         }
         for (int q = kPosCap; q < np; ++q) {  // positions past the register cap
@@ -430,11 +427,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             if (colok) {
                 const bool staged = kStage && rel0 + q < kStagePos;
                 const int32_t kk = staged ? s_kq[rel0 + q] : load_stream(crd2 + P0 + q);
-                Acc d[VEC];
-                load_row<VEC>(D + static_cast<int64_t>(kk) * ldd + col0, d);
+                RowVec<VEC, FT> d;
+                d.load(D + static_cast<int64_t>(kk) * ldd + col0);
                 const Acc vv = staged ? s_vq[rel0 + q] : widen<Acc>(load_stream(vals + P0 + q));
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) t[v] += vv * d[v];
+                for (int v = 0; v < VEC; ++v) t[v] += vv * static_cast<Acc>(d.at(v));
             }
         }
         while (f < b1) close_fiber();
@@ -555,8 +552,8 @@ hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
                                      ldd, A, lda, t.row, t.pos, t.ntiles, stride, carry);
         return hipGetLastError();
     };
-    if (vec > 1) {
-        if (vec != kMttkrpVec || (items != 8 && items != 4)) return hipErrorInvalidValue;
+    if (vec == kMttkrpVec) {
+        if (items != 8 && items != 4) return hipErrorInvalidValue;
         if (items == 4) {
             if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float>);
             if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float>);
@@ -566,6 +563,17 @@ hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
         if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float>);
         return hipErrorInvalidValue;
     }
+    if constexpr (sizeof(FT) == 2) {
+        // 16-byte BF16 lanes: chunks of at most 256 merged items (lanes x
+        // items >= 32), as the one-item-per-thread staging needs
+        if (vec == kMttkrpVecWide) {
+            if (lanes == 4 && items == 4) return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float>);
+            if (lanes == 8 && items == 4) return go(k_mttkrp_vec<8, 4, kMttkrpVecWide, V, FT, float>);
+            if (lanes == 8 && items == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVecWide, V, FT, float>);
+            return hipErrorInvalidValue;
+        }
+    }
+    if (vec > 1) return hipErrorInvalidValue;
     if (col_tile == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
                                           : go(k_mttkrp_tiles<16, 16, V, FT, float>);
     if (col_tile == 64) return items <= 8 ? go(k_mttkrp_tiles<64, 8, V, FT, float>)

@@ -132,6 +132,49 @@ __device__ __forceinline__ void store_row(double *p, const Acc (&a)[VEC]) {
     }
 }
 
+// VEC consecutive elements of a gathered dense row, held as loaded: FP32
+// and FP64 as values, BF16 packed two per 32-bit register and widened only
+// when read (at), so a row segment in flight takes half the registers.
+template <int VEC, typename BT>
+struct RowVec {
+    BT v[VEC];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) v[k] = 0;
+    }
+    __device__ __forceinline__ void load(const BT *p) { load_row<VEC>(p, v); }
+    __device__ __forceinline__ BT at(int k) const { return v[k]; }
+};
+template <int VEC>
+struct RowVec<VEC, bf16> {
+    static constexpr int kWords = VEC == 1 ? 1 : VEC / 2;
+    uint32_t w[kWords];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < kWords; ++k) w[k] = 0;
+    }
+    __device__ __forceinline__ void load(const bf16 *p) {
+        if constexpr (VEC == 1) {
+            w[0] = static_cast<uint32_t>(p->bits) << 16;
+        } else if constexpr (VEC == 4) {
+            typedef uint32_t vu32x2 __attribute__((ext_vector_type(2)));
+            const vu32x2 x = *reinterpret_cast<const vu32x2 *>(p);  // 8-byte access
+            w[0] = x[0];
+            w[1] = x[1];
+        } else {
+            static_assert(VEC == 8, "BF16 rows: 1, 4 or 8 per lane");
+            const vu32x4 x = *reinterpret_cast<const vu32x4 *>(p);  // 16-byte access
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = x[k];
+        }
+    }
+    // element 2k sits in the low half of word k (little-endian)
+    __device__ __forceinline__ float at(int k) const {
+        if constexpr (VEC == 1) return __uint_as_float(w[0]);
+        return __uint_as_float((k & 1) ? (w[k >> 1] & 0xffff0000u) : (w[k >> 1] << 16));
+    }
+};
+
 // Sum over aligned groups of L lanes (L a power of two <= 64) with xor
 // butterflies; every lane of the group ends with the group total.
 template <int L, typename T>

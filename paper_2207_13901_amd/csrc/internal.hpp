@@ -133,6 +133,10 @@ int64_t spadd3_scan_tiles(int64_t n);
 // tile_sum holds spadd3_scan_tiles(n) entries; the sum goes to *total.
 hipError_t launch_window_offsets(int64_t n, const int32_t *begin, const int32_t *end,
                                  int32_t *vpos, int64_t *tile_sum, int64_t *total, hipStream_t s);
+// In-place scan of per-row counts apos[1..n] into a pos array (apos[0] = 0);
+// tile_sum holds spadd3_scan_tiles(n) entries, the total goes to *total.
+hipError_t launch_pos_scan(int64_t n, int32_t *apos, int64_t *tile_sum, int64_t *total,
+                           hipStream_t s);
 hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
                                   const int32_t *cp, const int32_t *cc, const int32_t *dp,
                                   const int32_t *dc, int32_t *apos, int64_t *tile_sum,

@@ -290,6 +290,21 @@ hipError_t launch_window_offsets(int64_t n, const int32_t *begin, const int32_t 
     return hipGetLastError();
 }
 
+hipError_t launch_pos_scan(int64_t n, int32_t *apos, int64_t *tile_sum, int64_t *total,
+                           hipStream_t s) {
+    // apos[1..n] hold counts: scanned in place, apos[0] = 0
+    const int64_t nt = spadd3_scan_tiles(n);
+    k_scan_tile_sums<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, nullptr,
+                                                                        nullptr, tile_sum);
+    hipError_t e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_prefix<<<1, kBlock, 0, s>>>(nt, tile_sum, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_scan_tile_apply<<<dim3(static_cast<unsigned>(nt)), kBlock, 0, s>>>(n, apos + 1, nullptr,
+                                                                         nullptr, tile_sum, apos);
+    return hipGetLastError();
+}
+
 hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *bc,
                                   const int32_t *cp, const int32_t *cc, const int32_t *dp,
                                   const int32_t *dc, int32_t *apos, int64_t *tile_sum,

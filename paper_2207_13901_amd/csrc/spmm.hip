@@ -274,13 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         const int a1 = static_cast<int>(merge_search(d1, nr, np, cp, end_at));
         const int b0 = d0 - a0, b1 = d1 - a1;
         // every gather of the group's positions is issued before any is used
-        Acc pv[ITEMS][VEC];
+        // (BF16 rows stay packed until they are read)
+        RowVec<VEC, BT> pv[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) pv[k][v] = 0;
+            pv[k].zero();
             if (b0 + k < b1 && colok)
-                load_row<VEC>(Bd + static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col0, pv[k]);
+                pv[k].load(Bd + static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col0);
         }
         Acc acc[VEC];
 #pragma unroll
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
                 while (a < a1 && send[a] <= cp + b0 + k) finish(a++);
                 const Acc sv = s_val[buf][b0 + k];
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[v] += sv * pv[k][v];
+                for (int v = 0; v < VEC; ++v) acc[v] += sv * static_cast<Acc>(pv[k].at(v));
             }
         }
         while (a < a1) finish(a++);
@@ -367,12 +367,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
 }
 
 
-// Columns per lane of the vector-lane leaf: one 16-byte access for FP32 and
-// FP64 rows, one 8-byte access for BF16 rows (so 32 BF16 columns still take
-// a group of 8 lanes).
+// Columns per lane of the vector-lane leaf: one 16-byte access (4 FP32, 2
+// FP64 or 8 BF16 columns), so a 32-column BF16 row takes a group of 4 lanes
+// and half the gather instructions of FP32.  BF16 rows can also be read 4
+// columns (8 bytes) per lane (kSpmmVecNarrow).
 template <typename BT>
-constexpr int kSpmmVec = sizeof(BT) == 2 ? 4 : 16 / static_cast<int>(sizeof(BT));
+constexpr int kSpmmVec = 16 / static_cast<int>(sizeof(BT));
+constexpr int kSpmmVecNarrow = 4;
 
+#define SPL_SPMM_ARGS n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s
 template <typename V, typename BT, typename OT, typename Acc>
 struct SpmmTypes {
     static hipError_t row(int W, int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
@@ -419,25 +422,40 @@ struct SpmmTypes {
                                            static_cast<OT *>(Out), ldo, s);
     }
 
+    // vector lanes of VEC columns each: col_tile / VEC lanes per group
+    template <int VEC>
+    static hipError_t tiles_vec(int col_tile, int items, int64_t n, int64_t N,
+                                const int32_t *pos, const int32_t *crd, const void *vals,
+                                const void *Bd, int64_t ldb, void *Out, int64_t ldo,
+                                const Tiles &t, int64_t stride, bool exact, void *carry,
+                                hipStream_t s) {
+        switch (col_tile / VEC) {
+        case 4: return items <= 8 ? tiles_w<4, 8, VEC>(SPL_SPMM_ARGS)
+                                  : tiles_w<4, 16, VEC>(SPL_SPMM_ARGS);
+        case 8: return items <= 8 ? tiles_w<8, 8, VEC>(SPL_SPMM_ARGS)
+                                  : tiles_w<8, 16, VEC>(SPL_SPMM_ARGS);
+        case 16: return items <= 8 ? tiles_w<16, 8, VEC>(SPL_SPMM_ARGS)
+                                   : tiles_w<16, 16, VEC>(SPL_SPMM_ARGS);
+        case 32: return items <= 8 ? tiles_w<32, 8, VEC>(SPL_SPMM_ARGS)
+                                   : tiles_w<32, 16, VEC>(SPL_SPMM_ARGS);
+        default: return hipErrorInvalidValue;
+        }
+    }
+
     // col_tile columns per lane group; vec > 1 (merge split only): vec
     // columns per lane, so col_tile / vec lanes per group
     static hipError_t tiles(int col_tile, int items, int vec, int64_t n, int64_t N,
                             const int32_t *pos, const int32_t *crd, const void *vals,
                             const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
                             int64_t stride, bool exact, void *carry, hipStream_t s) {
-#define SPL_SPMM_ARGS n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s
         if (vec > 1) {
-            constexpr int VEC = kSpmmVec<BT>;
-            if (vec != VEC || !exact || (items != 8 && items != 16)) return hipErrorInvalidValue;
-            switch (col_tile / VEC) {
-            case 8: return items <= 8 ? tiles_w<8, 8, VEC>(SPL_SPMM_ARGS)
-                                      : tiles_w<8, 16, VEC>(SPL_SPMM_ARGS);
-            case 16: return items <= 8 ? tiles_w<16, 8, VEC>(SPL_SPMM_ARGS)
-                                       : tiles_w<16, 16, VEC>(SPL_SPMM_ARGS);
-            case 32: return items <= 8 ? tiles_w<32, 8, VEC>(SPL_SPMM_ARGS)
-                                       : tiles_w<32, 16, VEC>(SPL_SPMM_ARGS);
-            default: return hipErrorInvalidValue;
+            if (!exact || (items != 8 && items != 16)) return hipErrorInvalidValue;
+            if (vec == kSpmmVec<BT>) return tiles_vec<kSpmmVec<BT>>(col_tile, items, SPL_SPMM_ARGS);
+            if constexpr (sizeof(BT) == 2) {
+                if (vec == kSpmmVecNarrow)
+                    return tiles_vec<kSpmmVecNarrow>(col_tile, items, SPL_SPMM_ARGS);
             }
+            return hipErrorInvalidValue;
         }
 #define SPL_SPMM_ITEMS(Wv)                                                                    \
     if (items <= 8) return tiles_w<Wv, 8, 1>(SPL_SPMM_ARGS);                                  \
@@ -450,9 +468,9 @@ struct SpmmTypes {
         default: SPL_SPMM_ITEMS(32)
         }
 #undef SPL_SPMM_ITEMS
-#undef SPL_SPMM_ARGS
     }
 };
+#undef SPL_SPMM_ARGS
 
 }  // namespace
 

@@ -27,6 +27,17 @@ SPMM_CANDIDATES: List[Dict] = (
      for it in (8, 16, 32) for k in (1, 4)]
 )
 
+# BF16 values and dense rows: 16-byte lanes (8 columns, 4 lanes per 32-column
+# group) by default, 8-byte lanes (variant 2) as the alternative
+SPMM_BF16_CANDIDATES: List[Dict] = (
+    [dict(kind="row", col_tile=32)] +
+    [dict(kind="nnz", tile=T, col_tile=32, items_per_lane=16) for T in (256, 1024)] +
+    [dict(kind="merge", tile=64 * it * k, col_tile=32, items_per_lane=it)
+     for it in (8, 16) for k in (1, 4)] +
+    [dict(kind="merge", tile=32 * it, col_tile=32, items_per_lane=it, variant=2)
+     for it in (8, 16)]
+)
+
 
 MTTKRP_CANDIDATES: List[Dict] = [
     # 4 items per lane group: the 4-column-lane leaf only (R and every ld

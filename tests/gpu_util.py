@@ -35,3 +35,17 @@ def assert_close(got, ref, S, rtol, what=""):
             f"{np.unravel_index(k, got.shape)} got {got.flat[k]!r} ref {ref.flat[k]!r} "
             f"S {S.flat[k]!r}")
     return float(np.max(err / np.where(S > 0, S, 1.0))) if err.size else 0.0
+
+
+# Unit roundoff of BF16: 8 significand bits, round to nearest even.
+BF16_U = 2.0 ** -8
+
+
+def bf16_total_bound(k, rtol=1e-5):
+    """Bound on |got - ref| / S when `got` sums products of k BF16-rounded
+    factors (the rest exact) to within rtol, and ref, S come from the oracle
+    on the unrounded inputs: rounding moves each term t by at most
+    ((1 + u)^k - 1)|t|, and the accumulation error rtol is relative to the
+    rounded terms' sum of magnitudes, at most (1 + u)^k S."""
+    g = (1.0 + BF16_U) ** k
+    return (g - 1.0) + rtol * g

@@ -4,12 +4,14 @@ one by one: the 2,000,000-row power-law matrix (SpMV, SpMM), the three
 (SpTTV, SpMTTKRP, inner product).  Inputs are generated on the GPU and
 copied to the host for the oracle; the schedules are the ones the benchmark
 chooses among (its autotuner's candidates)."""
+import json
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from tests.gpu_util import assert_close, host64, need_gpu
+from tests.gpu_util import assert_close, bf16_total_bound, host64, need_gpu
 from workloads import configs
 
 pytestmark = pytest.mark.gpu
@@ -87,10 +89,19 @@ def test_config2_spmm_sampled(c2):
         D = c["B"].to(torch.float32).to(dtype)
         Dh = host64(D)
         ref, S = oracle.spmm(h["pos"], h["crd"], host64(B.vals), Dh, rows=rows)
+        if dtype == torch.bfloat16:
+            # (ii) total error against the oracle on the unrounded FP32 inputs
+            ref32, S32 = oracle.spmm(h["pos"], h["crd"], host64(c["vals"].to(torch.float32)),
+                                     host64(c["B"].to(torch.float32)), rows=rows)
         for cand in tuning.SPMM_CANDIDATES[1:]:
             A = spl.spmm(B, D, sched=spl.schedule(**cand))
             got = host64(A[torch.as_tensor(rows, device=A.device)])
             assert_close(got, ref, S, rtol, f"spmm {dtype} {cand}")
+            if dtype == torch.bfloat16:
+                assert_close(got, ref32, S32, bf16_total_bound(2), f"spmm bf16 total {cand}")
+                print("spmm bf16 " + json.dumps(
+                    {"schedule": cand, "vs_bf16_inputs": oracle.error_statement(got, ref, S),
+                     "vs_fp32_inputs": oracle.error_statement(got, ref32, S32)}))
         del D
 
 
@@ -104,13 +115,24 @@ def test_config3_sddmm_and_spadd3():
     rows = _sample_rows(hpos, k=3000, seed=2)
     sub_pos = np.concatenate([[0], np.cumsum(np.diff(hpos)[rows])]).astype(np.int32)
     sel = np.concatenate([np.arange(hpos[r], hpos[r + 1]) for r in rows])
+    C32 = c["Cd"].to(torch.float32)
+    D32 = c["Dd"].to(torch.float32)
+    # (ii) the oracle on the unrounded FP32 factors, for the BF16 forms
+    ref32, S32 = oracle.sddmm(sub_pos, hcrd[sel], host64(B.vals)[sel],
+                              host64(C32[torch.as_tensor(rows, device=C32.device)]), host64(D32))
     for fdt, variant in ((torch.float32, 0), (torch.bfloat16, 0), (torch.bfloat16, 1)):
-        C = c["Cd"].to(torch.float32).to(fdt)
-        D = c["Dd"].to(torch.float32).to(fdt)
+        C = C32.to(fdt)
+        D = D32.to(fdt)
         A = spl.sddmm(B, C, D, sched=spl.schedule(variant=variant))
         Ch = host64(C[torch.as_tensor(rows, device=C.device)])
         ref, S = oracle.sddmm(sub_pos, hcrd[sel], host64(B.vals)[sel], Ch, host64(D))
-        assert_close(host64(A)[sel], ref, S, 1e-5, f"sddmm {fdt} variant {variant}")
+        got = host64(A)[sel]
+        assert_close(got, ref, S, 1e-5, f"sddmm {fdt} variant {variant}")
+        if fdt == torch.bfloat16:
+            assert_close(got, ref32, S32, bf16_total_bound(2), f"sddmm bf16 total {variant}")
+            print(f"sddmm bf16 variant {variant} " + json.dumps(
+                {"vs_bf16_inputs": oracle.error_statement(got, ref, S),
+                 "vs_fp32_inputs": oracle.error_statement(got, ref32, S32)}))
         del C, D
     ops = [spl.CSR(c[k]["pos"], c[k]["crd"], c[k]["vals"].to(torch.float32), (n, n))
            for k in "BCD"]
@@ -152,15 +174,26 @@ def test_config4_csf_ops():
             assert ts[t] == oracle.rows_finished_at(h["pos1"], f), (T, t)
     # MTTKRP on sampled slices, FP32 and BF16
     rows = _sample_rows(h["pos1"], k=300, seed=3)
+    C32 = c["C"].to(torch.float32)
+    D32 = c["D"].to(torch.float32)
+    ref32 = S32 = None
     for dt in (torch.float32, torch.bfloat16):
         Bt = B.with_vals(vals32.to(dt))
-        C = c["C"].to(torch.float32).to(dt)
-        D = c["D"].to(torch.float32).to(dt)
+        C = C32.to(dt)
+        D = D32.to(dt)
         M = spl.mttkrp(Bt, C, D)
         ref, S = oracle.mttkrp(h["pos1"], h["crd1"], h["pos2"], h["crd2"], host64(Bt.vals),
                                host64(C), host64(D), rows=rows)
-        assert_close(host64(M[torch.as_tensor(rows, device=M.device)]), ref, S, 1e-5,
-                     f"mttkrp {dt}")
+        got = host64(M[torch.as_tensor(rows, device=M.device)])
+        assert_close(got, ref, S, 1e-5, f"mttkrp {dt}")
+        if dt == torch.float32:
+            ref32, S32 = ref, S  # the FP32 inputs are the unrounded ones
+        else:
+            # (ii) three BF16-rounded factors per term: vals, C and D
+            assert_close(got, ref32, S32, bf16_total_bound(3), "mttkrp bf16 total")
+            print("mttkrp bf16 " + json.dumps(
+                {"vs_bf16_inputs": oracle.error_statement(got, ref, S),
+                 "vs_fp32_inputs": oracle.error_statement(got, ref32, S32)}))
     # inner product in FP64: uniform[0, 1] values, so no cancellation
     B64 = B.with_vals(c["vals"])
     C64 = B.with_vals(c["vals2"])

@@ -129,6 +129,48 @@ def test_mttkrp_integer_values_bit_exact():
         assert np.array_equal(host64(A), ref), sc
 
 
+MTTKRP_BF16 = MTTKRP_VEC4 + [
+    dict(kind="merge", tile=256, col_tile=64, items_per_lane=8),
+    dict(kind="merge", tile=4096, col_tile=64, items_per_lane=8),
+    dict(kind="nnz", tile=1000, col_tile=32, items_per_lane=4),
+    dict(kind="row", tile=5, col_tile=32, items_per_lane=4),
+    # 8-byte lanes (4 BF16 rank columns per lane)
+    dict(kind="merge", tile=512, col_tile=32, items_per_lane=4, variant=2),
+    dict(kind="merge", tile=700, col_tile=32, items_per_lane=8, variant=2)]
+
+
+@pytest.mark.parametrize("R", [32, 24, 16, 40, 8, 12])
+def test_mttkrp_bf16_lane_widths(R):
+    # 16-byte lanes of 8 BF16 rank columns (4 or 8 lanes per group) and
+    # 8-byte lanes, R a multiple of 8 or only of 4; small-integer values make
+    # every product and sum exact (bit-exact against the oracle), random
+    # values stay within the tolerance
+    spl = _spl()
+    rs = np.random.RandomState(R)
+    for kind in ("int", "sym"):
+        c = _numpy(configs.config4(scale=0.001, R=R)) if kind == "sym" else \
+            _tiny_csf(6, kind="int")
+        J, K = c["J"], c["K"]
+        if kind == "int":
+            Cn, Dn = rs.randint(-4, 5, (J, R)), rs.randint(-4, 5, (K, R))
+        else:
+            Cn, Dn = c["C"], c["D"]
+        B = _csf(spl, c, torch.bfloat16)
+        C = _t(Cn, torch.float64).to(torch.float32).to(torch.bfloat16)
+        D = _t(Dn, torch.float64).to(torch.float32).to(torch.bfloat16)
+        ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
+                               host64(C), host64(D))
+        for sc in MTTKRP_BF16:
+            A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+            if kind == "int":
+                assert np.array_equal(host64(A), ref), (R, sc)
+            else:
+                assert_close(host64(A), ref, S, 1e-5, f"mttkrp bf16 R={R} {sc}")
+    with pytest.raises(spl.SpleafError, match="variant 2"):
+        B32 = _csf(spl, c, torch.float32)
+        spl.mttkrp(B32, C.float(), D.float(), sched=spl.schedule(**MTTKRP_BF16[-1]))
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_inner_product(dtype):
     spl = _spl()

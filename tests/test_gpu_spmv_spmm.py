@@ -272,6 +272,39 @@ def test_spmm_powerlaw_scaled(dtype, N):
         assert_close(host64(A), ref, S, RTOL[dtype], f"{dtype} N={N} {sc}")
 
 
+BF16_SCHEDULES = [
+    dict(kind="default"), dict(kind="merge", tile=512, col_tile=32, items_per_lane=16),
+    dict(kind="merge", tile=256, col_tile=32, items_per_lane=8),
+    dict(kind="merge", tile=4096, col_tile=64, items_per_lane=8),
+    dict(kind="merge", tile=1024, col_tile=16, items_per_lane=16),
+    # 8-byte lanes (4 BF16 columns per lane)
+    dict(kind="merge", tile=512, col_tile=32, items_per_lane=16, variant=2),
+    dict(kind="merge", tile=3000, col_tile=16, items_per_lane=8, variant=2),
+]
+
+
+@pytest.mark.parametrize("N", [32, 24, 40, 16, 8, 72, 5])
+def test_spmm_bf16_lane_widths(N):
+    # 16-byte lanes (8 BF16 columns: 2 to 8 lanes per group) and 8-byte
+    # lanes, N a multiple of 8 or not; small-integer values make every
+    # product and sum exact, so every schedule matches the oracle bit for bit
+    spl = _spl()
+    c2 = configs.config2(scale=0.004, N=N, kind="int")
+    B = _csr(spl, c2["pos"], c2["crd"], c2["vals"], (c2["n"], c2["n"]), torch.bfloat16)
+    Bd = c2["B"].to(torch.bfloat16).to(dev())
+    ref, _ = oracle.spmm(c2["pos"].numpy(), c2["crd"].numpy(), host64(B.vals), host64(Bd))
+    for sc in BF16_SCHEDULES:
+        A = spl.spmm(B, Bd, sched=spl.schedule(**sc))
+        assert np.array_equal(host64(A), ref), (N, sc)
+    c2 = configs.config2(scale=0.004, N=N)
+    B = _csr(spl, c2["pos"], c2["crd"], c2["vals"], (c2["n"], c2["n"]), torch.bfloat16)
+    Bd = c2["B"].to(torch.bfloat16).to(dev())
+    ref, S = oracle.spmm(c2["pos"].numpy(), c2["crd"].numpy(), host64(B.vals), host64(Bd))
+    for sc in BF16_SCHEDULES:
+        A = spl.spmm(B, Bd, sched=spl.schedule(**sc))
+        assert_close(host64(A), ref, S, 1e-5, f"bf16 N={N} {sc}")
+
+
 @pytest.mark.parametrize("name", list(_edge_cases().keys()))
 def test_spmm_edge_cases(name):
     spl = _spl()
