@@ -377,6 +377,62 @@ def _ops_config4(dev, spl, tuning, torch, configs, want, res, fixed):
     torch.cuda.empty_cache()
 
 
+def measure_live_regret(dev, spl, tuning, torch, count=40, max_nnz=1e7):
+    """The learned selectors against the exhaustive autotuner, measured in
+    this run: the first `count` held-out matrices of the 2,000-matrix corpus
+    (seeded; the training set never saw them) with at most `max_nnz`
+    nonzeros; every candidate schedule timed (median of 5), the selector's
+    choice from the matrix's features on the GPU.  Regret = t(choice) /
+    t(fastest) - 1 per matrix, for the learned choice, the library default
+    and the paper's fixed rule (SpMV row split, SpMM non-zero split; the
+    best of that kind on these matrices)."""
+    import numpy as np
+    from paper_2207_13901_amd import learned
+    from workloads import corpus
+    _, test_ids = corpus.split(2000, 400)
+    ids = [i for i in test_ids if corpus.spec(i)["nnz_target"] <= max_nnz][:count]
+    sels = {}
+    for op in ("spmv", "spmm"):
+        path = os.path.join(learned.DATA_DIR, f"selector_{op}.json")
+        if os.path.exists(path):
+            sels[op] = learned.Selector.from_json(json.load(open(path)))
+    if not sels:
+        return None
+    times = {op: [] for op in sels}
+    chosen = {op: [] for op in sels}
+    for i in ids:
+        s, pos, crd, vals = corpus.generate(i, dev)
+        n = s["n"]
+        B = spl.CSR(pos, crd, vals, (n, n))
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty(n, dtype=torch.float32, device=dev)
+        D = torch.ones(n, learned.SPMM_COLS, dtype=torch.float32, device=dev)
+        A = torch.empty(n, learned.SPMM_COLS, dtype=torch.float32, device=dev)
+        for op, sel in sels.items():
+            call = (lambda sc: spl.spmv(B, x, y, sched=sc)) if op == "spmv" else \
+                (lambda sc: spl.spmm(B, D, A, sched=sc))
+            cands = learned.candidates(op)
+            times[op].append([tuning.time_call(lambda c=c: call(spl.schedule(**c)), reps=5)
+                              for c in cands])
+            chosen[op].append(cands.index(sel.choose(B)))
+        del B, pos, crd, vals, x, y, D, A
+    torch.cuda.empty_cache()
+    out = {"matrices": len(ids), "max_nnz": max_nnz,
+           "families": {f: sum(1 for i in ids if corpus.spec(i)["family"] == f)
+                        for f in corpus.FAMILIES}}
+    for op in sels:
+        T = np.asarray(times[op])
+        cands = learned.candidates(op)
+        default = cands.index(learned.LIBRARY_DEFAULT[op])
+        kind = "row" if op == "spmv" else "nnz"
+        rule = min((k for k, c in enumerate(cands) if c["kind"] == kind),
+                   key=lambda k: float(np.mean(T[:, k] / T.min(1))))
+        out[op] = {"learned": learned.regret(T, np.asarray(chosen[op])),
+                   "library_default": learned.regret(T, np.full(len(T), default)),
+                   "paper_rule": learned.regret(T, np.full(len(T), rule))}
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -616,6 +672,8 @@ def main():
             learned_out[op] = {"learned_choice": choice, "autotuned_choice": best,
                                "learned_ms": round(t_learned, 5), "autotuned_ms": round(t_best, 5),
                                "regret": round(t_learned / t_best - 1.0, 4)}
+        print("[bench] live held-out regret", file=sys.stderr, flush=True)
+        learned_out["held_out_live"] = measure_live_regret(dev, spl, tuning, torch)
         regret_path = os.path.join(learned.DATA_DIR, "regret.json")
         if os.path.exists(regret_path):
             rep = json.load(open(regret_path))

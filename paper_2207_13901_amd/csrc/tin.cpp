@@ -283,7 +283,8 @@ struct Gen {
             if (conj[t].empty()) always = true;
         }
         auto P = [&](const Part &x) { return num(x.a) + "_" + num(x.l); };
-        auto A = [&](const Part &x) { return num(x.a); };
+        // the merge state of access a at level l: q, e, m suffixed a_l
+        auto A = [&](const Part &x) { return num(x.a) + "_" + num(x.l); };
         for (const Part &x : parts) {
             const std::string par = num(x.a) + "_" + num(x.l - 1);
             e.line("i64 q" + A(x) + " = h" + par + " ? (i64)P" + P(x) + "[p" + par + "] : 0, e" +
@@ -331,8 +332,7 @@ struct Gen {
         const int v = order[depth];
         for (const auto &x : parts) {
             const std::string n = num(x.a) + "_" + num(x.l);
-            e.line("const i64 p" + n + " = q" + num(x.a) + "; const bool h" + n + " = m" + num(x.a) +
-                   ";");
+            e.line("const i64 p" + n + " = q" + n + "; const bool h" + n + " = m" + n + ";");
         }
         for (const auto &x : dlev) {
             const std::string n = num(x.a) + "_" + num(x.l), par = num(x.a) + "_" + num(x.l - 1);
