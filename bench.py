@@ -303,6 +303,11 @@ def _ops_config3(dev, spl, tuning, torch, configs, want, res):
         res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1))
         del C, D, A
     if "spadd3" in want:
+        # the numeric phase's input staging: 1 direct, 2 coordinates in LDS,
+        # 3 coordinates and values in LDS (whole calls, both phases)
+        var_ms = {v: tuning.time_call(
+            lambda v=v: spl.spadd3(*ops, sched=spl.schedule("row", variant=v)), reps=10, warmup=3)
+            for v in (1, 2, 3)}
         ms = tuning.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
         out = spl.spadd3(*ops)
         nnzA = out.crd.numel()
@@ -311,6 +316,7 @@ def _ops_config3(dev, spl, tuning, torch, configs, want, res):
                  (3 * 4 * (n + 1) + 8 * nnzs + 4 * (n + 1) + 8 * nnzA)
         res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA)
         res["spadd3_f32"]["nnz_out"] = nnzA
+        res["spadd3_f32"]["variants_ms"] = {str(v): round(t, 5) for v, t in var_ms.items()}
         del out
     del ops, B, c3
     torch.cuda.empty_cache()
@@ -845,6 +851,18 @@ def main():
             var[name] = {"ms": round(ms, 5), "GFLOP_s": round(fl / (ms * 1e-3) / 1e9, 2),
                          "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                          "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # wide columns (N = 128): the dense operand that an MFMA form of SpMM
+        # would contract; timed on the vector-lane leaf
+        D128 = torch.empty(n, 128, dtype=torch.float32, device=dev).uniform_(-1, 1)
+        A128 = torch.empty(n, 128, dtype=torch.float32, device=dev)
+        ms = tuning.time_call(lambda: spl.spmm(B32, D128, A128), reps=10, warmup=3)
+        _, b128 = algorithmic_bytes(n, n, nnz, 128, 4, 4, 4)
+        var["spmm_f32_N128"] = {"ms": round(ms, 5),
+                                "GFLOP_s": round(2 * nnz * 128 / (ms * 1e-3) / 1e9, 2),
+                                "GB_s": round(b128 / (ms * 1e-3) / 1e9, 1),
+                                "frac_hbm": round(b128 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "gathered_row_GB_s": round(nnz * 512 / (ms * 1e-3) / 1e9, 1)}
+        del D128, A128
         var["spmm_bf16_f32acc"]["schedule"] = best16
         var["spmm_bf16_f32acc"]["schedules_ms"] = {json.dumps(c, sort_keys=True): round(t, 4)
                                                    for c, t in res16}

@@ -107,9 +107,13 @@ typedef void *spl_stream; /* a hipStream_t; NULL is the null stream */
  * [pos[2][f], pos[2][f+1]).  pos_type SPL_I64: pos[l] holds the address of
  * an int64 array (cast to the declared pointer type), so nnz may exceed
  * 2^31 - 1 (a matrix that fills a large part of one GPU's memory); crd
- * stays int32 (every dimension is below 2^31).  Only spl_spmv (CSR, MERGE
- * schedule, variant 0) and its workspace query accept SPL_I64; every other
- * call returns SPL_ERR_UNSUPPORTED for it. */
+ * stays int32 (every dimension is below 2^31).  SPL_I64 is accepted by
+ * spl_spmv (CSR, MERGE schedule, variant 0), spl_spmm (CSR, MERGE schedule,
+ * 16-byte vector lanes), spl_spttv (MERGE schedule, variant 0; only the last
+ * level's pos is read, as int64), spl_mttkrp (CSF with a Compressed middle
+ * level, MERGE schedule, vector lanes; pos[1] and pos[2] int64, fewer than
+ * 2^31 fibers) and their workspace queries; every other call returns
+ * SPL_ERR_UNSUPPORTED for it. */
 typedef struct spl_sparse {
     int32_t order;          /* 2 (CSR) or 3 (CSF)                              */
     int32_t vtype;          /* spl_dtype of vals                               */
@@ -429,10 +433,31 @@ spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_
  * increasing per row, *nnz_out entries) and A_vals (same dtype as the
  * operands, F64 or F32): each value sums the operands present at that
  * coordinate in the order B, C, D; a sum that cancels to zero keeps its
- * coordinate. */
+ * coordinate.  sched->variant picks how a workgroup reads its rows' inputs:
+ * 0 library default (1), 1 directly from memory, 2 coordinate runs staged
+ * in LDS, 3 coordinates and values staged (runs longer than the stage fall
+ * back to direct reads); every variant gives the same bits. */
 spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                               const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
                               void *A_vals, const spl_schedule *sched, spl_stream stream);
+
+/* ------------------------------------------------------ transposition */
+
+/* The CSR arrays of B^T from those of B (B CSR n x m, int32 positions; values
+ * F64, F32 or BF16, moved bit for bit).  The format language stores a CSC
+ * matrix as (Dense, Compressed) over the reversed dimension order
+ * (Sec. II-B), i.e. as the CSR arrays of its transpose: passing a CSC
+ * matrix A as the n x m CSR of A^T gives A's CSR (m x n), which every CSR
+ * leaf takes.  Outputs (device, caller-owned): T_pos m + 1 entries, T_crd
+ * and T_vals nnz entries, rows of B^T with strictly increasing coordinates.
+ * A stable LSD radix sort of the entries by column (8-bit digits, integer
+ * counts and ranks only): deterministic and exact.  Workspace: NULL for the
+ * context's pool, else at least spl_transpose_workspace_query bytes (about
+ * 16 bytes per nonzero). */
+spl_status spl_transpose_workspace_query(spl_context *ctx, const spl_sparse *B, size_t *bytes);
+spl_status spl_transpose(spl_context *ctx, const spl_sparse *B, int32_t *T_pos, int32_t *T_crd,
+                         void *T_vals, void *workspace, size_t workspace_bytes,
+                         spl_stream stream);
 
 /* ------------------------------------------- general index-notation leaves */
 

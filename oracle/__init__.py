@@ -364,6 +364,39 @@ def rows_finished_at(pos, p):
     return int(_load().orc_rows_finished_at(_i64(len(pos_a) - 1), pp, _i64(p)))
 
 
+def transpose(pos, crd, vals, shape):
+    """CSR arrays (pos, crd, vals) of B^T for B = CSR (pos, crd, vals) of
+    shape (n, m); a CSC matrix passed as the CSR of its transpose comes back
+    as its CSR."""
+    lib = _load()
+    n, m = shape
+    pos, pp = _i32(pos)
+    crd, cp = _i32(crd)
+    vals, vp = _f64(vals)
+    nnz = int(pos[n]) if n else 0
+    tpos = np.zeros(m + 1, dtype=np.int32)
+    tcrd = np.zeros(max(nnz, 1), dtype=np.int32)
+    tvals = np.zeros(max(nnz, 1), dtype=np.float64)
+    lib.orc_transpose(_i64(n), _i64(m), pp, cp, vp, tpos.ctypes.data_as(_i32p),
+                      tcrd.ctypes.data_as(_i32p), tvals.ctypes.data_as(_f64p))
+    return tpos, tcrd[:nnz], tvals[:nnz]
+
+
+def csc_spmv(cpos, crd, vals, x, n):
+    """y(i) = A(i,j) x(j) for A n x m stored as CSC (cpos over columns,
+    row coordinates in crd); returns (y, S)."""
+    lib = _load()
+    m = len(cpos) - 1
+    cpos, pp = _i32(cpos)
+    crd, cp = _i32(crd)
+    vals, vp = _f64(vals)
+    x, xp = _f64(x)
+    y, yp = _out(n)
+    S, sp = _out(n)
+    lib.orc_csc_spmv(_i64(n), _i64(m), pp, cp, vp, xp, yp, sp)
+    return y, S
+
+
 def error_statement(got, ref, S):
     """Error of a result against an oracle reference, entrywise normwise:
     max and median of |got - ref| / S over the entries with S > 0 (S the

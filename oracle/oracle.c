@@ -550,3 +550,53 @@ int64_t orc_csf_split(int64_t I, const int32_t *pos1, const int32_t *pos2,
     }
     return ntiles;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Transposition: the CSR arrays of B^T from those of B (n x m).            */
+/* A CSC matrix is (Dense, Compressed) over the reversed dimension order     */
+/* (Sec. II-B), so the CSR of A^T read as CSC is A; transposing it gives A's */
+/* CSR.  Definition: column c of B^T's rows holds B's entries of column c in */
+/* increasing row order -- each column's count, their running sum as tpos,   */
+/* then one sweep over B's rows in order appending each entry to its         */
+/* column.  Values are moved unchanged.                                      */
+/* ------------------------------------------------------------------------ */
+void orc_transpose(int64_t n, int64_t m, const int32_t *pos, const int32_t *crd,
+                   const double *vals, int32_t *tpos, int32_t *tcrd, double *tvals)
+{
+    int64_t *next = (int64_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    for (int64_t c = 0; c <= m; ++c) tpos[c] = 0;
+    for (int64_t p = 0; p < pos[n]; ++p) tpos[crd[p] + 1] += 1;
+    for (int64_t c = 0; c < m; ++c) tpos[c + 1] += tpos[c];
+    for (int64_t c = 0; c < m; ++c) next[c] = tpos[c];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = pos[i]; p < pos[i + 1]; ++p) {
+            int64_t q = next[crd[p]]++;
+            tcrd[q] = (int32_t)i;
+            tvals[q] = vals[p];
+        }
+    free(next);
+}
+
+/* ------------------------------------------------------------------------ */
+/* SpMV of a CSC matrix  y(i) = A(i,j) * x(j)  with A n x m stored by       */
+/* columns (cpos over the m columns, rows in crd): the plain definition,     */
+/* every stored entry's term added to its row.                               */
+/* ------------------------------------------------------------------------ */
+void orc_csc_spmv(int64_t n, int64_t m, const int32_t *cpos, const int32_t *crd,
+                  const double *vals, const double *x, double *y, double *S)
+{
+    ld *acc = (ld *)calloc((size_t)(n > 0 ? n : 1), sizeof(ld));
+    ld *mag = (ld *)calloc((size_t)(n > 0 ? n : 1), sizeof(ld));
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t p = cpos[j]; p < cpos[j + 1]; ++p) {
+            ld term = (ld)vals[p] * (ld)x[j];
+            acc[crd[p]] += term;
+            mag[crd[p]] += ld_abs(term);
+        }
+    for (int64_t i = 0; i < n; ++i) {
+        y[i] = (double)acc[i];
+        if (S) S[i] = (double)mag[i];
+    }
+    free(acc);
+    free(mag);
+}

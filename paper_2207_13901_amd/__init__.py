@@ -27,7 +27,7 @@ __all__ = [
     "timing_enable", "timing_read", "probe", "spttv", "mttkrp", "inner", "sddmm",
     "spadd3", "autotune", "mlp_load", "mlp_save", "mlp_predict", "mlp_train_step",
     "schedule_dict", "coord_partition", "spmv_window", "DDC", "csf_tile_bounds",
-    "spmv_noalloc", "tin", "tin_source",
+    "spmv_noalloc", "tin", "tin_source", "transpose", "CSC",
 ]
 
 _DT = {torch.float64: N.F64, torch.float32: N.F32, torch.bfloat16: N.BF16}
@@ -96,6 +96,10 @@ class CSF:
         s.vals = _ptr(self.vals)
         s.nnz = self.crd2.numel()
         s.nfibers = self.crd1.numel()
+        if self.pos2.dtype == torch.int64:
+            if self.pos1.dtype != torch.int64:
+                raise ValueError("int64 positions: pos1 and pos2 both int64")
+            s.pos_type = N.I64
         return s
 
     def with_vals(self, vals: torch.Tensor) -> "CSF":
@@ -127,6 +131,7 @@ class DDC:
         s.vals = _ptr(self.vals)
         s.nnz = self.crd2.numel()
         s.nfibers = self.shape[0] * self.shape[1]
+        s.pos_type = N.I64 if self.pos2.dtype == torch.int64 else N.I32
         return s
 
     def with_vals(self, vals: torch.Tensor) -> "DDC":
@@ -479,6 +484,47 @@ def spadd3(B: CSR, C: CSR, D: CSR, sched=None, ctx: Optional[Context] = None) ->
                                          _ptr(avals), _sched_ptr(sched), stream),
               "spl_spadd3_numeric")
     return CSR(apos, acrd, avals, B.shape)
+
+
+# ---------------------------------------------------------- transposition
+
+def transpose(B: CSR, ctx: Optional[Context] = None) -> CSR:
+    """The CSR of B^T (spl_transpose)."""
+    ctx, stream = _ctx_stream(B.vals, ctx)
+    dev = B.vals.device
+    n, m = B.shape
+    nnz = B.crd.numel()
+    s = B.struct()
+    nb = ctypes.c_size_t()
+    ctx.check(ctx.lib.spl_transpose_workspace_query(ctx.h, ctypes.byref(s), ctypes.byref(nb)),
+              "spl_transpose_workspace_query")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    tpos = torch.empty(m + 1, dtype=torch.int32, device=dev)
+    tcrd = torch.empty(nnz, dtype=torch.int32, device=dev)
+    tvals = torch.empty(nnz, dtype=B.vals.dtype, device=dev)
+    ctx.check(ctx.lib.spl_transpose(ctx.h, ctypes.byref(s), tpos.data_ptr(), _ptr(tcrd),
+                                    _ptr(tvals), ws.data_ptr(), nb.value, stream), "spl_transpose")
+    return CSR(tpos, tcrd, tvals, (m, n))
+
+
+@dataclass
+class CSC:
+    """CSC matrix n x m: pos int32[m+1] over columns, crd int32[nnz] row
+    coordinates (increasing within a column), vals[nnz] -- the
+    (Dense, Compressed) format over the dimension order (j, i), i.e. the CSR
+    arrays of the transpose."""
+    pos: torch.Tensor
+    crd: torch.Tensor
+    vals: torch.Tensor
+    shape: tuple
+
+    def as_transposed_csr(self) -> CSR:
+        """The same arrays read as the CSR of the m x n transpose."""
+        return CSR(self.pos, self.crd, self.vals, (self.shape[1], self.shape[0]))
+
+    def to_csr(self, ctx: Optional[Context] = None) -> CSR:
+        """This matrix in CSR, by the library's transposition."""
+        return transpose(self.as_transposed_csr(), ctx)
 
 
 # -------------------------------------------- general index-notation leaves

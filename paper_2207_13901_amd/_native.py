@@ -113,6 +113,8 @@ SIGNATURES = {
     "spl_mlp_save": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _SCH, _P, _P]),
     "spl_mlp_predict": (_I32, [_P, _I32, _SP, _SCH, _P]),
     "spl_mlp_train_step": (_I32, [_P, _I32, _P, _P, _I64, ctypes.c_float, _P, _P]),
+    "spl_transpose_workspace_query": (_I32, [_P, _SP, ctypes.POINTER(_SZ)]),
+    "spl_transpose": (_I32, [_P, _SP, _P, _P, _P, _P, _SZ, _P]),
     "spl_tin_workspace_query": (_I32, [_P, ctypes.c_char_p, ctypes.c_int,
                                        ctypes.POINTER(SplTinOperand),
                                        ctypes.POINTER(SplTinOperand), ctypes.POINTER(_SZ)]),

@@ -87,14 +87,15 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 bool valid_dtype(int dt) { return dt == SPL_F64 || dt == SPL_F32 || dt == SPL_BF16; }
 
-// allow_i64: the caller handles int64 positions (SpMV only).
+// allow_i64: the caller handles int64 positions (SpMV, SpMM, SpTTV, MTTKRP).
 spl_status check_sparse(spl_context *ctx, const spl_sparse *B, int order, bool allow_i64 = false) {
     if (!B) return fail(ctx, SPL_ERR_ARG, "sparse operand is NULL");
     if (B->pos_type != SPL_I32 && B->pos_type != SPL_I64)
         return fail(ctx, SPL_ERR_FORMAT, "unknown pos_type %d", B->pos_type);
     if (B->pos_type == SPL_I64 && !allow_i64)
         return fail(ctx, SPL_ERR_UNSUPPORTED,
-                    "int64 positions are accepted by SpMV (CSR, MERGE schedule) only");
+                    "int64 positions are accepted by SpMV, SpMM, SpTTV and MTTKRP (MERGE "
+                    "schedule) only");
     if (B->order != order)
         return fail(ctx, SPL_ERR_FORMAT, "expected an order-%d sparse operand, got order %d", order,
                     B->order);
@@ -389,7 +390,7 @@ size_t spmv_ws(const spl_sparse *B, const Plan &p) {
 size_t spmm_ws(const spl_sparse *B, int64_t N, const Plan &p) {
     if (p.kind == SPL_ROW) return 0;
     return tiled_ws(pieces_for(p, B->dims[0], B->nnz, spmm_chunk(p)), N,
-                    B->vtype == SPL_F64 ? 8 : 4);
+                    B->vtype == SPL_F64 ? 8 : 4, B->pos_type == SPL_I64 ? 8 : 4);
 }
 
 // SpTTV runs the SpMV leaf on the fiber level: a CSR view whose rows are the
@@ -883,7 +884,7 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
     switch (op) {
     case SPL_OP_SPMV:
     case SPL_OP_SPMM: {
-        SPL_CHECK(check_sparse(ctx, B, 2, op == SPL_OP_SPMV));
+        SPL_CHECK(check_sparse(ctx, B, 2, true));
         // a selection kind needs room for whichever candidate it picks
         std::vector<spl_schedule> one;
         const std::vector<spl_schedule> *list = &one;
@@ -903,14 +904,14 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
         return SPL_OK;
     }
     case SPL_OP_SPTTV: {
-        SPL_CHECK(check_sparse(ctx, B, 3));
+        SPL_CHECK(check_sparse(ctx, B, 3, true));
         const spl_sparse v = fiber_view(B);
         SPL_CHECK(resolve_spmv(ctx, &v, sched, p));
         *bytes = spmv_ws(&v, p);
         return SPL_OK;
     }
     case SPL_OP_MTTKRP:
-        SPL_CHECK(check_sparse(ctx, B, 3));
+        SPL_CHECK(check_sparse(ctx, B, 3, true));
         SPL_CHECK(resolve_mttkrp(ctx, ncols, sched, p));
         *bytes = dense_middle_ws(B) + mttkrp_ws(B, ncols, p);
         return SPL_OK;
@@ -1155,8 +1156,11 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
                     spl_stream stream) {
     SPL_GUARD_BEGIN
     if (!ctx) return SPL_ERR_ARG;
-    SPL_CHECK(check_sparse(ctx, B, 2));
+    SPL_CHECK(check_sparse(ctx, B, 2, true));
     if (!C) return fail(ctx, SPL_ERR_ARG, "dense operand C is NULL");
+    const bool pos64 = B->pos_type == SPL_I64;
+    if (pos64 && selection_kind(sched))
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "int64 positions: MERGE schedules only");
     const int64_t N = C->ndim == 2 ? C->dims[1] : -1;
     SPL_CHECK(check_dense(ctx, C, "C", 2, B->dims[1], -1));
     SPL_CHECK(check_dense(ctx, A, "A", 2, B->dims[0], N));
@@ -1174,6 +1178,8 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = B->dims[0];
     if (n == 0 || N == 0) return SPL_OK;
+    if (pos64 && p.kind != SPL_MERGE)
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "int64 positions: MERGE schedule only");
     if (p.kind == SPL_ROW) {
         LeafTimer tm(ctx, SPL_OP_SPMM, s);
         SPL_HIP(spl::launch_spmm_row(B->vtype, A->dtype, p.col_tile, n, N, B->pos[1], B->crd[1],
@@ -1184,10 +1190,29 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     }
     // the workspace query assumed one column per lane: the larger size
     p.vec = spmm_vec(p, B->vtype, C, A);
+    if (pos64 && p.vec != spl::spmm_vec_width(B->vtype))
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "int64 positions: 16-byte vector lanes only (variant 0; N, every ld and the "
+                    "dense pointers aligned to 16 bytes; items_per_lane 8 or 16)");
     void *ws = nullptr;
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmm_ws(B, N, p), &ws));
     const Pieces q = pieces_for(p, n, B->nnz, spmm_chunk(p));
-    Carved cv = carve(ws, q.count);
+    Carved cv = carve(ws, q.count, pos64);
+    if (pos64) {
+        const int64_t *pos = reinterpret_cast<const int64_t *>(B->pos[1]);
+        SPL_HIP(spl::launch_merge_bounds64(n, pos, B->nnz, q.size, cv.tiles, s),
+                "tile bounds launch");
+        LeafTimer tm(ctx, SPL_OP_SPMM, s);
+        SPL_HIP(spl::launch_spmm_tiles64(B->vtype, p.col_tile, p.items, p.vec, n, N, pos,
+                                         B->crd[1], B->vals, C->data, C->ld, A->data, A->ld,
+                                         cv.tiles, q.stride, cv.carry, s),
+                "SpMM tile launch");
+        tm.stop();
+        SPL_HIP(spl::launch_spmm_fixup(B->vtype, n, N, cv.tiles, q.stride, cv.carry, A->data,
+                                       A->ld, s),
+                "SpMM fix-up launch");
+        return SPL_OK;
+    }
     SPL_HIP(spl::launch_tile_bounds(p.kind, n, B->pos[1], B->nnz, q.size, cv.tiles, s),
             "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_SPMM, s);
@@ -1284,7 +1309,7 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
                      spl_stream stream) {
     SPL_GUARD_BEGIN
     if (!ctx) return SPL_ERR_ARG;
-    SPL_CHECK(check_sparse(ctx, B, 3));
+    SPL_CHECK(check_sparse(ctx, B, 3, true));
     SPL_CHECK(check_dense(ctx, c, "c", 1, B->dims[2], -1));
     SPL_CHECK(check_dense(ctx, A, "A", 1, B->nfibers, -1));
     if (B->vtype == SPL_BF16 || c->dtype != B->vtype || A->dtype != B->vtype)
@@ -1292,10 +1317,33 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c, 
     const spl_sparse v = fiber_view(B);
     Plan p;
     SPL_CHECK(resolve_spmv(ctx, &v, sched, p));
+    const bool pos64 = B->pos_type == SPL_I64;
+    if (pos64 && (p.kind != SPL_MERGE || p.variant != 0))
+        return fail(ctx, SPL_ERR_UNSUPPORTED, "int64 positions: MERGE schedule, variant 0 only");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t F = B->nfibers;
     if (F == 0) return SPL_OK;
+    if (pos64) {
+        // the fiber level's int64 positions: the SpMV flag leaf over fibers
+        void *ws = nullptr;
+        SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmv_ws(&v, p), &ws));
+        const Pieces q = pieces_for(p, F, B->nnz, spmv_chunk(p));
+        Carved cv = carve(ws, q.count, true);
+        const int64_t *pos = reinterpret_cast<const int64_t *>(v.pos[1]);
+        SPL_HIP(spl::launch_merge_bounds64(F, pos, B->nnz, q.size, cv.tiles, s),
+                "tile bounds launch");
+        LeafTimer tm(ctx, SPL_OP_SPTTV, s);
+        SPL_HIP(spl::launch_spmv_flag64(B->vtype, p.items, F, pos, v.crd[1], B->vals, c->data,
+                                        A->data, cv.tiles, q.stride,
+                                        static_cast<double *>(cv.carry), s),
+                "SpTTV tile launch");
+        tm.stop();
+        SPL_HIP(spl::launch_spmv_fixup(B->vtype, F, cv.tiles, q.stride,
+                                       static_cast<double *>(cv.carry), A->data, s),
+                "SpTTV fix-up launch");
+        return SPL_OK;
+    }
     if (p.kind == SPL_ROW) {
         LeafTimer tm(ctx, SPL_OP_SPTTV, s);
         SPL_HIP(spl::launch_spmv_row(B->vtype, p.lanes, F, v.pos[1], nullptr, v.crd[1], B->vals, c->data,
@@ -1328,8 +1376,12 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
                       void *workspace, size_t workspace_bytes, spl_stream stream) {
     SPL_GUARD_BEGIN
     if (!ctx) return SPL_ERR_ARG;
-    SPL_CHECK(check_sparse(ctx, B, 3));
+    SPL_CHECK(check_sparse(ctx, B, 3, true));
     if (!C || !D) return fail(ctx, SPL_ERR_ARG, "dense factor is NULL");
+    const bool pos64 = B->pos_type == SPL_I64;
+    if (pos64 && dense_middle(B))
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "int64 positions: MTTKRP takes a Compressed middle level (CSF)");
     const int64_t R = C->ndim == 2 ? C->dims[1] : -1;
     SPL_CHECK(check_dense(ctx, C, "C", 2, B->dims[1], -1));
     SPL_CHECK(check_dense(ctx, D, "D", 2, B->dims[2], R));
@@ -1350,6 +1402,10 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     if (I == 0 || R == 0) return SPL_OK;
     // the workspace query assumed one column per lane: the larger size
     p.vec = mttkrp_vec(p, C, D, A);
+    if (pos64 && (p.kind != SPL_MERGE || p.vec == 1))
+        return fail(ctx, SPL_ERR_UNSUPPORTED,
+                    "int64 positions: MERGE schedule with vector lanes only (variant 0 or 2, "
+                    "col_tile 32 or 64, items_per_lane 4 or 8, R and every ld multiples of 4)");
     if (p.items == 4 && p.vec == 1)
         return fail(ctx, SPL_ERR_ARG,
                     "MTTKRP items_per_lane 4 needs 4-column lanes (variant 0, col_tile 32 or 64, "
@@ -1363,6 +1419,24 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     B = &bv;
     const Pieces q = mttkrp_pieces(B, p);
     Carved cv = carve(wp, q.count);
+    if (pos64) {
+        // slice ends are fiber indices (below 2^31): int32 tile bounds
+        const int64_t *pos1 = reinterpret_cast<const int64_t *>(B->pos[1]);
+        const int64_t *pos2 = reinterpret_cast<const int64_t *>(B->pos[2]);
+        SPL_HIP(spl::launch_merge_bounds64_32(I, pos1, B->nfibers, q.size, cv.tiles, s),
+                "tile bounds launch");
+        LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
+        SPL_HIP(spl::launch_mttkrp_tiles64(B->vtype, p.col_tile, p.items, p.vec, I, R, pos1,
+                                           B->crd[1], pos2, B->crd[2], B->vals, C->data, C->ld,
+                                           D->data, D->ld, static_cast<float *>(A->data), A->ld,
+                                           cv.tiles, q.stride, static_cast<float *>(cv.carry), s),
+                "MTTKRP tile launch");
+        tm.stop();
+        SPL_HIP(spl::launch_mttkrp_fixup(I, R, cv.tiles, q.stride, static_cast<float *>(cv.carry),
+                                         static_cast<float *>(A->data), A->ld, s),
+                "MTTKRP fix-up launch");
+        return SPL_OK;
+    }
     if (p.kind == SPL_NNZ)
         SPL_HIP(spl::launch_csf_nnz_bounds(I, B->pos[1], B->nfibers, B->pos[2], B->nnz, p.tile,
                                            cv.tiles, s),
@@ -1502,6 +1576,10 @@ spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
 }
 
 namespace {
+// The numeric phase's default input staging (0 direct, 1 coordinates, 2
+// coordinates and values).
+constexpr int kSpadd3DefaultStage = 0;
+
 spl_status check_spadd3(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                         const spl_sparse *D, const spl_schedule *sched) {
     SPL_CHECK(check_sparse(ctx, B, 2));
@@ -1563,14 +1641,49 @@ spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_s
     const int64_t n = B->dims[0];
     if (n > 0 && (B->nnz + C->nnz + D->nnz > 0) && (!A_crd || !A_vals))
         return fail(ctx, SPL_ERR_ARG, "NULL output arrays");
+    // sched->variant: 0 library default, 1 inputs read directly, 2 the
+    // coordinate runs staged in LDS, 3 coordinates and values staged
+    const int variant = sched ? sched->variant : 0;
+    if (variant < 0 || variant > 3)
+        return fail(ctx, SPL_ERR_ARG, "SpAdd3 variant must be 0..3");
+    const int stage = variant == 0 ? kSpadd3DefaultStage : variant - 1;
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     LeafTimer tm(ctx, SPL_OP_SPADD3, s);
     SPL_HIP(spl::launch_spadd3_numeric(B->vtype, n, B->pos[1], B->crd[1], B->vals, C->pos[1],
                                        C->crd[1], C->vals, D->pos[1], D->crd[1], D->vals, A_pos,
-                                       A_crd, A_vals, s),
+                                       A_crd, A_vals, stage, s),
             "SpAdd3 numeric launch");
     tm.stop();
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_transpose_workspace_query(spl_context *ctx, const spl_sparse *B, size_t *bytes) {
+    SPL_GUARD_BEGIN
+    if (!ctx || !bytes) return fail(ctx, SPL_ERR_ARG, "NULL argument");
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    *bytes = spl::transpose_ws_bytes(B->nnz, B->dims[1]);
+    return SPL_OK;
+    SPL_GUARD_END
+}
+
+spl_status spl_transpose(spl_context *ctx, const spl_sparse *B, int32_t *T_pos, int32_t *T_crd,
+                         void *T_vals, void *workspace, size_t workspace_bytes,
+                         spl_stream stream) {
+    SPL_GUARD_BEGIN
+    if (!ctx) return SPL_ERR_ARG;
+    SPL_CHECK(check_sparse(ctx, B, 2));
+    if (!T_pos || (B->nnz > 0 && (!T_crd || !T_vals)))
+        return fail(ctx, SPL_ERR_ARG, "NULL output array");
+    SPL_CHECK(set_device(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes,
+                            spl::transpose_ws_bytes(B->nnz, B->dims[1]), &ws));
+    SPL_HIP(spl::launch_transpose(B->vtype, B->dims[0], B->dims[1], B->nnz, B->pos[1], B->crd[1],
+                                  B->vals, T_pos, T_crd, T_vals, ws, s),
+            "transpose launch");
     return SPL_OK;
     SPL_GUARD_END
 }

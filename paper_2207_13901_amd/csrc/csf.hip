@@ -217,10 +217,22 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
 // loads.  ITEMS 4 halves the C-row slab and the per-group registers (116
 // VGPRs and 28 KB of LDS against 161 and 45 KB): 4 waves per SIMD instead of
 // 3, more gathers in flight (4.93 -> 4.56 ms FP32, 6.40 -> 5.32 ms BF16).
-template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc>
+//
+// int64 positions (PosT): pos1's entries are fiber indices (below 2^31) and
+// are staged as they are; pos2's are staged relative to the chunk's first
+// position (the low 32 bits of the difference), and the global loads add
+// that base back.  With int32 positions the base is 0.
+template <typename PosT>
+__device__ __forceinline__ int32_t rel_pos(PosT p, int64_t base) {
+    if constexpr (sizeof(PosT) == 4) return p;
+    return static_cast<int32_t>(static_cast<uint32_t>(p) - static_cast<uint32_t>(base));
+}
+
+template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc,
+          typename PosT = int32_t>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
-    int64_t I, int64_t R, const int32_t *__restrict__ pos1, const int32_t *__restrict__ crd1,
-    const int32_t *__restrict__ pos2, const int32_t *__restrict__ crd2,
+    int64_t I, int64_t R, const PosT *__restrict__ pos1, const int32_t *__restrict__ crd1,
+    const PosT *__restrict__ pos2, const int32_t *__restrict__ crd2,
     const V *__restrict__ vals, const FT *__restrict__ C, int64_t ldc,
     const FT *__restrict__ D, int64_t ldd, float *__restrict__ A, int64_t lda,
     const int32_t *__restrict__ tslice, const int32_t *__restrict__ tfib, int64_t npieces,
@@ -272,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     int32_t pre_k[2] = {0, 0};
     V pre_v[2] = {};
     int64_t pre_np = 0;
+    int64_t pre_base = 0;  // the next chunk's first position (int64 positions)
     bool have = false;
 
     while (piece < piece_end) {
@@ -286,7 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         }
         piece = next;
         const int nr = static_cast<int>(ei - ci), nf = static_cast<int>(ef - cf);
+        // the base the chunk's staged fiber starts count from (0 for int32)
+        int64_t pbase = 0;
         if (have) {
+            if constexpr (sizeof(PosT) == 8) pbase = pre_base;
             if (tid < nr) s_end[tid] = pre_e;
             if (tid < nf) s_j[tid] = pre_j;
             if (tid <= nf) s_fp[tid] = pre_f;
@@ -303,9 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
                 }
             }
         } else {
-            for (int k = tid; k < nr; k += kBlock) s_end[k] = pos1[ci + 1 + k];
+            if constexpr (sizeof(PosT) == 8) pbase = pos2[cf];
+            for (int k = tid; k < nr; k += kBlock) s_end[k] = static_cast<int32_t>(pos1[ci + 1 + k]);
             for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
-            for (int k = tid; k <= nf; k += kBlock) s_fp[k] = pos2[cf + k];
+            for (int k = tid; k <= nf; k += kBlock) s_fp[k] = rel_pos(pos2[cf + k], pbase);
             if constexpr (kStage) {
                 const int64_t p0 = pos2[cf], npb = pos2[ef] - p0;
                 for (int k = tid; k < npb && k < kStagePos; k += kBlock) {
@@ -323,8 +340,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
         const int a0 = static_cast<int>(merge_search(d0, nr, nf, cf, end_at));
         const int a1 = static_cast<int>(merge_search(d1, nr, nf, cf, end_at));
         const int b0 = d0 - a0, b1 = d1 - a1;
-        const int64_t P0 = s_fp[b0];
+        const int64_t P0 = s_fp[b0];  // relative to pbase
         const int np = static_cast<int>(s_fp[b1] - P0);
+        const int32_t *__restrict__ kcrd = crd2 + pbase;
+        const V *__restrict__ kval = vals + pbase;
 
         // every C-row and D-row gather of the group before any is used
         // (BF16 rows stay packed until they are read)
@@ -347,8 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
                     kq[q] = s_kq[rel0 + q];
                     vq[q] = s_vq[rel0 + q];
                 } else {
-                    kq[q] = load_stream(crd2 + P0 + q);
-                    vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+                    kq[q] = load_stream(kcrd + P0 + q);
+                    vq[q] = widen<Acc>(load_stream(kval + P0 + q));
                 }
             }
         }
@@ -365,11 +384,12 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             const int64_t nei = tslice[piece + 1], nef = tfib[piece + 1];
             if (nei + nef - ei - ef <= kChunk) {
                 const int nnr = static_cast<int>(nei - ei), nnf = static_cast<int>(nef - ef);
-                if (tid < nnr) pre_e = pos1[ei + 1 + tid];
+                if constexpr (sizeof(PosT) == 8) pre_base = pos2[ef];
+                if (tid < nnr) pre_e = static_cast<int32_t>(pos1[ei + 1 + tid]);
                 if (tid < nnf) pre_j = crd1[ef + tid];
-                if (tid <= nnf) pre_f = pos2[ef + tid];
+                if (tid <= nnf) pre_f = rel_pos(pos2[ef + tid], pre_base);
                 if constexpr (kChunk >= kBlock)
-                    if (tid == 0 && nnf == kBlock) pre_f2 = pos2[ef + kBlock];
+                    if (tid == 0 && nnf == kBlock) pre_f2 = rel_pos(pos2[ef + kBlock], pre_base);
                 if constexpr (kStage) {
                     const int64_t pp0 = pos2[ef];
                     pre_np = pos2[nef] - pp0;
@@ -426,10 +446,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             while (P0 + q >= s_fp[f + 1]) close_fiber();
             if (colok) {
                 const bool staged = kStage && rel0 + q < kStagePos;
-                const int32_t kk = staged ? s_kq[rel0 + q] : load_stream(crd2 + P0 + q);
+                const int32_t kk = staged ? s_kq[rel0 + q] : load_stream(kcrd + P0 + q);
                 RowVec<VEC, FT> d;
                 d.load(D + static_cast<int64_t>(kk) * ldd + col0);
-                const Acc vv = staged ? s_vq[rel0 + q] : widen<Acc>(load_stream(vals + P0 + q));
+                const Acc vv = staged ? s_vq[rel0 + q] : widen<Acc>(load_stream(kval + P0 + q));
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) t[v] += vv * static_cast<Acc>(d.at(v));
             }
@@ -537,9 +557,9 @@ __global__ __launch_bounds__(kBlock) void k_inner_final(int64_t nparts,
     if (threadIdx.x == 0) *out = s[0];
 }
 
-template <typename V, typename FT>
+template <typename V, typename FT, typename PosT = int32_t>
 hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
-                        const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
+                        const PosT *pos1, const int32_t *crd1, const PosT *pos2,
                         const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
                         const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
                         int64_t stride, float *carry, hipStream_t s) {
@@ -555,24 +575,30 @@ hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
     if (vec == kMttkrpVec) {
         if (items != 8 && items != 4) return hipErrorInvalidValue;
         if (items == 4) {
-            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float>);
-            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float>);
+            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT>);
+            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float, PosT>);
             return hipErrorInvalidValue;
         }
-        if (lanes == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVec, V, FT, float>);
-        if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float>);
+        if (lanes == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVec, V, FT, float, PosT>);
+        if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float, PosT>);
         return hipErrorInvalidValue;
     }
     if constexpr (sizeof(FT) == 2) {
         // 16-byte BF16 lanes: chunks of at most 256 merged items (lanes x
         // items >= 32), as the one-item-per-thread staging needs
         if (vec == kMttkrpVecWide) {
-            if (lanes == 4 && items == 4) return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float>);
-            if (lanes == 8 && items == 4) return go(k_mttkrp_vec<8, 4, kMttkrpVecWide, V, FT, float>);
-            if (lanes == 8 && items == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVecWide, V, FT, float>);
+            if (lanes == 4 && items == 4)
+                return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float, PosT>);
+            if (lanes == 8 && items == 4)
+                return go(k_mttkrp_vec<8, 4, kMttkrpVecWide, V, FT, float, PosT>);
+            if (lanes == 8 && items == 8)
+                return go(k_mttkrp_vec<8, 8, kMttkrpVecWide, V, FT, float, PosT>);
             return hipErrorInvalidValue;
         }
     }
+    if constexpr (sizeof(PosT) == 8) {
+        return hipErrorInvalidValue;  // int64 positions: vector lanes only
+    } else {
     if (vec > 1) return hipErrorInvalidValue;
     if (col_tile == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
                                           : go(k_mttkrp_tiles<16, 16, V, FT, float>);
@@ -580,6 +606,7 @@ hipError_t mttkrp_types(int col_tile, int items, int vec, int64_t I, int64_t R,
                                           : go(k_mttkrp_tiles<64, 16, V, FT, float>);
     return items <= 8 ? go(k_mttkrp_tiles<32, 8, V, FT, float>)
                       : go(k_mttkrp_tiles<32, 16, V, FT, float>);
+    }
 }
 
 }  // namespace
@@ -601,6 +628,20 @@ hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int vec, int6
                                           C, ldc, D, ldd, A, lda, t, stride, carry, s);
     return mttkrp_types<bf16, bf16>(col_tile, items, vec, I, R, pos1, crd1, pos2, crd2, vals, C,
                                     ldc, D, ldd, A, lda, t, stride, carry, s);
+}
+
+hipError_t launch_mttkrp_tiles64(int vtype, int col_tile, int items, int vec, int64_t I,
+                                 int64_t R, const int64_t *pos1, const int32_t *crd1,
+                                 const int64_t *pos2, const int32_t *crd2, const void *vals,
+                                 const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
+                                 int64_t lda, const Tiles &t, int64_t stride, float *carry,
+                                 hipStream_t s) {
+    if (vtype == SPL_F32)
+        return mttkrp_types<float, float, int64_t>(col_tile, items, vec, I, R, pos1, crd1, pos2,
+                                                   crd2, vals, C, ldc, D, ldd, A, lda, t, stride,
+                                                   carry, s);
+    return mttkrp_types<bf16, bf16, int64_t>(col_tile, items, vec, I, R, pos1, crd1, pos2, crd2,
+                                             vals, C, ldc, D, ldd, A, lda, t, stride, carry, s);
 }
 
 hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t stride,

@@ -212,7 +212,8 @@ __host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { ret
 // with a binary search over pos.  Writes (ei, ep) to s_next and returns the
 // piece the walk is in afterwards.  Contains a workgroup barrier; every
 // thread must call it.
-__device__ __forceinline__ int64_t chunk_end(const int32_t *__restrict__ pos,
+template <typename P>
+__device__ __forceinline__ int64_t chunk_end(const P *__restrict__ pos,
                                              const int32_t *__restrict__ trow,
                                              const int32_t *__restrict__ tpos, int64_t piece,
                                              int64_t ci, int64_t cp, int chunk,
@@ -225,7 +226,7 @@ __device__ __forceinline__ int64_t chunk_end(const int32_t *__restrict__ pos,
             s_next[1] = bp;
         } else {
             const int64_t k = merge_search(chunk, bi - ci, bp - cp, cp,
-                                           [&](int64_t m) { return pos[ci + m + 1]; });
+                                           [&](int64_t m) { return static_cast<int64_t>(pos[ci + m + 1]); });
             s_next[0] = ci + k;
             s_next[1] = cp + chunk - k;
         }

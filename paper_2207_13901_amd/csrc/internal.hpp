@@ -26,6 +26,10 @@ int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size);
 // Merge split of a CSR with int64 positions: t.row and t.pos64.
 hipError_t launch_merge_bounds64(int64_t rows, const int64_t *pos, int64_t nnz, int64_t size,
                                  const Tiles &t, hipStream_t s);
+// Merge split of a level with int64 pos whose child count is below 2^31 (a
+// CSF slice level over fibers): tile positions in t.pos (int32).
+hipError_t launch_merge_bounds64_32(int64_t rows, const int64_t *pos, int64_t nnz, int64_t size,
+                                    const Tiles &t, hipStream_t s);
 hipError_t launch_tile_bounds(int kind, int64_t rows, const int32_t *pos, int64_t nnz,
                               int64_t size, const Tiles &t, hipStream_t s);
 
@@ -74,6 +78,12 @@ hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_
                              const int32_t *pos, const int32_t *crd, const void *vals,
                              const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
                              int64_t stride, bool exact_chunks, void *carry, hipStream_t s);
+// The same over a CSR with int64 positions: merge split and vector lanes
+// only (vec == spmm_vec_width(vtype); tile positions in t.pos64).
+hipError_t launch_spmm_tiles64(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
+                               const int64_t *pos, const int32_t *crd, const void *vals,
+                               const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
+                               int64_t stride, void *carry, hipStream_t s);
 hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, int64_t stride,
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 
@@ -96,6 +106,14 @@ hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int vec, int6
                                const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
                                const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
                                int64_t stride, float *carry, hipStream_t s);
+// The vector-lane MTTKRP leaf over a CSF with int64 pos1/pos2 (fiber count
+// below 2^31; merge split over slices and fibers, tiles in t.row / t.pos).
+hipError_t launch_mttkrp_tiles64(int vtype, int col_tile, int items, int vec, int64_t I,
+                                 int64_t R, const int64_t *pos1, const int32_t *crd1,
+                                 const int64_t *pos2, const int32_t *crd2, const void *vals,
+                                 const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
+                                 int64_t lda, const Tiles &t, int64_t stride, float *carry,
+                                 hipStream_t s);
 hipError_t launch_mttkrp_fixup(int64_t I, int64_t R, const Tiles &t, int64_t stride,
                                const float *carry, float *A, int64_t lda, hipStream_t s);
 hipError_t launch_inner(int vtype, int64_t nnz, const void *a, const void *b, double *part,
@@ -145,7 +163,7 @@ hipError_t launch_spadd3_numeric(int vtype, int64_t n, const int32_t *bp, const 
                                  const void *bv, const int32_t *cp, const int32_t *cc,
                                  const void *cv, const int32_t *dp, const int32_t *dc,
                                  const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
-                                 hipStream_t s);
+                                 int stage, hipStream_t s);
 
 // ---- mlp.hip -------------------------------------------------------------
 int64_t mlp_param_count(int K);
@@ -169,6 +187,16 @@ hipError_t launch_probe(int kind, const void *buf, int64_t bytes, int64_t row_by
 hipError_t launch_validate_level(int64_t parents, const int32_t *pos, const int32_t *crd,
                                  int64_t children, int64_t extent, int64_t *flags,
                                  hipStream_t s);
+
+// ---- transpose.hip -------------------------------------------------------
+// Radix passes for column indices below m (8 bits each).
+int transpose_passes(int64_t m);
+// Workspace of launch_transpose for nnz entries and m columns.
+size_t transpose_ws_bytes(int64_t nnz, int64_t m);
+// CSR arrays of B^T (m + 1 pos, nnz crd and vals) from B's (n x m).
+hipError_t launch_transpose(int vtype, int64_t n, int64_t m, int64_t nnz, const int32_t *pos,
+                            const int32_t *crd, const void *vals, int32_t *tpos, int32_t *tcrd,
+                            void *tvals, void *ws, hipStream_t s);
 
 // ---- scratch.hip ---------------------------------------------------------
 // Bytes of the static device scratch behind spl_spmv_noalloc.

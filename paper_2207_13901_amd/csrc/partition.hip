@@ -226,4 +226,9 @@ hipError_t launch_merge_bounds64(int64_t rows, const int64_t *pos, int64_t nnz, 
     return merge_bounds(rows, pos, nnz, size, t.ntiles, t.row, t.pos64, s);
 }
 
+hipError_t launch_merge_bounds64_32(int64_t rows, const int64_t *pos, int64_t nnz, int64_t size,
+                                    const Tiles &t, hipStream_t s) {
+    return merge_bounds(rows, pos, nnz, size, t.ntiles, t.row, t.pos, s);
+}
+
 }  // namespace spl

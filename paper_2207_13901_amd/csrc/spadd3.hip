@@ -37,6 +37,13 @@ struct Crd3 {
     int32_t ob, oc, od;
 };
 
+// Where a workgroup reads the three operands' values from (as Crd3).
+template <typename V>
+struct Vals3 {
+    const V *b, *c, *d;
+    int32_t ob, oc, od;
+};
+
 // Three-way merge of one row's sorted coordinate lists, resumable: next()
 // yields the union's coordinates in increasing order; with values, the sum
 // over the operands present in operand order B, C, D.
@@ -58,24 +65,24 @@ struct Merge3 {
 
     __device__ __forceinline__ bool done() const { return min(xa, min(xb, xd)) == kInf; }
 
-    // Advance past the smallest remaining coordinate c; returns c.
+    // Advance past the smallest remaining coordinate c; returns c.  Values
+    // of operand X at position q are read at vals.X[q - vals.oX].
     template <bool kValues, typename V>
-    __device__ __forceinline__ int32_t next(const Crd3 &x, const V *bv, const V *cv, const V *dv,
-                                            V &sum) {
+    __device__ __forceinline__ int32_t next(const Crd3 &x, const Vals3<V> &v, V &sum) {
         const int32_t c = min(xa, min(xb, xd));
         V s = 0;
         if (xa == c) {
-            if (kValues) s = bv[a];
+            if (kValues) s = v.b[a - v.ob];
             ++a;
             xa = a < ae ? x.b[a - x.ob] : kInf;
         }
         if (xb == c) {
-            if (kValues) s = s + cv[b];
+            if (kValues) s = s + v.c[b - v.oc];
             ++b;
             xb = b < be ? x.c[b - x.oc] : kInf;
         }
         if (xd == c) {
-            if (kValues) s = s + dv[d];
+            if (kValues) s = s + v.d[d - v.od];
             ++d;
             xd = d < de ? x.d[d - x.od] : kInf;
         }
@@ -114,8 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
     Merge3 mg(m, x, i);
     int32_t k = 0;
     float unused;
+    const Vals3<float> none{nullptr, nullptr, nullptr, 0, 0, 0};
     while (!mg.done()) {
-        mg.next<false, float>(x, nullptr, nullptr, nullptr, unused);
+        mg.next<false, float>(x, none, unused);
         ++k;
     }
     apos[i + 1] = k;
@@ -132,28 +140,53 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
 // than the repeated line fetches it saves.
 constexpr int kFillCap = 2048;
 
-template <typename V>
+// STAGE 0: inputs read directly; 1: the workgroup's coordinate runs staged
+// in LDS (as the count phase does); 2: coordinates and values staged, with a
+// smaller output window.  Runs longer than kStageCap fall back to direct
+// reads for the whole workgroup.
+template <typename V, int STAGE>
 __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const V *bv,
                                                         const V *cv, const V *dv,
                                                         const int32_t *apos, int32_t *acrd,
                                                         V *aval) {
-    __shared__ int32_t s_crd[kFillCap];
-    __shared__ V s_val[kFillCap];
+    constexpr int kWin = STAGE == 2 ? 1024 : kFillCap;
+    __shared__ int32_t s_crd[kWin];
+    __shared__ V s_val[kWin];
+    __shared__ int32_t s_x[STAGE ? 3 : 1][STAGE ? kStageCap : 1];
+    __shared__ V s_v[STAGE == 2 ? 3 : 1][STAGE == 2 ? kStageCap : 1];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
     const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
     const int64_t i = r0 + threadIdx.x;
-    const Crd3 x{m.bc, m.cc, m.dc, 0, 0, 0};
+    Crd3 x{m.bc, m.cc, m.dc, 0, 0, 0};
+    Vals3<V> vv{bv, cv, dv, 0, 0, 0};
+    if constexpr (STAGE > 0) {
+        const int32_t b0 = m.bp[r0], c0 = m.cp[r0], d0 = m.dp[r0];
+        const int32_t nb = m.bp[r1] - b0, nc = m.cp[r1] - c0, nd = m.dp[r1] - d0;
+        if (nb <= kStageCap && nc <= kStageCap && nd <= kStageCap) {
+            for (int k = threadIdx.x; k < nb; k += kBlock) s_x[0][k] = m.bc[b0 + k];
+            for (int k = threadIdx.x; k < nc; k += kBlock) s_x[1][k] = m.cc[c0 + k];
+            for (int k = threadIdx.x; k < nd; k += kBlock) s_x[2][k] = m.dc[d0 + k];
+            x = Crd3{s_x[0], s_x[1], s_x[2], b0, c0, d0};
+            if constexpr (STAGE == 2) {
+                for (int k = threadIdx.x; k < nb; k += kBlock) s_v[0][k] = bv[b0 + k];
+                for (int k = threadIdx.x; k < nc; k += kBlock) s_v[1][k] = cv[c0 + k];
+                for (int k = threadIdx.x; k < nd; k += kBlock) s_v[2][k] = dv[d0 + k];
+                vv = Vals3<V>{s_v[0], s_v[1], s_v[2], b0, c0, d0};
+            }
+            __syncthreads();
+        }
+    }
     const int64_t base = apos[r0];
     const int64_t total = apos[r1] - base;
     const bool mine = i < n;
     int64_t k = mine ? apos[i] - base : 0;
     const int64_t hi = mine ? apos[i + 1] - base : 0;
     Merge3 mg(m, x, mine ? i : r0);
-    for (int64_t w = 0; w < total; w += kFillCap) {
-        const int64_t we = w + kFillCap < total ? w + kFillCap : total;
+    for (int64_t w = 0; w < total; w += kWin) {
+        const int64_t we = w + kWin < total ? w + kWin : total;
         for (; k < hi && k < we; ++k) {
             V sum;
-            const int32_t c = mg.next<true, V>(x, bv, cv, dv, sum);
+            const int32_t c = mg.next<true, V>(x, vv, sum);
             s_crd[k - w] = c;
             s_val[k - w] = sum;
         }
@@ -325,23 +358,30 @@ hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *b
     return hipGetLastError();
 }
 
+template <typename V>
+hipError_t spadd3_fill(int stage, int64_t n, const Csr3 &m, const void *bv, const void *cv,
+                       const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
+                       hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(ceil_div(n, kBlock)));
+    auto go = [&](auto kern) {
+        kern<<<grid, kBlock, 0, s>>>(n, m, static_cast<const V *>(bv), static_cast<const V *>(cv),
+                                     static_cast<const V *>(dv), apos, acrd, static_cast<V *>(aval));
+        return hipGetLastError();
+    };
+    if (stage == 1) return go(k_spadd3_fill<V, 1>);
+    if (stage == 2) return go(k_spadd3_fill<V, 2>);
+    return go(k_spadd3_fill<V, 0>);
+}
+
 hipError_t launch_spadd3_numeric(int vtype, int64_t n, const int32_t *bp, const int32_t *bc,
                                  const void *bv, const int32_t *cp, const int32_t *cc,
                                  const void *cv, const int32_t *dp, const int32_t *dc,
                                  const void *dv, const int32_t *apos, int32_t *acrd, void *aval,
-                                 hipStream_t s) {
+                                 int stage, hipStream_t s) {
     Csr3 m{bp, bc, cp, cc, dp, dc};
     if (n == 0) return hipSuccess;
-    dim3 grid(static_cast<unsigned>(ceil_div(n, kBlock)));
-    if (vtype == SPL_F64)
-        k_spadd3_fill<double><<<grid, kBlock, 0, s>>>(
-            n, m, static_cast<const double *>(bv), static_cast<const double *>(cv),
-            static_cast<const double *>(dv), apos, acrd, static_cast<double *>(aval));
-    else
-        k_spadd3_fill<float><<<grid, kBlock, 0, s>>>(
-            n, m, static_cast<const float *>(bv), static_cast<const float *>(cv),
-            static_cast<const float *>(dv), apos, acrd, static_cast<float *>(aval));
-    return hipGetLastError();
+    if (vtype == SPL_F64) return spadd3_fill<double>(stage, n, m, bv, cv, dv, apos, acrd, aval, s);
+    return spadd3_fill<float>(stage, n, m, bv, cv, dv, apos, acrd, aval, s);
 }
 
 }  // namespace spl

@@ -187,11 +187,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
 // one iteration earlier still.  After the walk they are stored to the other
 // LDS buffer, so the loads of the next chunk never sit on the critical path.
 // The walk, the cross-group pass and the carries are those of k_spmm_tiles.
-template <int W, int ITEMS, int VEC, typename V, typename BT, typename OT, typename Acc>
+// With int64 positions (PosT) the row ends are staged relative to the
+// chunk's first position (they lie in [0, chunk]), so the walk and the
+// searches stay 32-bit; int32 positions are staged as they are.
+template <int W, int ITEMS, int VEC, typename V, typename BT, typename OT, typename Acc,
+          typename PosT = int32_t>
 __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
-    int64_t n, int64_t N, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    int64_t n, int64_t N, const PosT *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
-    int64_t ldo, const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos,
+    int64_t ldo, const int32_t *__restrict__ trow, const PosT *__restrict__ tpos,
     int64_t npieces, int64_t stride, Acc *__restrict__ carry) {
     constexpr int G = kBlock / W;
     constexpr int kChunk = G * ITEMS;
@@ -230,7 +234,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int k = tid + j * kBlock;
-            if (k < nr) r_end[j] = pos[fi + 1 + k];
+            if (k < nr) {
+                if constexpr (sizeof(PosT) == 4)
+                    r_end[j] = pos[fi + 1 + k];
+                else  // the difference fits 32 bits: subtract the low words
+                    r_end[j] = static_cast<int>(static_cast<uint32_t>(pos[fi + 1 + k]) -
+                                                static_cast<uint32_t>(fp));
+            }
             if (k < np) {
                 r_crd[j] = load_stream(crd + fp + k);
                 r_val[j] = widen<Acc>(load_stream(vals + fp + k));
@@ -270,8 +280,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         const int d1 = min(d0 + ITEMS, total);
         const int32_t *send = s_end[buf];
         auto end_at = [&](int64_t m) { return send[m]; };
-        const int a0 = static_cast<int>(merge_search(d0, nr, np, cp, end_at));
-        const int a1 = static_cast<int>(merge_search(d1, nr, np, cp, end_at));
+        const int64_t ebase = sizeof(PosT) == 4 ? cp : 0;  // what the staged ends count from
+        const int a0 = static_cast<int>(merge_search(d0, nr, np, ebase, end_at));
+        const int a1 = static_cast<int>(merge_search(d1, nr, np, ebase, end_at));
         const int b0 = d0 - a0, b1 = d1 - a1;
         // every gather of the group's positions is issued before any is used
         // (BF16 rows stay packed until they are read)
@@ -301,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             if (b0 + k < b1) {
-                while (a < a1 && send[a] <= cp + b0 + k) finish(a++);
+                while (a < a1 && send[a] <= ebase + b0 + k) finish(a++);
                 const Acc sv = s_val[buf][b0 + k];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) acc[v] += sv * static_cast<Acc>(pv[k].at(v));
@@ -397,20 +408,30 @@ struct SpmmTypes {
         }
     }
 
-    template <int W, int ITEMS, int VEC>
-    static hipError_t tiles_w(int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
+    template <int W, int ITEMS, int VEC, typename PosT>
+    static hipError_t tiles_w(int64_t n, int64_t N, const PosT *pos, const int32_t *crd,
                               const void *vals, const void *Bd, int64_t ldb, void *Out,
                               int64_t ldo, const Tiles &t, int64_t stride, bool exact,
                               void *carry, hipStream_t s) {
         const int64_t tiles = ceil_div(t.ntiles, stride);
         dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(ceil_div(N, W * VEC)));
         if (grid.y == 0) return hipSuccess;
-        // pieces of exactly one chunk (merge split): the pipelined leaf
-        auto kern = exact ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc>
-                          : k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>;
-        kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
-                                     static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out), ldo,
-                                     t.row, t.pos, t.ntiles, stride, static_cast<Acc *>(carry));
+        if constexpr (sizeof(PosT) == 8) {
+            // int64 positions: merge pieces only (tile positions in t.pos64)
+            if (!exact) return hipErrorInvalidValue;
+            k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int64_t><<<grid, kBlock, 0, s>>>(
+                n, N, pos, crd, static_cast<const V *>(vals), static_cast<const BT *>(Bd), ldb,
+                static_cast<OT *>(Out), ldo, t.row, t.pos64, t.ntiles, stride,
+                static_cast<Acc *>(carry));
+        } else {
+            // pieces of exactly one chunk (merge split): the pipelined leaf
+            auto kern = exact ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc>
+                              : k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>;
+            kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
+                                         static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out),
+                                         ldo, t.row, t.pos, t.ntiles, stride,
+                                         static_cast<Acc *>(carry));
+        }
         return hipGetLastError();
     }
 
@@ -423,27 +444,37 @@ struct SpmmTypes {
     }
 
     // vector lanes of VEC columns each: col_tile / VEC lanes per group
-    template <int VEC>
+    template <int VEC, typename PosT>
     static hipError_t tiles_vec(int col_tile, int items, int64_t n, int64_t N,
-                                const int32_t *pos, const int32_t *crd, const void *vals,
+                                const PosT *pos, const int32_t *crd, const void *vals,
                                 const void *Bd, int64_t ldb, void *Out, int64_t ldo,
                                 const Tiles &t, int64_t stride, bool exact, void *carry,
                                 hipStream_t s) {
         switch (col_tile / VEC) {
-        case 4: return items <= 8 ? tiles_w<4, 8, VEC>(SPL_SPMM_ARGS)
-                                  : tiles_w<4, 16, VEC>(SPL_SPMM_ARGS);
-        case 8: return items <= 8 ? tiles_w<8, 8, VEC>(SPL_SPMM_ARGS)
-                                  : tiles_w<8, 16, VEC>(SPL_SPMM_ARGS);
-        case 16: return items <= 8 ? tiles_w<16, 8, VEC>(SPL_SPMM_ARGS)
-                                   : tiles_w<16, 16, VEC>(SPL_SPMM_ARGS);
-        case 32: return items <= 8 ? tiles_w<32, 8, VEC>(SPL_SPMM_ARGS)
-                                   : tiles_w<32, 16, VEC>(SPL_SPMM_ARGS);
+        case 4: return items <= 8 ? tiles_w<4, 8, VEC, PosT>(SPL_SPMM_ARGS)
+                                  : tiles_w<4, 16, VEC, PosT>(SPL_SPMM_ARGS);
+        case 8: return items <= 8 ? tiles_w<8, 8, VEC, PosT>(SPL_SPMM_ARGS)
+                                  : tiles_w<8, 16, VEC, PosT>(SPL_SPMM_ARGS);
+        case 16: return items <= 8 ? tiles_w<16, 8, VEC, PosT>(SPL_SPMM_ARGS)
+                                   : tiles_w<16, 16, VEC, PosT>(SPL_SPMM_ARGS);
+        case 32: return items <= 8 ? tiles_w<32, 8, VEC, PosT>(SPL_SPMM_ARGS)
+                                   : tiles_w<32, 16, VEC, PosT>(SPL_SPMM_ARGS);
         default: return hipErrorInvalidValue;
         }
     }
 
     // col_tile columns per lane group; vec > 1 (merge split only): vec
     // columns per lane, so col_tile / vec lanes per group
+    // int64 positions: vector lanes and the merge split only
+    static hipError_t tiles64(int col_tile, int items, int vec, int64_t n, int64_t N,
+                              const int64_t *pos, const int32_t *crd, const void *vals,
+                              const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
+                              int64_t stride, bool exact, void *carry, hipStream_t s) {
+        if (vec != kSpmmVec<BT> || !exact || (items != 8 && items != 16))
+            return hipErrorInvalidValue;
+        return tiles_vec<kSpmmVec<BT>>(col_tile, items, SPL_SPMM_ARGS);
+    }
+
     static hipError_t tiles(int col_tile, int items, int vec, int64_t n, int64_t N,
                             const int32_t *pos, const int32_t *crd, const void *vals,
                             const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
@@ -458,9 +489,9 @@ struct SpmmTypes {
             return hipErrorInvalidValue;
         }
 #define SPL_SPMM_ITEMS(Wv)                                                                    \
-    if (items <= 8) return tiles_w<Wv, 8, 1>(SPL_SPMM_ARGS);                                  \
-    if (items <= 16) return tiles_w<Wv, 16, 1>(SPL_SPMM_ARGS);                                \
-    return tiles_w<Wv, 32, 1>(SPL_SPMM_ARGS);
+    if (items <= 8) return tiles_w<Wv, 8, 1, int32_t>(SPL_SPMM_ARGS);                         \
+    if (items <= 16) return tiles_w<Wv, 16, 1, int32_t>(SPL_SPMM_ARGS);                       \
+    return tiles_w<Wv, 32, 1, int32_t>(SPL_SPMM_ARGS);
         switch (col_tile) {
         case 8: SPL_SPMM_ITEMS(8)
         case 16: SPL_SPMM_ITEMS(16)
@@ -498,6 +529,23 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
 int spmm_vec_width(int vtype) {
     return vtype == SPL_F64 ? kSpmmVec<double> : vtype == SPL_F32 ? kSpmmVec<float>
                                                                   : kSpmmVec<bf16>;
+}
+
+hipError_t launch_spmm_tiles64(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
+                               const int64_t *pos, const int32_t *crd, const void *vals,
+                               const void *Bd, int64_t ldb, void *Out, int64_t ldo,
+                               const Tiles &t, int64_t stride, void *carry, hipStream_t s) {
+    if (vtype == SPL_F64)
+        return SpmmTypes<double, double, double, double>::tiles64(col_tile, items, vec, n, N, pos,
+                                                                  crd, vals, Bd, ldb, Out, ldo, t,
+                                                                  stride, true, carry, s);
+    if (vtype == SPL_F32)
+        return SpmmTypes<float, float, float, float>::tiles64(col_tile, items, vec, n, N, pos, crd,
+                                                              vals, Bd, ldb, Out, ldo, t, stride,
+                                                              true, carry, s);
+    return SpmmTypes<bf16, bf16, float, float>::tiles64(col_tile, items, vec, n, N, pos, crd, vals,
+                                                        Bd, ldb, Out, ldo, t, stride, true, carry,
+                                                        s);
 }
 
 hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,

@@ -254,5 +254,62 @@ def test_spmv_int64_positions_past_2_31_sampled():
     ref, S = oracle.spmv(pos_s, crd_s, val_s, c["x"].cpu().numpy())
     got = y[torch.as_tensor(rows, device=y.device)].cpu().numpy()
     assert_close(got, ref, S, 1e-12, "int64 positions, sampled rows")
-    del B, c, y, it
+    del y
+    # SpMM with N = 8 on the same matrix (int64 positions, vector lanes): the
+    # sampled rows' columns renumbered into a compact copy of the dense rows
+    # they gather
+    N = 8
+    D = torch.empty(n, N, dtype=torch.float64, device="cuda")
+    D.copy_(c["x"][:, None] * torch.arange(1, N + 1, dtype=torch.float64, device="cuda"))
+    A = spl.spmm(B, D)
+    ucols, inv = np.unique(crd_s, return_inverse=True)
+    Dh = D[torch.as_tensor(ucols, device="cuda")].cpu().numpy()
+    ref, S = oracle.spmm(pos_s, inv.astype(np.int32), val_s, Dh)
+    got = A[torch.as_tensor(rows, device=A.device)].cpu().numpy()
+    assert_close(got, ref, S, 1e-12, "SpMM with int64 positions, sampled rows")
+    del A, D
+    # SpTTV with int64 positions: the same arrays as the last level of a
+    # (Dense, Dense, Compressed) tensor of shape (n, 1, n), whose fibers are
+    # the matrix's rows
+    T = spl.DDC(c["pos"], c["crd"], c["vals"], (n, 1, n))
+    At = spl.spttv(T, c["x"])
+    got = At[torch.as_tensor(rows, device=At.device)].cpu().numpy()
+    ref, S = oracle.spmv(pos_s, crd_s, val_s, c["x"].cpu().numpy())
+    assert_close(got, ref, S, 1e-12, "SpTTV with int64 positions, sampled fibers")
+    del B, c, At, it, T
+    torch.cuda.empty_cache()
+
+
+def test_mttkrp_int64_positions_past_2_31_sampled():
+    # a CSF tensor of 2,214,592,512 positions (int64 pos1 and pos2; 8.9 GB
+    # each of coordinates and FP32 values): MTTKRP with R = 32 on sampled
+    # slices, several of them past position 2^31
+    spl, _ = _spl()
+    c = configs.csf_int64(device="cuda")
+    I, J, K = c["I"], c["J"], c["K"]
+    assert c["crd2"].numel() > 2**31
+    B = spl.CSF(c["pos1"], c["crd1"], c["pos2"], c["crd2"], c["vals"], (I, J, K))
+    M = spl.mttkrp(B, c["C"], c["D"])
+    rs = np.random.RandomState(9)
+    rows = np.unique(np.concatenate([rs.randint(0, I, 30), [0, 1, I - 2, I - 1],
+                                     np.arange(1_040_000, 1_040_008)]))
+    p1 = c["pos1"].cpu().numpy()
+    p2 = c["pos2"][torch.as_tensor(np.concatenate([p1[rows], p1[rows + 1]]),
+                                   device="cuda")].cpu().numpy()
+    assert p2[len(rows):].max() > 2**31
+    # the sampled slices as a small CSF: their fibers and positions
+    sp1, sc1, sp2, sc2, sv = [0], [], [0], [], []
+    for r in rows:
+        f0, f1 = int(p1[r]), int(p1[r + 1])
+        fpos = c["pos2"][f0:f1 + 1].cpu().numpy()
+        sc1.append(c["crd1"][f0:f1].cpu().numpy())
+        sp2.extend((fpos[1:] - fpos[0] + sp2[-1]).tolist())
+        sc2.append(c["crd2"][fpos[0]:fpos[-1]].cpu().numpy())
+        sv.append(c["vals"][fpos[0]:fpos[-1]].double().cpu().numpy())
+        sp1.append(sp1[-1] + f1 - f0)
+    ref, S = oracle.mttkrp(np.array(sp1, np.int32), np.concatenate(sc1), np.array(sp2, np.int32),
+                           np.concatenate(sc2), np.concatenate(sv), host64(c["C"]), host64(c["D"]))
+    got = host64(M[torch.as_tensor(rows, device=M.device)])
+    assert_close(got, ref, S, 1e-5, "MTTKRP with int64 positions, sampled slices")
+    del B, M, c
     torch.cuda.empty_cache()

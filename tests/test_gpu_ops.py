@@ -315,11 +315,35 @@ def test_spadd3_long_rows_span_output_windows():
     p3, c3, v3 = tiny.csr(rs, n, m, 0.001, full_rows={699}, kind="int")
     ops = [spl.CSR(_t(p), _t(c), _t(v, torch.float32), (n, m))
            for p, c, v in ((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))]
-    A = spl.spadd3(*ops)
     rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
-    assert np.array_equal(A.pos.cpu().numpy(), rpos)
-    assert np.array_equal(A.crd.cpu().numpy(), rcrd)
-    assert np.array_equal(host64(A.vals), rvals)
+    # every input-staging form of the numeric phase (direct, coordinates in
+    # LDS, coordinates and values in LDS; workgroups whose runs exceed the
+    # stage read directly)
+    for variant in (0, 1, 2, 3):
+        A = spl.spadd3(*ops, sched=spl.schedule("row", variant=variant))
+        assert np.array_equal(A.pos.cpu().numpy(), rpos), variant
+        assert np.array_equal(A.crd.cpu().numpy(), rcrd), variant
+        assert np.array_equal(host64(A.vals), rvals), variant
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spadd3_staged_fill_variants(dtype):
+    spl = _spl()
+    c = configs.config3(scale=0.003, with_dense=False)
+    shape = (c["n"], c["m"])
+    ops = [_csr_dev(spl, c[k], shape, dtype) for k in "BCD"]
+    host = [(c[k]["pos"].numpy(), c[k]["crd"].numpy(), host64(o.vals)) for k, o in zip("BCD", ops)]
+    rpos, rcrd, rvals, rS, _ = oracle.spadd3(*host)
+    first = None
+    for variant in (1, 2, 3):
+        A = spl.spadd3(*ops, sched=spl.schedule("row", variant=variant))
+        assert np.array_equal(A.pos.cpu().numpy(), rpos) and np.array_equal(A.crd.cpu().numpy(), rcrd)
+        assert_close(host64(A.vals), rvals, rS, RTOL[dtype], f"spadd3 variant {variant}")
+        if first is None:
+            first = A.vals.clone()
+        assert torch.equal(A.vals, first), variant  # same sums in the same order
+    with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
+        spl.spadd3(*ops, sched=spl.schedule("row", variant=4))
 
 
 def _perturbed_csf(c, rs, drop=0.3, extra=0.3):
@@ -604,3 +628,52 @@ def test_csf_tile_bounds_errors():
     Bd = spl.DDC(_t(pos2), _t(crd2), _t(v, torch.float64).float(), (3, 4, 20))
     with pytest.raises(spl.SpleafError):
         spl.csf_tile_bounds(Bd, 8)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spttv_int64_positions_match_int32(dtype):
+    spl = _spl()
+    c = _numpy(configs.config4(scale=0.001, with_dense=False))
+    B = _csf(spl, c, dtype)
+    B64 = spl.CSF(B.pos1.to(torch.int64), B.crd1, B.pos2.to(torch.int64), B.crd2, B.vals,
+                  B.shape)
+    cv = _t(c["c"], torch.float64).to(dtype)
+    ref, S = oracle.spttv(c["pos1"], c["pos2"], c["crd2"], host64(B.vals), host64(cv))
+    for sc in (dict(kind="default"), dict(kind="merge", tile=8192, items_per_lane=4),
+               dict(kind="merge", tile=3000, items_per_lane=8)):
+        a32 = spl.spttv(B, cv, sched=spl.schedule(**sc))
+        a64 = spl.spttv(B64, cv, sched=spl.schedule(**sc))
+        assert torch.equal(a32, a64), sc
+        assert_close(host64(a64), ref, S, RTOL[dtype], f"int64 spttv {sc}")
+    with pytest.raises(spl.SpleafError, match="SPL_ERR_UNSUPPORTED"):
+        spl.spttv(B64, cv, sched=spl.schedule(kind="row"))
+
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_mttkrp_int64_positions_match_int32(dtype):
+    # int64 pos1/pos2 (fiber starts staged relative to each chunk): the
+    # same walk as with int32 positions, so identical bits
+    spl = _spl()
+    c = _numpy(configs.config4(scale=0.001, R=32))
+    B = _csf(spl, c, dtype)
+    B64 = spl.CSF(B.pos1.to(torch.int64), B.crd1, B.pos2.to(torch.int64), B.crd2, B.vals,
+                  B.shape)
+    C = _t(c["C"], torch.float64).to(torch.float32).to(dtype)
+    D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
+    ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
+                           host64(C), host64(D))
+    scheds = [dict(kind="default"), dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
+              dict(kind="merge", tile=4096, col_tile=32, items_per_lane=4),
+              dict(kind="merge", tile=1, col_tile=64, items_per_lane=8)]
+    if dtype == torch.bfloat16:
+        scheds.append(dict(kind="merge", tile=700, col_tile=32, items_per_lane=4, variant=2))
+    for sc in scheds:
+        a32 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+        a64 = spl.mttkrp(B64, C, D, sched=spl.schedule(**sc))
+        assert torch.equal(a32, a64), (dtype, sc)
+        assert_close(host64(a64), ref, S, 1e-5, f"int64 mttkrp {dtype} {sc}")
+    for bad in (dict(kind="nnz", tile=1000), dict(kind="row", tile=4),
+                dict(kind="merge", variant=1)):
+        with pytest.raises(spl.SpleafError, match="SPL_ERR_UNSUPPORTED"):
+            spl.mttkrp(B64, C, D, sched=spl.schedule(**bad))

@@ -155,8 +155,9 @@ def test_spmv_int64_positions(dtype):
                 dict(kind="learned")):
         with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
             spl.spmv(B64, x, sched=spl.schedule(**bad))
+    # SpMM takes int64 positions with vector lanes only: 5 columns give none
     with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
-        spl.spmm(B64, torch.ones(B64.shape[1], 8, dtype=dtype, device=dev()))
+        spl.spmm(B64, torch.ones(B64.shape[1], 5, dtype=dtype, device=dev()))
 
 
 def test_merge_bounds_above_the_sweep_limit():
@@ -379,3 +380,25 @@ def test_host_errors_reported():
         with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
             spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                      sched=spl.schedule(**bad))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_spmm_int64_positions_match_int32(dtype):
+    # the same matrix with int64 pos: the same kernel walk (row ends staged
+    # relative to each chunk), so bit-identical results, and within the
+    # oracle's tolerance
+    spl = _spl()
+    c2 = configs.config2(scale=0.005, N=32)
+    B = _csr(spl, c2["pos"], c2["crd"], c2["vals"], (c2["n"], c2["n"]), dtype)
+    B64 = spl.CSR(B.pos.to(torch.int64), B.crd, B.vals, B.shape)
+    Bd = c2["B"].to(torch.float32).to(dtype).to(dev())
+    ref, S = oracle.spmm(c2["pos"].numpy(), c2["crd"].numpy(), host64(B.vals), host64(Bd))
+    for sc in (dict(kind="default"), dict(kind="merge", tile=4096, col_tile=32, items_per_lane=8),
+               dict(kind="merge", tile=777, col_tile=32, items_per_lane=16)):
+        a32 = spl.spmm(B, Bd, sched=spl.schedule(**sc))
+        a64 = spl.spmm(B64, Bd, sched=spl.schedule(**sc))
+        assert torch.equal(a32, a64), (dtype, sc)
+        assert_close(host64(a64), ref, S, RTOL[dtype], f"int64 spmm {dtype} {sc}")
+    for bad in (dict(kind="nnz", tile=512), dict(kind="row"), dict(kind="merge", variant=1)):
+        with pytest.raises(spl.SpleafError, match="SPL_ERR_UNSUPPORTED"):
+            spl.spmm(B64, Bd, sched=spl.schedule(**bad))

@@ -515,3 +515,53 @@ def test_csf_split_against_set_definitions(seed):
         assert np.all(tile_of >= 0)                     # every position covered once
         for f in range(F):                              # fiber aligned
             assert len(set(tile_of[p2[f]:p2[f + 1]].tolist())) <= 1
+
+
+# ---- transposition and CSC (the CSR of the transpose read by columns)
+
+@pytest.mark.parametrize("seed", range(5))
+def test_transpose_matches_dense_transpose_and_is_an_involution(seed):
+    rs = np.random.RandomState(seed)
+    n, m = 9 + seed, 13 - seed
+    pos, crd, vals = tiny.csr(rs, n, m, 0.3, empty_rows={2}, full_rows={4})
+    tpos, tcrd, tvals = oracle.transpose(pos, crd, vals, (n, m))
+    Bd, Bm = brute.dense_csr(pos, crd, vals, (n, m))
+    Td, Tm = brute.dense_csr(tpos, tcrd, tvals, (m, n))
+    assert np.array_equal(Td, Bd.T) and np.array_equal(Tm, Bm.T)
+    for c in range(m):  # rows of B^T strictly increasing
+        assert np.all(np.diff(tcrd[tpos[c]:tpos[c + 1]]) > 0)
+    p2, c2, v2 = oracle.transpose(tpos, tcrd, tvals, (m, n))
+    assert np.array_equal(p2, pos) and np.array_equal(c2, crd) and np.array_equal(v2, vals)
+
+
+def test_transpose_edge_cases():
+    # no entries; one column; one row
+    tpos, tcrd, tvals = oracle.transpose(np.zeros(4, np.int32), np.zeros(0, np.int32),
+                                         np.zeros(0), (3, 5))
+    assert np.array_equal(tpos, np.zeros(6, np.int32)) and tcrd.size == 0
+    pos = np.array([0, 1, 1, 2], np.int32)
+    tpos, tcrd, tvals = oracle.transpose(pos, np.array([0, 0], np.int32), np.array([2., 3.]),
+                                         (3, 1))
+    assert list(tpos) == [0, 2] and list(tcrd) == [0, 2] and list(tvals) == [2., 3.]
+    tpos, tcrd, _ = oracle.transpose(np.array([0, 3], np.int32), np.array([1, 4, 6], np.int32),
+                                     np.ones(3), (1, 7))
+    assert list(tpos) == [0, 0, 1, 1, 1, 2, 2, 3] and list(tcrd) == [0, 0, 0]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_csc_spmv_matches_einsum_and_the_transposed_csr(seed):
+    rs = np.random.RandomState(10 + seed)
+    n, m = 11, 8  # A is n x m, stored by columns: the CSR of the m x n A^T
+    kind = "int" if seed % 2 else "float"
+    cpos, crd, vals = tiny.csr(rs, m, n, 0.35, empty_rows={3}, kind=kind)
+    x = rs.randint(-4, 5, m).astype(np.float64) if kind == "int" else rs.uniform(-1, 1, m)
+    y, S = oracle.csc_spmv(cpos, crd, vals, x, n)
+    At, _ = brute.dense_csr(cpos, crd, vals, (m, n))
+    want = np.einsum("ij,j->i", At.T, x)
+    if kind == "int":
+        assert np.array_equal(y, want)
+    else:
+        assert np.allclose(y, want, rtol=0, atol=1e-14)
+    rpos, rcrd, rvals = oracle.transpose(cpos, crd, vals, (m, n))
+    y2, S2 = oracle.spmv(rpos, rcrd, rvals, x)
+    assert np.allclose(y, y2, rtol=0, atol=1e-15 * max(1, S.max())) and np.allclose(S, S2)

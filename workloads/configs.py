@@ -153,6 +153,35 @@ def banded(device="cpu", n=20_000_000, half_width=17, kind="sym", pos_dtype=torc
     return dict(n=n, m=n, pos=pos.to(pos_dtype), crd=crd, vals=vals, x=x, half_width=w)
 
 
+def csf_int64(device="cpu", I=1 << 20, fibers=64, run=33, R=32, chunk=1 << 27):
+    """A CSF tensor past 2^31 positions with a regular pattern (int64 pos1 and
+    pos2): every slice holds `fibers` fibers at j = t * (J / fibers) + i mod
+    (J / fibers), every fiber `run` positions at k = s * 32 + (7 f) mod 32, so
+    nnz = I * fibers * run (2,214,592,512 by default); values uniform[0, 1)
+    in FP32, factors N(0, 1) in FP32, all drawn in chunks."""
+    dev = _dev(device)
+    J = 65536
+    K = 32 * run
+    F = I * fibers
+    nnz = F * run
+    pos1 = torch.arange(I + 1, dtype=torch.int64, device=dev) * fibers
+    f = torch.arange(F, dtype=torch.int64, device=dev)
+    crd1 = ((f % fibers) * (J // fibers) + (f // fibers) % (J // fibers)).to(torch.int32)
+    pos2 = torch.arange(F + 1, dtype=torch.int64, device=dev) * run
+    del f
+    crd2 = torch.empty(nnz, dtype=torch.int32, device=dev)
+    vals = torch.empty(nnz, dtype=torch.float32, device=dev)
+    key = gen.key_for(9, 1)
+    for a in range(0, nnz, chunk):
+        p = torch.arange(a, min(nnz, a + chunk), dtype=torch.int64, device=dev)
+        crd2[a:a + p.numel()] = ((p % run) * 32 + ((p // run) * 7) % 32).to(torch.int32)
+        vals[a:a + p.numel()] = gen.uniform(key, p).to(torch.float32)
+        del p
+    C = gen.values(gen.key_for(9, 2), J * R, dev, "normal").reshape(J, R).to(torch.float32)
+    D = gen.values(gen.key_for(9, 3), K * R, dev, "normal").reshape(K, R).to(torch.float32)
+    return dict(I=I, J=J, K=K, pos1=pos1, crd1=crd1, pos2=pos2, crd2=crd2, vals=vals, C=C, D=D)
+
+
 def ddc(device="cpu", scale=1.0, R=32, I=46, with_dense=True):
     """Config 7: (Dense, Dense, Compressed) tensor; pos2 indexes all I*J
     fibers (fiber f = i*J + j)."""
