@@ -459,10 +459,10 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     const int64_t chunk = (256 / (p.items <= 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
-    if (s->variant < 0 || s->variant > 2)
+    if (s->variant < 0 || s->variant > 3)
         return fail(ctx, SPL_ERR_ARG,
-                    "MTTKRP variant must be 0 (vector lanes), 1 (one column per lane) or 2 "
-                    "(8-byte BF16 lanes)");
+                    "MTTKRP variant must be 0 (vector lanes), 1 (one column per lane), 2 "
+                    "(8-byte BF16 lanes) or 3 (FP32 vector lanes with positions staged in LDS)");
     p.variant = s->variant;
     return SPL_OK;
 }
@@ -486,7 +486,8 @@ int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_
                reinterpret_cast<uintptr_t>(A->data) % 16 == 0;
     };
     const bool bf = C->dtype == SPL_BF16;
-    if (bf && p.variant == 0 && (p.items == 4 || p.col_tile == 64) && fits(8)) return 8;
+    if (bf && p.variant == 0 && (p.items == 4 || (p.items == 8 && p.col_tile == 64)) && fits(8))
+        return 8;
     return fits(4) ? 4 : 1;
 }
 
@@ -1396,6 +1397,9 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     SPL_CHECK(resolve_mttkrp(ctx, R, sched, p));
     if (p.variant == 2 && B->vtype != SPL_BF16)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP variant 2 (8-byte lanes) is for BF16 factors");
+    if (p.variant == 3 && (B->vtype != SPL_F32 || p.items != 4))
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP variant 3 (staged positions) is for F32 with items_per_lane 4");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t I = B->dims[0];
@@ -1445,7 +1449,8 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
         SPL_HIP(spl::launch_tile_bounds(p.kind, I, B->pos[1], B->nfibers, q.size, cv.tiles, s),
                 "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
-    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.col_tile, p.items, p.vec, I, R, B->pos[1], B->crd[1],
+    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.variant == 3, p.col_tile, p.items, p.vec, I, R,
+                                     B->pos[1], B->crd[1],
                                      B->pos[2], B->crd[2], B->vals, C->data, C->ld, D->data,
                                      D->ld, static_cast<float *>(A->data), A->ld, cv.tiles,
                                      q.stride, static_cast<float *>(cv.carry), s),

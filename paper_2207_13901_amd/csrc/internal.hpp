@@ -101,11 +101,14 @@ hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, cons
 // vec: 1, or 4 rank columns per lane (R, ldc, ldd, lda multiples of 4, C and D
 // aligned to 4 elements and A to 16 bytes, col_tile / 4 in {8, 16}, items
 // 8).
-hipError_t launch_mttkrp_tiles(int vtype, int col_tile, int items, int vec, int64_t I, int64_t R,
-                               const int32_t *pos1, const int32_t *crd1, const int32_t *pos2,
-                               const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
-                               const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
-                               int64_t stride, float *carry, hipStream_t s);
+// stage: FP32 vector lanes with 4 items stage the chunk's leading positions
+// in LDS as the BF16 leaf always does.
+hipError_t launch_mttkrp_tiles(int vtype, bool stage, int col_tile, int items, int vec, int64_t I,
+                               int64_t R, const int32_t *pos1, const int32_t *crd1,
+                               const int32_t *pos2, const int32_t *crd2, const void *vals,
+                               const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
+                               int64_t lda, const Tiles &t, int64_t stride, float *carry,
+                               hipStream_t s);
 // The vector-lane MTTKRP leaf over a CSF with int64 pos1/pos2 (fiber count
 // below 2^31; merge split over slices and fibers, tiles in t.row / t.pos).
 hipError_t launch_mttkrp_tiles64(int vtype, int col_tile, int items, int vec, int64_t I,

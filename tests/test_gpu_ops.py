@@ -106,7 +106,9 @@ def test_mttkrp(dtype, R):
         D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
         ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
                                host64(C), host64(D))
-        for sc in MTTKRP_SCHEDULES + (MTTKRP_VEC4 if R % 4 == 0 else []):
+        staged = [dict(sc, variant=3) for sc in MTTKRP_VEC4 if sc["items_per_lane"] == 4] \
+            if dtype == torch.float32 and R % 4 == 0 else []
+        for sc in MTTKRP_SCHEDULES + (MTTKRP_VEC4 if R % 4 == 0 else []) + staged:
             A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
             assert A.dtype == torch.float32
             assert_close(host64(A), ref, S, 1e-5, f"mttkrp {dtype} R={R} {sc}")
@@ -124,7 +126,8 @@ def test_mttkrp_integer_values_bit_exact():
     B = _csf(spl, c, torch.float32)
     ref, _ = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], c["vals"],
                            host64(C), host64(D))
-    for sc in MTTKRP_SCHEDULES + MTTKRP_VEC4:
+    for sc in MTTKRP_SCHEDULES + MTTKRP_VEC4 + [dict(sc, variant=3) for sc in MTTKRP_VEC4
+                                                if sc["items_per_lane"] == 4]:
         A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
         assert np.array_equal(host64(A), ref), sc
 
