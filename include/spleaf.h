@@ -374,7 +374,9 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * (16 bytes) per lane instead when R and every ld are multiples of 8, C and
  * D 16-byte aligned and (col_tile, items_per_lane) is (32, 4), (64, 4) or
  * (64, 8); 1 = one column per lane; 2 (BF16 only, else SPL_ERR_ARG) = 4
- * BF16 rank columns (8 bytes) per lane.
+ * BF16 rank columns (8 bytes) per lane; 3 (F32 with items_per_lane 4, else
+ * SPL_ERR_ARG) = as 0 with each chunk's leading positions staged in LDS, as
+ * the BF16 leaf does.
  * items_per_lane: 8 (default) or 16 for either leaf; 4 only with the
  * 4-column lanes (SPL_ERR_ARG when they do not apply): half the registers
  * and LDS of 8, so more waves per SIMD.  The workspace query returns the
