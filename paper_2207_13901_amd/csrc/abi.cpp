@@ -454,8 +454,9 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     p.items = s->items_per_lane ? s->items_per_lane : 8;
     if (p.items != 4 && p.items != 8 && p.items != 16)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 4, 8 or 16");
-    // four leaf chunks per workgroup by default (vector-lane chunks when
-    // the operands allow them: col_tile 32 or 64 with 4 or 8 items)
+    // by default four chunks of a 256-thread workgroup with 4-column lanes
+    // (col_tile 32 or 64, 4 or 8 items), eight of the vector-lane leaf's
+    // 128-thread workgroup: 512 merged items for col_tile 32 and 4 items
     const int64_t chunk = (256 / (p.items <= 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
@@ -467,7 +468,12 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     return SPL_OK;
 }
 
-int64_t mttkrp_chunk(const Plan &p) { return (256 / (p.col_tile / p.vec)) * p.items; }
+// Merged items per leaf chunk: lane groups of one workgroup (128 threads for
+// the vector-lane leaf, 256 for one column per lane) times items per group.
+int64_t mttkrp_chunk(const Plan &p) {
+    const int64_t threads = p.vec > 1 ? spl::kMttkrpThreads : 256;
+    return (threads / (p.col_tile / p.vec)) * p.items;
+}
 
 // Vector lanes for the MTTKRP leaf: v rank columns per lane when R, the
 // leading dimensions and the pointers allow it, col_tile is 32 or 64 and

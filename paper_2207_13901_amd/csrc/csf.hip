@@ -213,13 +213,17 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
 // are loaded right after this chunk's gathers are issued, and the groups'
 // heads and tails are combined by all threads at once (a column of a part
 // each), so a chunk costs one barrier-separated round of gathers.  With
-// BF16 factors the chunk's first 512 positions (k and value) are staged in
-// LDS with the chunk, so the D-row gathers wait on LDS rather than on a
+// BF16 factors the chunk's first 2 * NT positions (k and value) are staged
+// in LDS with the chunk, so the D-row gathers wait on LDS rather than on a
 // load from HBM (7.2 -> 6.4 ms on the 1e8-nonzero tensor); with FP32 the
-// registers this needs would cost a wave per SIMD, so FP32 keeps the direct
-// loads.  ITEMS 4 halves the C-row slab and the per-group registers (116
-// VGPRs and 28 KB of LDS against 161 and 45 KB): 4 waves per SIMD instead of
+// registers this needs cost more than it saves (4.08 against 3.69 ms), so
+// FP32 keeps the direct loads.  ITEMS 4 halves the C-row slab and the
+// per-group registers (116 VGPRs against 161): 4 waves per SIMD instead of
 // 3, more gathers in flight (4.93 -> 4.56 ms FP32, 6.40 -> 5.32 ms BF16).
+// Workgroups of NT = 128 threads (two waves): a barrier waits for one
+// other wave instead of three, and the 16-byte BF16 leaf's LDS (41 KB per
+// 256 threads) no longer caps it at 3 workgroups of 4 waves per CU
+// (FP32 3.85 -> 3.69 ms, BF16 3.76 -> 3.25 ms; 64 threads: 3.78 and 3.33).
 //
 // int64 positions (PosT): pos1's entries are fiber indices (below 2^31) and
 // are staged as they are; pos2's are staged relative to the chunk's first
@@ -232,21 +236,23 @@ __device__ __forceinline__ int32_t rel_pos(PosT p, int64_t base) {
 }
 
 template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc,
-          typename PosT = int32_t, bool STAGE = sizeof(FT) == 2>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
+          typename PosT = int32_t, bool STAGE = sizeof(FT) == 2, int NT = kMttkrpThreads>
+__global__ __launch_bounds__(NT) void k_mttkrp_vec(
     int64_t I, int64_t R, const PosT *__restrict__ pos1, const int32_t *__restrict__ crd1,
     const PosT *__restrict__ pos2, const int32_t *__restrict__ crd2,
     const V *__restrict__ vals, const FT *__restrict__ C, int64_t ldc,
     const FT *__restrict__ D, int64_t ldd, float *__restrict__ A, int64_t lda,
     const int32_t *__restrict__ tslice, const int32_t *__restrict__ tfib, int64_t npieces,
     int64_t stride, Acc *__restrict__ carry) {
-    constexpr int G = kBlock / W;
+    constexpr int G = NT / W;
     constexpr int kChunk = G * ITEMS;
+    static_assert(kChunk <= NT, "the chunk is staged one item per thread");
     // BF16 factors stage the chunk's leading positions in LDS (below); FP32
-    // keeps more positions per group in registers instead (both measured
-    // best that way at 3 waves per SIMD)
+    // keeps more positions per group in registers instead (7 per batch for
+    // 4 items: 122 VGPRs, still 4 waves per SIMD; 6: 3.69 ms, 8: 3.75 ms
+    // against 3.65 on the 1e8-nonzero tensor)
     constexpr bool kStage = STAGE;
-    constexpr int kPosCap = kStage ? ITEMS + ITEMS / 4 : ITEMS + ITEMS / 2;
+    constexpr int kPosCap = kStage ? ITEMS + ITEMS / 4 : ITEMS == 4 ? 7 : ITEMS + ITEMS / 2;
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];
@@ -260,13 +266,13 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
     // cross-group combine: the tile's columns split over kParts parts of
     // G / kParts groups each
     constexpr int NC = W * VEC;
-    constexpr int kParts = kBlock / NC;
+    constexpr int kParts = NT / NC;
     constexpr int kGroupsPerPart = G / kParts;
-    static_assert(kParts * NC == kBlock && kGroupsPerPart * kParts == G, "combine layout");
+    static_assert(kParts * NC == NT && kGroupsPerPart * kParts == G, "combine layout");
     __shared__ Acc s_open[NC];  // the open row's partial entering the chunk
     // the chunk's first kStagePos positions (k and value), staged with the
     // chunk so that the D-row gathers wait on LDS, not on HBM
-    constexpr int kStagePos = kStage ? 2 * kBlock : 0;
+    constexpr int kStagePos = kStage ? 2 * NT : 0;
     __shared__ int32_t s_kq[kStage ? kStagePos : 1];
     __shared__ Acc s_vq[kStage ? kStagePos : 1];
     __shared__ Acc s_pb[kParts][NC];
@@ -309,12 +315,12 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             if (tid < nr) s_end[tid] = pre_e;
             if (tid < nf) s_j[tid] = pre_j;
             if (tid <= nf) s_fp[tid] = pre_f;
-            if constexpr (kChunk >= kBlock)  // nf + 1 entries: one more than lanes
-                if (tid == 0 && nf == kBlock) s_fp[kBlock] = pre_f2;
+            if constexpr (kChunk >= NT)  // nf + 1 entries: one more than lanes
+                if (tid == 0 && nf == NT) s_fp[NT] = pre_f2;
             if constexpr (kStage) {
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
-                    const int k = tid + jj * kBlock;
+                    const int k = tid + jj * NT;
                     if (k < pre_np && k < kStagePos) {
                         s_kq[k] = pre_k[jj];
                         s_vq[k] = widen<Acc>(pre_v[jj]);
@@ -323,12 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
             }
         } else {
             if constexpr (sizeof(PosT) == 8) pbase = pos2[cf];
-            for (int k = tid; k < nr; k += kBlock) s_end[k] = static_cast<int32_t>(pos1[ci + 1 + k]);
-            for (int k = tid; k < nf; k += kBlock) s_j[k] = crd1[cf + k];
-            for (int k = tid; k <= nf; k += kBlock) s_fp[k] = rel_pos(pos2[cf + k], pbase);
+            for (int k = tid; k < nr; k += NT) s_end[k] = static_cast<int32_t>(pos1[ci + 1 + k]);
+            for (int k = tid; k < nf; k += NT) s_j[k] = crd1[cf + k];
+            for (int k = tid; k <= nf; k += NT) s_fp[k] = rel_pos(pos2[cf + k], pbase);
             if constexpr (kStage) {
                 const int64_t p0 = pos2[cf], npb = pos2[ef] - p0;
-                for (int k = tid; k < npb && k < kStagePos; k += kBlock) {
+                for (int k = tid; k < npb && k < kStagePos; k += NT) {
                     s_kq[k] = crd2[p0 + k];
                     s_vq[k] = widen<Acc>(vals[p0 + k]);
                 }
@@ -391,14 +397,14 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_vec(
                 if (tid < nnr) pre_e = static_cast<int32_t>(pos1[ei + 1 + tid]);
                 if (tid < nnf) pre_j = crd1[ef + tid];
                 if (tid <= nnf) pre_f = rel_pos(pos2[ef + tid], pre_base);
-                if constexpr (kChunk >= kBlock)
-                    if (tid == 0 && nnf == kBlock) pre_f2 = rel_pos(pos2[ef + kBlock], pre_base);
+                if constexpr (kChunk >= NT)
+                    if (tid == 0 && nnf == NT) pre_f2 = rel_pos(pos2[ef + NT], pre_base);
                 if constexpr (kStage) {
                     const int64_t pp0 = pos2[ef];
                     pre_np = pos2[nef] - pp0;
 #pragma unroll
                     for (int jj = 0; jj < 2; ++jj) {
-                        const int kk = tid + jj * kBlock;
+                        const int kk = tid + jj * NT;
                         if (kk < pre_np && kk < kStagePos) {
                             pre_k[jj] = load_stream(crd2 + pp0 + kk);
                             pre_v[jj] = load_stream(vals + pp0 + kk);
@@ -590,12 +596,16 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
     const int lanes = col_tile / vec;
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)),
               static_cast<unsigned>(ceil_div(R, col_tile)));
-    auto go = [&](auto kern) {
-        kern<<<grid, kBlock, 0, s>>>(I, R, pos1, crd1, pos2, crd2, static_cast<const V *>(vals),
+    // every launch names its thread count, which must be the kernel's NT
+    // (k_mttkrp_vec) or kBlock (k_mttkrp_tiles)
+    auto launch = [&](auto kern, int threads) {
+        kern<<<grid, threads, 0, s>>>(I, R, pos1, crd1, pos2, crd2, static_cast<const V *>(vals),
                                      static_cast<const FT *>(C), ldc, static_cast<const FT *>(D),
                                      ldd, A, lda, t.row, t.pos, t.ntiles, stride, carry);
         return hipGetLastError();
     };
+    auto go = [&](auto kern) { return launch(kern, kMttkrpThreads); };
+    auto go_tiles = [&](auto kern) { return launch(kern, kBlock); };
     if constexpr (sizeof(FT) == 4) {
         // FP32 with the chunk's leading positions staged in LDS as for BF16
         if (stage && vec == kMttkrpVec && items == 4) {
@@ -632,12 +642,12 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
         return hipErrorInvalidValue;  // int64 positions: vector lanes only
     } else {
     if (vec > 1) return hipErrorInvalidValue;
-    if (col_tile == 16) return items <= 8 ? go(k_mttkrp_tiles<16, 8, V, FT, float>)
-                                          : go(k_mttkrp_tiles<16, 16, V, FT, float>);
-    if (col_tile == 64) return items <= 8 ? go(k_mttkrp_tiles<64, 8, V, FT, float>)
-                                          : go(k_mttkrp_tiles<64, 16, V, FT, float>);
-    return items <= 8 ? go(k_mttkrp_tiles<32, 8, V, FT, float>)
-                      : go(k_mttkrp_tiles<32, 16, V, FT, float>);
+    if (col_tile == 16) return items <= 8 ? go_tiles(k_mttkrp_tiles<16, 8, V, FT, float>)
+                                          : go_tiles(k_mttkrp_tiles<16, 16, V, FT, float>);
+    if (col_tile == 64) return items <= 8 ? go_tiles(k_mttkrp_tiles<64, 8, V, FT, float>)
+                                          : go_tiles(k_mttkrp_tiles<64, 16, V, FT, float>);
+    return items <= 8 ? go_tiles(k_mttkrp_tiles<32, 8, V, FT, float>)
+                      : go_tiles(k_mttkrp_tiles<32, 16, V, FT, float>);
     }
 }
 

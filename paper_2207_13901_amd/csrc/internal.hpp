@@ -88,6 +88,9 @@ hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, in
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 
 // ---- csf.hip -------------------------------------------------------------
+// Threads per workgroup of the vector-lane MTTKRP leaf (the one-column
+// leaf uses 256): its merged-item chunk is (128 / lanes) * items_per_lane.
+constexpr int kMttkrpThreads = 128;
 // Value-range partition of a Compressed level: out[c * rows + i] = first
 // position of parent i whose coordinate is >= bounds[c], c < nbounds.
 hipError_t launch_coord_split(int64_t rows, const int32_t *pos, const int32_t *crd, int64_t nbounds,

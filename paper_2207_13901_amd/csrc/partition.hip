@@ -189,14 +189,19 @@ int64_t tile_count(int kind, int64_t rows, int64_t nnz, int64_t size) {
     return nt > 0 ? nt : 1;
 }
 
-// Up to this many rows the merge split is computed by the sweep (a read of
-// 4 (rows + 1) bytes); beyond, by one merge-path search per tile.
+// Up to this many rows, and while there are fewer tiles than rows, the
+// merge split is computed by the sweep (a read of 4 (rows + 1) bytes);
+// otherwise by one merge-path search per tile.  With more tiles than rows
+// the sweep's lanes would write many bounds each, one after another: the
+// 200,000 power-law slices of a 1e8-nonzero CSF cut into 990,000 chunks of
+// 64 merged items took 253 us by the sweep, its longest slice writing about
+// 3,000 bounds.
 constexpr int64_t kMergeSweepRows = 8000000;
 
 template <typename P, typename TP>
 hipError_t merge_bounds(int64_t rows, const P *pos, int64_t nnz, int64_t size, int64_t ntiles,
                         int32_t *trow, TP *tpos, hipStream_t s) {
-    if (rows <= kMergeSweepRows)
+    if (rows <= kMergeSweepRows && ntiles < rows)
         k_merge_sweep<P, TP><<<dim3(static_cast<unsigned>(ceil_div(rows + 1, kBlock))), kBlock, 0,
                                s>>>(rows, pos, nnz, size, ntiles, trow, tpos);
     else
