@@ -143,7 +143,8 @@ typedef struct spl_schedule {
     int32_t tile;           /* SPL_NNZ: positions per tile; SPL_MERGE: merged
                                items per tile                                 */
     int32_t items_per_lane; /* merged items one lane (SpMV) or lane group
-                               (SpMM, MTTKRP) walks per chunk: 4, 8 or 16      */
+                               (SpMM, MTTKRP) walks per chunk: 4, 8 or 16
+                               (MTTKRP also 3 and 5); 0 = the op's default  */
     int32_t col_tile;       /* SpMM: dense columns per lane group: 8,16,32,64 */
     int32_t variant;        /* op-specific kernel variant, 0 = default        */
 } spl_schedule;
@@ -369,18 +370,23 @@ spl_status spl_spttv(spl_context *ctx, const spl_sparse *B, const spl_dense *c,
  * 32 or 64 rank columns per lane group.  sched->variant: 0 = each lane reads
  * and writes 4 consecutive rank columns with one vector access when R,
  * C->ld, D->ld and A->ld are multiples of 4, C and D are aligned to 4
- * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is 4 or
- * 8 (otherwise one column per lane) -- with BF16 factors 8 rank columns
+ * elements, A to 16 bytes, col_tile is 32 or 64 and items_per_lane is not
+ * 16 (otherwise one column per lane) -- with BF16 factors 8 rank columns
  * (16 bytes) per lane instead when R and every ld are multiples of 8, C and
- * D 16-byte aligned and (col_tile, items_per_lane) is (32, 4), (64, 4) or
- * (64, 8); 1 = one column per lane; 2 (BF16 only, else SPL_ERR_ARG) = 4
+ * D 16-byte aligned and (col_tile, items_per_lane) is (32, 0), (32, 3),
+ * (32, 4), (64, 0), (64, 4) or (64, 8); 1 = one column per lane; 2 (BF16 only, else SPL_ERR_ARG) = 4
  * BF16 rank columns (8 bytes) per lane; 3 (F32 with items_per_lane 4, else
  * SPL_ERR_ARG) = as 0 with each chunk's leading positions staged in LDS, as
  * the BF16 leaf does.
- * items_per_lane: 8 (default) or 16 for either leaf; 4 only with the
- * 4-column lanes (SPL_ERR_ARG when they do not apply): half the registers
- * and LDS of 8, so more waves per SIMD.  The workspace query returns the
- * one-column-per-lane size, enough for both.  A
+ * items_per_lane: 8 or 16 for either leaf; 4 only with vector lanes, 5
+ * only with 4-column lanes at col_tile 32, 3 only with 8-column BF16 lanes
+ * at col_tile 32 (SPL_ERR_ARG when they do not apply): fewer registers and
+ * LDS than 8, so more waves per SIMD.  0 (default) takes 5 for 4-column
+ * lanes at col_tile 32 (4 with int64 positions or variant 3), 3 for
+ * 8-column BF16 lanes at col_tile 32, 4 for the other vector lanes and 8
+ * for one column per lane; tile 0 (default) takes 512 merged items with
+ * vector lanes.  The workspace query returns the largest size over the
+ * lane widths the call may take.  A
  * (Dense, Dense, Compressed) B is accepted: its middle level's pos/crd
  * (I + 1 and I * J int32) are written into the workspace, counted by the
  * query, and the leaf runs as for CSF. */

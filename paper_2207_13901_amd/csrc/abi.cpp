@@ -451,15 +451,13 @@ spl_status resolve_mttkrp(spl_context *ctx, int64_t R, const spl_schedule *s, Pl
     if (ct != 16 && ct != 32 && ct != 64)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP col_tile must be 16, 32 or 64");
     p.col_tile = ct;
-    p.items = s->items_per_lane ? s->items_per_lane : 8;
-    if (p.items != 4 && p.items != 8 && p.items != 16)
-        return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 4, 8 or 16");
-    // by default four chunks of a 256-thread workgroup with 4-column lanes
-    // (col_tile 32 or 64, 4 or 8 items), eight of the vector-lane leaf's
-    // 128-thread workgroup: 512 merged items for col_tile 32 and 4 items
-    const int64_t chunk = (256 / (p.items <= 8 && ct >= 32 ? ct / 4 : ct)) * p.items;
-    p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048 : 4 * chunk);
-    if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
+    // 0: chosen with the lane width (finish_mttkrp)
+    p.items = s->items_per_lane;
+    if (p.items != 0 && p.items != 3 && p.items != 4 && p.items != 5 && p.items != 8 &&
+        p.items != 16)
+        return fail(ctx, SPL_ERR_ARG, "MTTKRP items_per_lane must be 3, 4, 5, 8 or 16");
+    p.tile = s->tile;  // 0: chosen with the lane width
+    if (p.tile < 0) return fail(ctx, SPL_ERR_ARG, "tile must be positive");
     if (s->variant < 0 || s->variant > 3)
         return fail(ctx, SPL_ERR_ARG,
                     "MTTKRP variant must be 0 (vector lanes), 1 (one column per lane), 2 "
@@ -475,14 +473,39 @@ int64_t mttkrp_chunk(const Plan &p) {
     return (threads / (p.col_tile / p.vec)) * p.items;
 }
 
+// The defaults that depend on the lane width p.vec: items per lane group
+// (5 for 8 lanes of 4 columns, 3 for 4 lanes of 8 BF16 columns -- each the
+// most merged items whose registers still leave 4 waves per SIMD; 4 for the
+// other vector lanes and for variant 3; 8 for one column per lane) and the
+// tile (512 merged items with vector lanes, four 256-thread chunks
+// otherwise).  With int64 positions the 4-column leaf takes 4 items: 5 would
+// need one register more than 4 waves per SIMD allow.
+void finish_mttkrp(Plan &p, bool pos64) {
+    const int lanes = p.col_tile / p.vec;
+    if (p.items == 0) {
+        if (p.vec == 1)
+            p.items = 8;
+        else if (p.variant == 3)
+            p.items = 4;
+        else if (p.vec == 8)
+            p.items = lanes == 4 ? 3 : 4;
+        else
+            p.items = lanes == 8 && !pos64 ? 5 : 4;
+    }
+    if (p.tile == 0)
+        p.tile = p.kind == SPL_ROW ? 64 : p.kind == SPL_NNZ ? 2048
+                 : p.vec > 1     ? 512
+                                 : 4 * mttkrp_chunk(p);
+}
+
 // Vector lanes for the MTTKRP leaf: v rank columns per lane when R, the
 // leading dimensions and the pointers allow it, col_tile is 32 or 64 and
-// items_per_lane 4 or 8; otherwise one column per lane.  v = 4 (16-byte
+// items_per_lane is not 16; otherwise one column per lane.  v = 4 (16-byte
 // FP32 rows, 8-byte BF16 rows; BF16 variant 2), or for BF16 under variant 0
-// v = 8 (16-byte rows) with (col_tile, items) (32, 4), (64, 4) or (64, 8).
+// v = 8 (16-byte rows) with (col_tile, items) (32, 3), (32, 4), (64, 4),
+// (64, 8) or items chosen by default.
 int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_dense *A) {
-    if (p.variant == 1 || (p.items != 8 && p.items != 4) || (p.col_tile != 32 && p.col_tile != 64))
-        return 1;
+    if (p.variant == 1 || p.items == 16 || (p.col_tile != 32 && p.col_tile != 64)) return 1;
     const int64_t R = C->dims[1];
     auto fits = [&](int v) {
         const size_t fb = v * dtype_bytes(C->dtype);
@@ -492,7 +515,9 @@ int mttkrp_vec(const Plan &p, const spl_dense *C, const spl_dense *D, const spl_
                reinterpret_cast<uintptr_t>(A->data) % 16 == 0;
     };
     const bool bf = C->dtype == SPL_BF16;
-    if (bf && p.variant == 0 && (p.items == 4 || (p.items == 8 && p.col_tile == 64)) && fits(8))
+    if (bf && p.variant == 0 && fits(8) &&
+        (p.items == 0 || p.items == 4 || (p.items == 3 && p.col_tile == 32) ||
+         (p.items == 8 && p.col_tile == 64)))
         return 8;
     return fits(4) ? 4 : 1;
 }
@@ -917,11 +942,21 @@ spl_status spl_workspace_query(spl_context *ctx, spl_op op, const spl_sparse *B,
         *bytes = spmv_ws(&v, p);
         return SPL_OK;
     }
-    case SPL_OP_MTTKRP:
+    case SPL_OP_MTTKRP: {
         SPL_CHECK(check_sparse(ctx, B, 3, true));
         SPL_CHECK(resolve_mttkrp(ctx, ncols, sched, p));
-        *bytes = dense_middle_ws(B) + mttkrp_ws(B, ncols, p);
+        // the lane width depends on the factors' pointers: the largest
+        // workspace over every width the call may take
+        size_t ws = 0;
+        for (int v : {1, 4, 8}) {
+            Plan q = p;
+            q.vec = v;
+            finish_mttkrp(q, B->pos_type == SPL_I64);
+            ws = std::max(ws, mttkrp_ws(B, ncols, q));
+        }
+        *bytes = dense_middle_ws(B) + ws;
         return SPL_OK;
+    }
     case SPL_OP_SDDMM:
         SPL_CHECK(check_sparse(ctx, B, 2));
         SPL_CHECK(resolve_sddmm(ctx, sched, p));
@@ -1403,15 +1438,24 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     SPL_CHECK(resolve_mttkrp(ctx, R, sched, p));
     if (p.variant == 2 && B->vtype != SPL_BF16)
         return fail(ctx, SPL_ERR_ARG, "MTTKRP variant 2 (8-byte lanes) is for BF16 factors");
-    if (p.variant == 3 && (B->vtype != SPL_F32 || p.items != 4))
-        return fail(ctx, SPL_ERR_ARG,
-                    "MTTKRP variant 3 (staged positions) is for F32 with items_per_lane 4");
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t I = B->dims[0];
     if (I == 0 || R == 0) return SPL_OK;
-    // the workspace query assumed one column per lane: the larger size
+    // the workspace query took the largest size over the lane widths
     p.vec = mttkrp_vec(p, C, D, A);
+    finish_mttkrp(p, pos64);
+    if (p.variant == 3 && (B->vtype != SPL_F32 || p.items != 4))
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP variant 3 (staged positions) is for F32 with items_per_lane 4");
+    if (p.items == 3 && !(p.vec == 8 && p.col_tile == 32))
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP items_per_lane 3 needs 8-column BF16 lanes (BF16 factors, variant 0, "
+                    "col_tile 32, R and every ld multiples of 8, 16-byte aligned factors)");
+    if (p.items == 5 && !(p.vec == 4 && p.col_tile == 32))
+        return fail(ctx, SPL_ERR_ARG,
+                    "MTTKRP items_per_lane 5 needs 4-column lanes at col_tile 32 (variant 0 or "
+                    "2, R and every ld multiples of 4, aligned factors)");
     if (pos64 && (p.kind != SPL_MERGE || p.vec == 1))
         return fail(ctx, SPL_ERR_UNSUPPORTED,
                     "int64 positions: MERGE schedule with vector lanes only (variant 0 or 2, "

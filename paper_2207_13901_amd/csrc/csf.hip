@@ -248,11 +248,14 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
     constexpr int kChunk = G * ITEMS;
     static_assert(kChunk <= NT, "the chunk is staged one item per thread");
     // BF16 factors stage the chunk's leading positions in LDS (below); FP32
-    // keeps more positions per group in registers instead (7 per batch for
-    // 4 items: 122 VGPRs, still 4 waves per SIMD; 6: 3.69 ms, 8: 3.75 ms
-    // against 3.65 on the 1e8-nonzero tensor)
+    // keeps more positions per group in registers instead.  Positions per
+    // batch, measured on the 1e8-nonzero tensor: FP32 4 items 7 (122 VGPRs;
+    // 6: 3.69 ms, 8: 3.75 against 3.65), 5 items 7 (128 VGPRs, still 4
+    // waves per SIMD; 6: 3.40, 8: 3.38 against 3.30); BF16 8-column lanes
+    // with 3 items 5 (3 or 4: 3.03-3.05 against 3.02)
     constexpr bool kStage = STAGE;
-    constexpr int kPosCap = kStage ? ITEMS + ITEMS / 4 : ITEMS == 4 ? 7 : ITEMS + ITEMS / 2;
+    constexpr int kPosCap = kStage ? (ITEMS == 3 ? 5 : ITEMS + ITEMS / 4)
+                                   : (ITEMS == 4 || ITEMS == 5) ? 7 : ITEMS + ITEMS / 2;
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];
@@ -615,6 +618,9 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
         }
     }
     if (vec == kMttkrpVec) {
+        if (items == 5)  // col_tile 32 only
+            return lanes == 8 ? go(k_mttkrp_vec<8, 5, kMttkrpVec, V, FT, float, PosT>)
+                              : hipErrorInvalidValue;
         if (items != 8 && items != 4) return hipErrorInvalidValue;
         if (items == 4) {
             if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT>);
@@ -629,6 +635,8 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
         // 16-byte BF16 lanes: chunks of at most 256 merged items (lanes x
         // items >= 32), as the one-item-per-thread staging needs
         if (vec == kMttkrpVecWide) {
+            if (lanes == 4 && items == 3)
+                return go(k_mttkrp_vec<4, 3, kMttkrpVecWide, V, FT, float, PosT>);
             if (lanes == 4 && items == 4)
                 return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float, PosT>);
             if (lanes == 8 && items == 4)

@@ -40,7 +40,11 @@ SPMM_BF16_CANDIDATES: List[Dict] = (
 
 
 MTTKRP_CANDIDATES: List[Dict] = [
-    # 4 items per lane group: the 4-column-lane leaf only (R and every ld
+    # items per lane group left to the library (5 with 4-column FP32 lanes, 3
+    # with 8-column BF16 lanes), at two tile sizes
+    dict(kind="merge", tile=512, col_tile=32),
+    dict(kind="merge", tile=768, col_tile=32),
+    # 4 items per lane group: the vector-lane leaves only (R and every ld
     # multiples of 4); more waves per SIMD than with 8
     dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
     dict(kind="merge", tile=1024, col_tile=32, items_per_lane=4),

@@ -31,10 +31,15 @@ MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=
                     dict(kind="nnz", tile=700, col_tile=32, items_per_lane=8),
                     dict(kind="merge", tile=2048, col_tile=32, items_per_lane=8),
                     dict(kind="merge", tile=512, col_tile=32, items_per_lane=8, variant=1)]
-# 4 items per lane group: the 4-column-lane leaf only (R and every ld multiples of 4)
+# 4 items per lane group: the 4-column-lane leaf only (R and every ld multiples
+# of 4); 5 items: 4-column lanes at col_tile 32 only; col_tile 32 with items
+# and tile left to the library (5 items, tile 512 with 4-column lanes)
 MTTKRP_VEC4 = [dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
                dict(kind="merge", tile=1, col_tile=64, items_per_lane=4),
-               dict(kind="merge", tile=3000, col_tile=32, items_per_lane=4)]
+               dict(kind="merge", tile=3000, col_tile=32, items_per_lane=4),
+               dict(kind="merge", tile=512, col_tile=32, items_per_lane=5),
+               dict(kind="merge", tile=1, col_tile=32, items_per_lane=5),
+               dict(kind="merge", col_tile=32)]
 # merge tiles of 2048 and 5000 items give the vector-ALU leaves several chunks
 # per workgroup (their default is one)
 SDDMM_SCHEDULES = [dict(kind="default"), dict(kind="nnz", tile=300), dict(kind="row", tile=7),
@@ -106,7 +111,7 @@ def test_mttkrp(dtype, R):
         D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
         ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
                                host64(C), host64(D))
-        staged = [dict(sc, variant=3) for sc in MTTKRP_VEC4 if sc["items_per_lane"] == 4] \
+        staged = [dict(sc, variant=3) for sc in MTTKRP_VEC4 if sc.get("items_per_lane") == 4] \
             if dtype == torch.float32 and R % 4 == 0 else []
         for sc in MTTKRP_SCHEDULES + (MTTKRP_VEC4 if R % 4 == 0 else []) + staged:
             A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
@@ -115,6 +120,17 @@ def test_mttkrp(dtype, R):
         if R % 4:
             with pytest.raises(spl.SpleafError, match="items_per_lane 4"):
                 spl.mttkrp(B, C, D, sched=spl.schedule(**MTTKRP_VEC4[0]))
+            with pytest.raises(spl.SpleafError, match="items_per_lane 5"):
+                spl.mttkrp(B, C, D, sched=spl.schedule(**MTTKRP_VEC4[3]))
+        else:
+            # 5 items need col_tile 32; 3 items need 8-column BF16 lanes
+            with pytest.raises(spl.SpleafError, match="items_per_lane 5"):
+                spl.mttkrp(B, C, D, sched=spl.schedule(kind="merge", col_tile=64,
+                                                       items_per_lane=5))
+            if dtype == torch.float32:
+                with pytest.raises(spl.SpleafError, match="items_per_lane 3"):
+                    spl.mttkrp(B, C, D, sched=spl.schedule(kind="merge", col_tile=32,
+                                                           items_per_lane=3))
 
 
 def test_mttkrp_integer_values_bit_exact():
@@ -127,11 +143,15 @@ def test_mttkrp_integer_values_bit_exact():
     ref, _ = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], c["vals"],
                            host64(C), host64(D))
     for sc in MTTKRP_SCHEDULES + MTTKRP_VEC4 + [dict(sc, variant=3) for sc in MTTKRP_VEC4
-                                                if sc["items_per_lane"] == 4]:
+                                                if sc.get("items_per_lane") == 4]:
         A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
         assert np.array_equal(host64(A), ref), sc
 
 
+# 3 items: 8-column BF16 lanes at col_tile 32 only (R and every ld multiples of 8)
+MTTKRP_BF16_ITEMS3 = [dict(kind="merge", tile=512, col_tile=32, items_per_lane=3),
+                      dict(kind="merge", tile=1, col_tile=32, items_per_lane=3),
+                      dict(kind="merge", tile=5000, col_tile=32, items_per_lane=3)]
 MTTKRP_BF16 = MTTKRP_VEC4 + [
     dict(kind="merge", tile=256, col_tile=64, items_per_lane=8),
     dict(kind="merge", tile=4096, col_tile=64, items_per_lane=8),
@@ -163,12 +183,15 @@ def test_mttkrp_bf16_lane_widths(R):
         D = _t(Dn, torch.float64).to(torch.float32).to(torch.bfloat16)
         ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
                                host64(C), host64(D))
-        for sc in MTTKRP_BF16:
+        for sc in MTTKRP_BF16 + (MTTKRP_BF16_ITEMS3 if R % 8 == 0 else []):
             A = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
             if kind == "int":
                 assert np.array_equal(host64(A), ref), (R, sc)
             else:
                 assert_close(host64(A), ref, S, 1e-5, f"mttkrp bf16 R={R} {sc}")
+        if R % 8:
+            with pytest.raises(spl.SpleafError, match="items_per_lane 3"):
+                spl.mttkrp(B, C, D, sched=spl.schedule(**MTTKRP_BF16_ITEMS3[0]))
     with pytest.raises(spl.SpleafError, match="variant 2"):
         B32 = _csf(spl, c, torch.float32)
         spl.mttkrp(B32, C.float(), D.float(), sched=spl.schedule(**MTTKRP_BF16[-1]))
@@ -668,11 +691,17 @@ def test_mttkrp_int64_positions_match_int32(dtype):
                            host64(C), host64(D))
     scheds = [dict(kind="default"), dict(kind="merge", tile=512, col_tile=32, items_per_lane=4),
               dict(kind="merge", tile=4096, col_tile=32, items_per_lane=4),
-              dict(kind="merge", tile=1, col_tile=64, items_per_lane=8)]
+              dict(kind="merge", tile=1, col_tile=64, items_per_lane=8),
+              dict(kind="merge", tile=700, col_tile=32, items_per_lane=5)]
     if dtype == torch.bfloat16:
         scheds.append(dict(kind="merge", tile=700, col_tile=32, items_per_lane=4, variant=2))
+        scheds.append(dict(kind="merge", tile=300, col_tile=32, items_per_lane=3))
     for sc in scheds:
-        a32 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc))
+        # by default FP32 takes 5 items with int32 positions and 4 with
+        # int64: the int64 default walks as the int32 leaf with 4 items
+        sc32 = dict(kind="merge", tile=512, col_tile=32, items_per_lane=4) \
+            if sc["kind"] == "default" and dtype == torch.float32 else sc
+        a32 = spl.mttkrp(B, C, D, sched=spl.schedule(**sc32))
         a64 = spl.mttkrp(B64, C, D, sched=spl.schedule(**sc))
         assert torch.equal(a32, a64), (dtype, sc)
         assert_close(host64(a64), ref, S, 1e-5, f"int64 mttkrp {dtype} {sc}")
