@@ -199,8 +199,9 @@ def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
 # longer merge tiles (several chunks per workgroup), which short fibers favour
 def _ttv_candidates():
     from paper_2207_13901_amd import tuning
-    return tuning.SPMV_CANDIDATES + [dict(kind="merge", tile=T, items_per_lane=it)
-                                     for T, it in ((4096, 4), (16384, 4), (8192, 8), (32768, 8))]
+    return tuning.SPMV_CANDIDATES + [dict(kind="merge", tile=T, items_per_lane=it, variant=v)
+                                     for T, it in ((4096, 4), (16384, 4), (8192, 8), (32768, 8))
+                                     for v in (0, 2)]
 
 
 TTV_CANDIDATES = _ttv_candidates()

@@ -261,10 +261,13 @@ spl_status spl_probe(spl_context *ctx, int kind, const void *buf, int64_t bytes,
  * adds the other tiles' F64 carries to that value and rounds a second
  * time).  Schedules: ROW,
  * NNZ, MERGE (default MERGE), and SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE
- * (below).  sched->variant (MERGE only; both walk chunks of
+ * (below).  sched->variant (MERGE only; all walk chunks of
  * 256 * items_per_lane merged items): 0 = the row ends are staged as flags
  * in the merged sequence and each lane's start comes from a count (default);
- * 1 = each lane finds its start by a merge-path search over the row ends.
+ * 1 = each lane finds its start by a merge-path search over the row ends;
+ * 2 = each lane sums whole rows of the chunk from its staged products (rows
+ * of more than 32 positions in the chunk by a wave each), the open row by
+ * the workgroup -- for short rows such as CSF fibers (int32 positions only).
  * Kinds
  * SPL_SCHED_LEARNED / SPL_SCHED_AUTOTUNE are resolved first to one of the
  * candidates (which synchronizes on

@@ -180,10 +180,12 @@ spl_status resolve_spmv(spl_context *ctx, const spl_sparse *B, const spl_schedul
     if (!pow2_in(p.lanes, 1, 64)) return fail(ctx, SPL_ERR_ARG, "lanes_per_row must be 1..64, power of 2");
     p.items = s->items_per_lane ? s->items_per_lane : 8;
     if (p.items != 4 && p.items != 8) return fail(ctx, SPL_ERR_ARG, "SpMV items_per_lane must be 4 or 8");
-    if (s->variant != 0 && s->variant != 1)
-        return fail(ctx, SPL_ERR_ARG, "SpMV variant must be 0 (row-end flags) or 1 (row-end search)");
+    if (s->variant < 0 || s->variant > 2)
+        return fail(ctx, SPL_ERR_ARG,
+                    "SpMV variant must be 0 (row-end flags), 1 (row-end search) or 2 (whole rows "
+                    "per lane)");
     if (s->variant != 0 && p.kind != SPL_MERGE)
-        return fail(ctx, SPL_ERR_ARG, "SpMV variant 1 needs the MERGE schedule");
+        return fail(ctx, SPL_ERR_ARG, "SpMV variants 1 and 2 need the MERGE schedule");
     p.variant = s->variant;
     p.tile = s->tile ? s->tile : (p.kind == SPL_ROW ? 256 / p.lanes : spmv_chunk(p));
     if (p.tile < 1) return fail(ctx, SPL_ERR_ARG, "tile must be positive");

@@ -629,6 +629,126 @@ __global__ __launch_bounds__(kBlock) void k_spmv_flag(
     if (tid == 0) carry[blockIdx.x] = open;
 }
 
+// Merge-split leaf that sums whole rows per lane (schedule variant 2).  The
+// same pieces and carries as k_spmv_flag, without a scan: per chunk the
+// products vals[p] * c[crd[p]] of its positions and the ends of its rows
+// (relative to the chunk's first position) are staged in LDS with
+// coalesced loads; lane t then sums rows t, t + 256, ... of the chunk from
+// LDS in position order and writes them, and the row still open at the end
+// of the chunk is summed by the workgroup (lane-strided partials, then a
+// fixed tree).  A row with more than kLongRow positions in the chunk is
+// queued and summed by one wave (lane-strided partials and a butterfly),
+// so one long row does not serialize its lane.  For rows of one or two
+// positions (the fibers of a CSF tensor) this costs a fraction of the flag
+// walk's instructions: one LDS read and add per position, no segmented
+// scan and two barriers per chunk.  Every order is fixed, so the result is
+// reproducible; sums are in double as in the other leaves.
+constexpr int kLongRow = 32;
+
+template <typename V, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_spmv_rows(
+    int64_t n, const int32_t *__restrict__ pos, const int32_t *__restrict__ crd,
+    const V *__restrict__ vals, const V *__restrict__ x, V *__restrict__ y,
+    const int32_t *__restrict__ trow, const int32_t *__restrict__ tpos, int64_t npieces,
+    int64_t stride, double *__restrict__ carry) {
+    constexpr int kChunk = kBlock * ITEMS;
+    constexpr int kWaves = kBlock / kWave;
+    __shared__ double s_prod[kChunk];
+    __shared__ int32_t s_end[kChunk];
+    __shared__ int32_t s_long[kChunk / (kLongRow + 1) + 1];
+    __shared__ int s_nlong;
+    __shared__ double s_red[kWaves];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * stride;
+    const int64_t pend = p0 + stride < npieces ? p0 + stride : npieces;
+    double open = 0.0;
+    if (tid == 0) s_nlong = 0;
+    // two chunks ahead: the coordinates, values and row ends of chunk c + 2
+    // are loaded and the c gathers of chunk c + 1 issued while chunk c is
+    // summed
+    int32_t k2[ITEMS], e2[ITEMS], e1[ITEMS];
+    V v2[ITEMS], v1[ITEMS], x1[ITEMS];
+    int np2 = 0;  // positions of the loaded chunk
+    auto load = [&](int64_t cc) {
+        const int64_t li0 = trow[cc], lp0 = tpos[cc];
+        const int lnr = static_cast<int>(trow[cc + 1] - li0);
+        const int lnp = static_cast<int>(tpos[cc + 1] - lp0);
+        np2 = lnp;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            k2[j] = k < lnp ? load_stream(crd + lp0 + k) : 0;
+            v2[j] = k < lnp ? load_stream(vals + lp0 + k) : V(0);
+            e2[j] = k < lnr ? pos[li0 + k + 1] : 0;
+        }
+    };
+    auto gather = [&]() {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            e1[j] = e2[j];
+            v1[j] = v2[j];
+        }
+        if (np2 > 0) {  // lanes past the positions gather c[0]
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) x1[j] = x[k2[j]];
+        }
+    };
+    if (p0 < pend) {
+        load(p0);
+        gather();
+        if (p0 + 1 < pend) load(p0 + 1);
+    }
+    for (int64_t c = p0; c < pend; ++c) {
+        const int64_t bi0 = trow[c], bp0 = tpos[c];
+        const int nr = static_cast<int>(trow[c + 1] - bi0);
+        const int np = static_cast<int>(tpos[c + 1] - bp0);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = tid + j * kBlock;
+            if (k < np) s_prod[k] = to_f64(v1[j]) * to_f64(x1[j]);
+            if (k < nr) s_end[k] = static_cast<int32_t>(e1[j] - bp0);
+        }
+        if (c + 1 < pend) {
+            gather();
+            if (c + 2 < pend) load(c + 2);
+        }
+        __syncthreads();
+        for (int k = tid; k < nr; k += kBlock) {
+            const int b = k ? s_end[k - 1] : 0, e = s_end[k];
+            if (e - b > kLongRow) {
+                s_long[atomicAdd(&s_nlong, 1)] = k;
+                continue;
+            }
+            double acc = k ? 0.0 : open;
+            for (int q = b; q < e; ++q) acc += s_prod[q];
+            store_stream(y + bi0 + k, static_cast<V>(acc));
+        }
+        // the row open at the chunk's end
+        const int t0 = nr ? s_end[nr - 1] : 0;
+        double part = 0.0;
+        for (int q = t0 + tid; q < np; q += kBlock) part += s_prod[q];
+        part = group_sum<kWave>(part);
+        if (lane == 0) s_red[wave] = part;
+        __syncthreads();  // the tail partials and the long-row queue
+        double tail = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) tail += s_red[w];
+        const int nlong = s_nlong;
+        for (int u = wave; u < nlong; u += kWaves) {
+            const int k = s_long[u];
+            const int b = k ? s_end[k - 1] : 0, e = s_end[k];
+            double acc = 0.0;
+            for (int q = b + lane; q < e; q += kWave) acc += s_prod[q];
+            acc = group_sum<kWave>(acc);
+            if (lane == 0) store_stream(y + bi0 + k, static_cast<V>(k ? acc : open + acc));
+        }
+        open = nr ? tail : open + tail;
+        __syncthreads();  // the chunk's LDS is read before the next one overwrites it
+        if (tid == 0) s_nlong = 0;
+    }
+    if (tid == 0) carry[blockIdx.x] = open;
+}
+
 // Merge-split leaf over position windows: row i contributes its positions
 // [begin[i], end[i]) (the windows of one color of a coordinate-value
 // partition).  The rows and the window positions are merged as for a CSR
@@ -758,6 +878,15 @@ hipError_t spmv_tiles_dispatch(int items, int64_t n, const int32_t *pos, const i
                                const V *vals, const V *x, V *y, const Tiles &t, int64_t stride,
                                bool exact, int variant, double *carry, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(ceil_div(t.ntiles, stride)));
+    if (exact && variant == 2) {
+        if (items <= 4)
+            k_spmv_rows<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        else
+            k_spmv_rows<V, 8><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,
+                                                       t.ntiles, stride, carry);
+        return hipGetLastError();
+    }
     if (exact && variant == 0) {
         if (items <= 4)
             k_spmv_flag<V, 4><<<grid, kBlock, 0, s>>>(n, pos, crd, vals, x, y, t.row, t.pos,

@@ -157,6 +157,9 @@ def test_config4_csf_ops():
     A = spl.spttv(B, cv)
     ref, S = oracle.spttv(h["pos1"], h["pos2"], h["crd2"], host64(vals32), host64(cv))
     assert_close(host64(A), ref, S, 1e-5, "spttv full size")
+    # whole fibers per lane (schedule variant 2)
+    A = spl.spttv(B, cv, sched=spl.schedule("merge", tile=8192, items_per_lane=8, variant=2))
+    assert_close(host64(A), ref, S, 1e-5, "spttv full size, whole fibers per lane")
     del A, ref, S
     # the fiber-aligned non-zero split bounds on sampled tiles, each checked
     # by the oracle's preimage counts (the fiber holding position t*T, the

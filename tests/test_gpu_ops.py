@@ -21,7 +21,10 @@ pytestmark = pytest.mark.gpu
 TTV_SCHEDULES = [dict(kind="default"), dict(kind="row", lanes_per_row=2),
                  dict(kind="nnz", tile=500), dict(kind="merge", tile=4096, items_per_lane=4),
                  dict(kind="merge", tile=20000, items_per_lane=8), dict(kind="merge", variant=1),
-                 dict(kind="merge", tile=5000, items_per_lane=4, variant=1)]
+                 dict(kind="merge", tile=5000, items_per_lane=4, variant=1),
+                 dict(kind="merge", variant=2),
+                 dict(kind="merge", tile=20000, items_per_lane=8, variant=2),
+                 dict(kind="merge", tile=3000, items_per_lane=4, variant=2)]
 MTTKRP_SCHEDULES = [dict(kind="default"), dict(kind="merge", tile=128, col_tile=32, items_per_lane=8),
                     dict(kind="nnz", tile=300), dict(kind="nnz", tile=4096, col_tile=16),
                     dict(kind="row", tile=3), dict(kind="merge", tile=5000, col_tile=64,

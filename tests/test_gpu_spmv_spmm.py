@@ -30,6 +30,10 @@ SCHEDULES_SPMV = [
     dict(kind="merge", variant=1), dict(kind="merge", tile=1024, items_per_lane=4, variant=1),
     dict(kind="merge", tile=9000, items_per_lane=8, variant=1),
     dict(kind="merge", tile=7777, items_per_lane=4, variant=1),
+    # whole rows per lane (long rows by a wave): one chunk, several, ragged
+    dict(kind="merge", variant=2), dict(kind="merge", tile=1024, items_per_lane=4, variant=2),
+    dict(kind="merge", tile=9000, items_per_lane=8, variant=2),
+    dict(kind="merge", tile=7777, items_per_lane=4, variant=2),
 ]
 SCHEDULES_SPMM = [
     dict(kind="row", col_tile=32), dict(kind="row", col_tile=8),
@@ -152,7 +156,7 @@ def test_spmv_int64_positions(dtype):
             assert_close(host64(y), ref, S, RTOL[dtype], f"int64 pos {shape} {sc}")
     x = torch.ones(B64.shape[1], dtype=dtype, device=dev())
     for bad in (dict(kind="row"), dict(kind="nnz"), dict(kind="merge", variant=1),
-                dict(kind="learned")):
+                dict(kind="merge", variant=2), dict(kind="learned")):
         with pytest.raises(spl.SpleafError, match="UNSUPPORTED"):
             spl.spmv(B64, x, sched=spl.schedule(**bad))
     # SpMM takes int64 positions with vector lanes only: 5 columns give none
@@ -376,7 +380,7 @@ def test_host_errors_reported():
         spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                  sched=spl.schedule("row", lanes_per_row=3))
     for bad in (dict(kind="nnz", variant=1), dict(kind="row", variant=1),
-                dict(kind="merge", variant=2)):
+                dict(kind="nnz", variant=2), dict(kind="merge", variant=3)):
         with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
             spl.spmv(B, torch.ones(10, dtype=torch.float64, device=dev()),
                      sched=spl.schedule(**bad))
