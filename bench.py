@@ -22,7 +22,8 @@ Besides the headline line it reports, from the same run:
  - variants: FP64 SpMV/SpMM and BF16 SpMM (FP32 accumulation) with the same
    schedules, and the row / non-zero / merge schedules compared;
  - ops: every other leaf at its full workload, and the SpMV of the paper's
-   weak-scaling study at one GPU's share (banded, 7e8 nonzeros, FP64);
+   weak-scaling study at one GPU's share (banded, 7e8 nonzeros, FP64),
+   each warm (median, min, max) and with the MALL flushed (cold_ms);
  - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 10]
@@ -102,10 +103,53 @@ def algorithmic_bytes(n, m, nnz, N, vbytes, dbytes, obytes):
     return spmv, spmm
 
 
-def _rate(ms, nbytes, flops):
-    return {"ms": round(ms, 5), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
-            "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
+def tuning_median(fn, reps, warmup):
+    from paper_2207_13901_amd import tuning
+    return tuning.time_call(fn, reps=reps, warmup=warmup)
+
+
+def _rate(ms, nbytes, flops, spread=None):
+    out = {"ms": round(ms, 5), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "GFLOP_s": round(flops / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": int(nbytes)}
+    if spread:
+        out.update(spread)
+        out["cold_frac_hbm"] = round(nbytes / (spread["cold_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+_FLUSH = []
+_COLD = [True]  # --no-cold clears it
+
+
+def _time_ops(fn, reps=10, warmup=3):
+    """Median milliseconds of fn() back to back (warm), plus min / max and the
+    median with the 256 MB MALL flushed by a 1 GiB write before each call
+    (cold; the write itself is not timed)."""
+    import torch
+    if not _COLD[0]:
+        return tuning_median(fn, reps, warmup), None
+    if not _FLUSH:
+        _FLUSH.append(torch.empty(1 << 28, dtype=torch.float32, device="cuda"))
+    flush = _FLUSH[0]
+
+    def once(cold):
+        if cold:
+            flush.fill_(1.0)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    for _ in range(warmup):
+        fn()
+    warm = sorted(once(False) for _ in range(reps))
+    cold = sorted(once(True) for _ in range(reps))
+    return warm[len(warm) // 2], {"min_ms": round(warm[0], 5), "max_ms": round(warm[-1], 5),
+                                  "cold_ms": round(cold[len(cold) // 2], 5)}
 
 
 def measure_banded(dev, spl, tuning, torch):
@@ -126,8 +170,8 @@ def measure_banded(dev, spl, tuning, torch):
              [dict(kind="merge", tile=4096, items_per_lane=4, variant=1),
               dict(kind="nnz", tile=4096, items_per_lane=8)])
     best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
-    ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
-    out = _rate(ms, 4 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)
+    ms, ms_spread = _time_ops(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)))
+    out = _rate(ms, 4 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz, ms_spread)
     out.update(schedule=best, n=n, nnz=nnz,
                schedules_ms={json.dumps(c, sort_keys=True): round(t, 4) for c, t in res})
     del B, c, x, y
@@ -148,8 +192,8 @@ def measure_banded64(dev, spl, tuning, torch, n=62_000_000):
     cands = ([dict(kind="merge", tile=T, items_per_lane=4) for T in (4096, 16384)] +
              [dict(kind="merge", tile=T, items_per_lane=8) for T in (8192, 32768)])
     best, res = tuning.search(lambda s: (lambda: spl.spmv(B, x, y, sched=s)), cands, reps=3)
-    ms = tuning.time_call(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)), reps=10, warmup=3)
-    out = _rate(ms, 8 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz)
+    ms, ms_spread = _time_ops(lambda: spl.spmv(B, x, y, sched=spl.schedule(**best)))
+    out = _rate(ms, 8 * (n + 1) + 12 * nnz + 8 * n + 8 * n, 2 * nnz, ms_spread)
     out.update(schedule=best, n=n, nnz=nnz, pos="int64",
                schedules_ms={json.dumps(c, sort_keys=True): round(t, 4) for c, t in res})
     del B, c, x, y
@@ -171,7 +215,7 @@ def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
     bounds = torch.as_tensor(np.linspace(0, n, ncolors + 1).astype(np.int32), device=dev)
     out = torch.empty(ncolors + 1, n, dtype=torch.int32, device=dev)
     y = torch.empty(n, dtype=torch.float64, device=dev)
-    ms_p = tuning.time_call(lambda: spl.coord_partition(B, bounds, out), reps=10, warmup=3)
+    ms_p, ms_p_spread = _time_ops(lambda: spl.coord_partition(B, bounds, out))
     spl.coord_partition(B, bounds, out)
     lanes = [dict(kind="row", lanes_per_row=L) for L in (1, 2, 4, 8)] + \
         [dict(kind="merge", tile=T, items_per_lane=it)
@@ -183,10 +227,11 @@ def measure_coord_partition(dev, spl, tuning, torch, ncolors=8):
 
     best, _ = tuning.search(lambda sc: (lambda: windows(sc)), lanes, reps=3)
     sb = spl.schedule(**best)
-    ms_w = tuning.time_call(lambda: windows(sb), reps=10, warmup=3)
-    res = {"partition": _rate(ms_p, 4 * (n + 1) + 4 * nnz + 4 * (ncolors + 1) * n, 0),
+    ms_w, ms_w_spread = _time_ops(lambda: windows(sb))
+    res = {"partition": _rate(ms_p, 4 * (n + 1) + 4 * nnz + 4 * (ncolors + 1) * n, 0,
+                              ms_p_spread),
            "windows_spmv_f64": _rate(ms_w, ncolors * 8 * n + 12 * nnz + 8 * n + ncolors * 8 * n,
-                                     2 * nnz)}
+                                     2 * nnz, ms_w_spread)}
     res["windows_spmv_f64"]["schedule"] = best
     res["workload"] = (f"power-law CSR {n}^2, {nnz} nnz, FP64; {ncolors} equal column blocks, "
                        f"the SpMV as the {ncolors} blocks' windowed products")
@@ -226,8 +271,8 @@ def measure_ddc(dev, spl, tuning, torch):
     best, _ = tuning.search(lambda s: (lambda: spl.spttv(B, cv, A, sched=s)),
                             TTV_CANDIDATES, reps=5)
     st = spl.schedule(**best)
-    ms = tuning.time_call(lambda: spl.spttv(B, cv, A, sched=st), reps=10, warmup=3)
-    out["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+    ms, ms_spread = _time_ops(lambda: spl.spttv(B, cv, A, sched=st))
+    out["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz, ms_spread)
     out["spttv_f32"]["schedule"] = best
     del A
     C = c["C"].to(torch.float32)
@@ -237,9 +282,9 @@ def measure_ddc(dev, spl, tuning, torch):
                             tuning.MTTKRP_CANDIDATES, reps=3)
     sk = spl.schedule(**best)
     ws = spl.workspace(spl.N.OP_MTTKRP, B, R, sk)  # holds the expanded Dense level too
-    ms = tuning.time_call(lambda: spl.mttkrp(B, C, D, M, sched=sk, ws=ws), reps=10, warmup=3)
+    ms, ms_spread = _time_ops(lambda: spl.mttkrp(B, C, D, M, sched=sk, ws=ws))
     nbytes = 4 * (F + 1) + 8 * nnz + 4 * (J + Kd) * R + 4 * I * R
-    out["mttkrp_f32"] = _rate(ms, nbytes, 2 * R * (nnz + F))
+    out["mttkrp_f32"] = _rate(ms, nbytes, 2 * R * (nnz + F), ms_spread)
     out["mttkrp_f32"]["schedule"] = best
     out["workload"] = f"(Dense, Dense, Compressed) {I}x{J}x{Kd}, {nnz} nnz, {F} fibers, R={R}"
     del B, C, D, M, c, cv, ws
@@ -255,8 +300,10 @@ def measure_other_ops(dev, spl, tuning, torch, fixed=None, next_rows=True, only=
     1,000,000-row CSR matrices, SpTTV, SpMTTKRP and the inner product on the
     200,000^3 CSF tensor with 1e8 nonzeros.  SpTTV and SpMTTKRP run with the
     autotuned schedule unless `fixed` gives one ({"spttv": {...},
-    "mttkrp": {...}}).  Median of 10 timed calls after
-    3 warm-up calls, inputs resident in HBM.  `only`: a subset of OPS."""
+    "mttkrp": {...}}).  Median (and min, max) of 10 timed calls after
+    3 warm-up calls, inputs resident in HBM, and the median of 10 calls
+    each after a 1 GiB write that flushes the MALL (cold_ms, cold_frac_hbm).
+    `only`: a subset of OPS."""
     from workloads import configs
     want = set(only) if only else set(OPS if next_rows else OPS[:5])
     res = {}
@@ -298,10 +345,10 @@ def _ops_config3(dev, spl, tuning, torch, configs, want, res):
         D = c3["Dd"].to(torch.float32).to(fdt)
         A = torch.empty(nnzB, dtype=torch.float32, device=dev)
         s = spl.schedule(variant=variant)
-        ms = tuning.time_call(lambda: spl.sddmm(B, C, D, A, sched=s), reps=10, warmup=3)
+        ms, ms_spread = _time_ops(lambda: spl.sddmm(B, C, D, A, sched=s))
         esz = 2 if fdt == torch.bfloat16 else 4
         nbytes = 4 * (n + 1) + 8 * nnzB + K * n * esz * 2 + 4 * nnzB
-        res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1))
+        res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1), ms_spread)
         del C, D, A
     if "spadd3" in want:
         # the numeric phase's input staging: 1 direct, 2 coordinates in LDS,
@@ -309,13 +356,13 @@ def _ops_config3(dev, spl, tuning, torch, configs, want, res):
         var_ms = {v: tuning.time_call(
             lambda v=v: spl.spadd3(*ops, sched=spl.schedule("row", variant=v)), reps=10, warmup=3)
             for v in (1, 2, 3)}
-        ms = tuning.time_call(lambda: spl.spadd3(*ops), reps=10, warmup=3)
+        ms, ms_spread = _time_ops(lambda: spl.spadd3(*ops))
         out = spl.spadd3(*ops)
         nnzA = out.crd.numel()
         nnzs = sum(o.crd.numel() for o in ops)
         nbytes = (3 * 4 * (n + 1) + 4 * nnzs + 4 * (n + 1)) + \
                  (3 * 4 * (n + 1) + 8 * nnzs + 4 * (n + 1) + 8 * nnzA)
-        res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA)
+        res["spadd3_f32"] = _rate(ms, nbytes, nnzs - nnzA, ms_spread)
         res["spadd3_f32"]["nnz_out"] = nnzA
         res["spadd3_f32"]["variants_ms"] = {str(v): round(t, 5) for v, t in var_ms.items()}
         del out
@@ -344,8 +391,8 @@ def _ops_config4(dev, spl, tuning, torch, configs, want, res, fixed):
             best_t, _ = tuning.search(lambda s: (lambda: spl.spttv(B32, cv, At, sched=s)),
                                         TTV_CANDIDATES, reps=5)
         st = spl.schedule(**best_t)
-        ms = tuning.time_call(lambda: spl.spttv(B32, cv, At, sched=st), reps=10, warmup=3)
-        res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz)
+        ms, ms_spread = _time_ops(lambda: spl.spttv(B32, cv, At, sched=st))
+        res["spttv_f32"] = _rate(ms, 4 * (F + 1) + 8 * nnz + 4 * Kd + 4 * F, 2 * nnz, ms_spread)
         res["spttv_f32"]["schedule"] = best_t
         del At
     mttkrp_forms = (("mttkrp_f32", torch.float32), ("mttkrp_bf16_f32acc", torch.bfloat16))
@@ -360,25 +407,25 @@ def _ops_config4(dev, spl, tuning, torch, configs, want, res, fixed):
             best_k, _ = tuning.search(lambda s: (lambda: spl.mttkrp(Bt, C, D, M, sched=s)),
                                         tuning.MTTKRP_CANDIDATES, reps=3)
         sk = spl.schedule(**best_k)
-        ms = tuning.time_call(lambda: spl.mttkrp(Bt, C, D, M, sched=sk), reps=10, warmup=3)
+        ms, ms_spread = _time_ops(lambda: spl.mttkrp(Bt, C, D, M, sched=sk))
         esz = 2 if dt == torch.bfloat16 else 4
         nbytes = 4 * (I + 1) + 4 * F + 4 * (F + 1) + (4 + esz) * nnz + esz * (J + Kd) * R + 4 * I * R
-        res[name] = _rate(ms, nbytes, 2 * R * (nnz + F))
+        res[name] = _rate(ms, nbytes, 2 * R * (nnz + F), ms_spread)
         res[name]["schedule"] = best_k
         del Bt, C, D, M
     if "inner" in want:
         B64 = B32.with_vals(c4["vals"])
         C64 = B32.with_vals(c4["vals2"])
         a = torch.empty(1, dtype=torch.float64, device=dev)
-        ms = tuning.time_call(lambda: spl.inner(B64, C64, a), reps=10, warmup=3)
-        res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz)
+        ms, ms_spread = _time_ops(lambda: spl.inner(B64, C64, a))
+        res["inner_f64"] = _rate(ms, 16 * nnz, 2 * nnz, ms_spread)
         # the co-iteration of two patterns: the same coordinates in other
         # arrays, so every fiber is looked up and every position matched
         Cg = spl.CSF(c4["pos1"].clone(), c4["crd1"].clone(), c4["pos2"].clone(),
                      c4["crd2"].clone(), c4["vals2"], (I, J, Kd))
-        ms = tuning.time_call(lambda: spl.inner(B64, Cg, a), reps=10, warmup=3)
+        ms, ms_spread = _time_ops(lambda: spl.inner(B64, Cg, a))
         res["inner_general_f64"] = _rate(
-            ms, 2 * (4 * (I + 1) + 4 * F + 4 * (F + 1) + 12 * nnz), 2 * nnz)
+            ms, 2 * (4 * (I + 1) + 4 * F + 4 * (F + 1) + 12 * nnz), 2 * nnz, ms_spread)
         del B64, C64, Cg
     del B32, c4
     torch.cuda.empty_cache()
@@ -588,7 +635,11 @@ def main():
                     help="with --ops-only: comma-separated subset of " + ",".join(OPS))
     ap.add_argument("--calibrate", action="store_true",
                     help="run a 1 GiB device copy first (counter scale reference)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="time the other leaves back to back only, without the MALL-flushed "
+                         "trials (for rocprofv3 runs whose kernel averages are the warm ones)")
     args = ap.parse_args()
+    _COLD[0] = not args.no_cold
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    f"--gpus {args.gpus} is not supported"}))

@@ -20,8 +20,10 @@
 // slice end writes acc (first finished slice and the open one go through
 // the cross-group pass and the tile carry exactly as the SpMM rows do).
 //
-// k_mttkrp_vec: the same leaf with 4 rank columns per lane (one vector access
-// per row), the D products and C rows kept in registers.
+// k_mttkrp_vec: the same leaf with 4 (FP32) or 8 (BF16) rank columns per
+// lane, one vector access per row, in 128-thread workgroups: the C rows of
+// the group's fibers go to an LDS slab, the D rows of its positions are
+// gathered a batch at a time into registers (details below).
 #include "carry.hpp"
 #include "device.hpp"
 #include "internal.hpp"

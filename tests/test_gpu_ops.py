@@ -136,6 +136,31 @@ def test_mttkrp(dtype, R):
                                                            items_per_lane=3))
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_mttkrp_caller_workspace_from_query(dtype):
+    # the query cannot see the lane width (it depends on the factors'
+    # pointers) and takes the largest size over the widths: a workspace of
+    # exactly that size serves every schedule, including the defaults that
+    # pick items and tile with the lane width
+    spl = _spl()
+    c = _numpy(configs.config4(scale=0.001, R=32))
+    B = _csf(spl, c, dtype)
+    C = _t(c["C"], torch.float64).to(torch.float32).to(dtype)
+    D = _t(c["D"], torch.float64).to(torch.float32).to(dtype)
+    ref, S = oracle.mttkrp(c["pos1"], c["crd1"], c["pos2"], c["crd2"], host64(B.vals),
+                           host64(C), host64(D))
+    scheds = [None, dict(kind="merge", col_tile=32), dict(kind="merge", tile=1, col_tile=32),
+              dict(kind="merge", tile=1, col_tile=32, items_per_lane=4),
+              dict(kind="nnz", tile=300), dict(kind="merge", tile=1, col_tile=64, items_per_lane=8)]
+    scheds.append(dict(kind="merge", tile=1, col_tile=32, items_per_lane=3) if dtype == torch.bfloat16
+                  else dict(kind="merge", tile=1, col_tile=32, items_per_lane=5))
+    for sc in scheds:
+        sched = spl.schedule(**sc) if sc else None
+        ws = spl.workspace(N.OP_MTTKRP, B, 32, sched)
+        A = spl.mttkrp(B, C, D, sched=sched, ws=ws)
+        assert_close(host64(A), ref, S, 1e-5, f"mttkrp caller workspace {dtype} {sc}")
+
+
 def test_mttkrp_integer_values_bit_exact():
     spl = _spl()
     c = _tiny_csf(6, kind="int")
