@@ -1475,6 +1475,9 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
     B = &bv;
     const Pieces q = mttkrp_pieces(B, p);
     Carved cv = carve(wp, q.count);
+    const size_t fb = dtype_bytes(C->dtype);
+    const bool buf = spl::mttkrp_buf(B->nnz, dtype_bytes(B->vtype), B->dims[1], C->ld, B->dims[2],
+                                     D->ld, fb);
     if (pos64) {
         // slice ends are fiber indices (below 2^31): int32 tile bounds
         const int64_t *pos1 = reinterpret_cast<const int64_t *>(B->pos[1]);
@@ -1482,7 +1485,7 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
         SPL_HIP(spl::launch_merge_bounds64_32(I, pos1, B->nfibers, q.size, cv.tiles, s),
                 "tile bounds launch");
         LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
-        SPL_HIP(spl::launch_mttkrp_tiles64(B->vtype, p.col_tile, p.items, p.vec, I, R, pos1,
+        SPL_HIP(spl::launch_mttkrp_tiles64(B->vtype, buf, p.col_tile, p.items, p.vec, I, R, pos1,
                                            B->crd[1], pos2, B->crd[2], B->vals, C->data, C->ld,
                                            D->data, D->ld, static_cast<float *>(A->data), A->ld,
                                            cv.tiles, q.stride, static_cast<float *>(cv.carry), s),
@@ -1501,7 +1504,7 @@ spl_status spl_mttkrp(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
         SPL_HIP(spl::launch_tile_bounds(p.kind, I, B->pos[1], B->nfibers, q.size, cv.tiles, s),
                 "tile bounds launch");
     LeafTimer tm(ctx, SPL_OP_MTTKRP, s);
-    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, p.variant == 3, p.col_tile, p.items, p.vec, I, R,
+    SPL_HIP(spl::launch_mttkrp_tiles(B->vtype, buf, p.variant == 3, p.col_tile, p.items, p.vec, I, R,
                                      B->pos[1], B->crd[1],
                                      B->pos[2], B->crd[2], B->vals, C->data, C->ld, D->data,
                                      D->ld, static_cast<float *>(A->data), A->ld, cv.tiles,

@@ -238,7 +238,8 @@ __device__ __forceinline__ int32_t rel_pos(PosT p, int64_t base) {
 }
 
 template <int W, int ITEMS, int VEC, typename V, typename FT, typename Acc,
-          typename PosT = int32_t, bool STAGE = sizeof(FT) == 2, int NT = kMttkrpThreads>
+          typename PosT = int32_t, bool STAGE = sizeof(FT) == 2, int NT = kMttkrpThreads,
+          bool BUF = true>
 __global__ __launch_bounds__(NT) void k_mttkrp_vec(
     int64_t I, int64_t R, const PosT *__restrict__ pos1, const int32_t *__restrict__ crd1,
     const PosT *__restrict__ pos2, const int32_t *__restrict__ crd2,
@@ -362,34 +363,96 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
         // every C-row and D-row gather of the group before any is used
         // (BF16 rows stay packed until they are read)
         RowVec<VEC, FT> cv[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            cv[k].zero();
-            if (b0 + k < b1 && colok) cv[k].load(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0);
-        }
         int kq[kPosCap];
         Acc vq[kPosCap];
+        RowVec<VEC, FT> dv[kPosCap];
         // the group's first position within the chunk (staged positions)
         const int64_t rel0 = kStage ? P0 - s_fp[0] : 0;
+        // BUF: every load below is issued by every lane (buffer descriptors
+        // over the chunk's positions, relative to its first one, and over
+        // the factors; a lane with nothing to load reads 0 at kBufOut), so a
+        // batch's gathers are all in flight at once.  The host takes this
+        // form when the positions and both factors span at most kBufRange
+        // bytes.
+        const int32_t cp0 = BUF ? __builtin_amdgcn_readfirstlane(static_cast<int32_t>(s_fp[0])) : 0;
+        const int32_t cpn =
+            BUF ? __builtin_amdgcn_readfirstlane(static_cast<int32_t>(s_fp[nf])) - cp0 : 0;
+        const auto rK = span_rsrc(kcrd + cp0, static_cast<uint32_t>(cpn) * 4u);
+        const auto rV = span_rsrc(kval + cp0, static_cast<uint32_t>(cpn) * static_cast<uint32_t>(sizeof(V)));
+        const auto rC = span_rsrc(C, kBufRange);
+        const auto rD = span_rsrc(D, kBufRange);
+        constexpr uint32_t kFs = sizeof(FT), kVs = sizeof(V);
+        // positions q0 .. q0 + kPosCap - 1 of the group: coordinates, values
+        // (a staged position from LDS, selected per position: separate
+        // arrays for the LDS values cost a wave per SIMD)
+        auto load_pos = [&](int q0) {
 #pragma unroll
-        for (int q = 0; q < kPosCap; ++q) {
-            kq[q] = 0;
-            vq[q] = 0;
-            if (q < np) {
-                if (kStage && rel0 + q < kStagePos) {
-                    kq[q] = s_kq[rel0 + q];
-                    vq[q] = s_vq[rel0 + q];
-                } else {
-                    kq[q] = load_stream(kcrd + P0 + q);
-                    vq[q] = widen<Acc>(load_stream(kval + P0 + q));
+            for (int q = 0; q < kPosCap; ++q) {
+                const int qq = q0 + q;
+                const bool ok = qq < np;
+                const bool staged = kStage && rel0 + qq < kStagePos;
+                const uint32_t rel = static_cast<uint32_t>(P0 - cp0 + qq);
+                int k = static_cast<int>(buf_u32(rK, ok && !staged ? 4u * rel : kBufOut));
+                Acc v = buf_val(kval, rV, ok && !staged ? kVs * rel : kBufOut);
+                if constexpr (kStage) {
+                    const int si = static_cast<int>(rel0 + qq < kStagePos ? rel0 + qq : kStagePos - 1);
+                    const int ksv = s_kq[si];
+                    const Acc vsv = s_vq[si];
+                    k = ok && staged ? ksv : k;
+                    v = ok && staged ? vsv : v;
+                }
+                kq[q] = k;
+                vq[q] = v;
+            }
+        };
+        auto gather_d = [&](int q0) {
+#pragma unroll
+            for (int q = 0; q < kPosCap; ++q) {
+                const bool ok = q0 + q < np && colok;
+                dv[q].load_buf(rD, ok ? kFs * (static_cast<uint32_t>(kq[q]) *
+                                                   static_cast<uint32_t>(ldd) +
+                                               static_cast<uint32_t>(col0))
+                                      : kBufOut);
+            }
+        };
+        if constexpr (BUF) {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const bool ok = b0 + k < b1 && colok;
+                const int jj = s_j[b0 + k < kChunk ? b0 + k : kChunk - 1];
+                cv[k].load_buf(rC, ok ? kFs * (static_cast<uint32_t>(jj) *
+                                                   static_cast<uint32_t>(ldc) +
+                                               static_cast<uint32_t>(col0))
+                                      : kBufOut);
+            }
+            load_pos(0);
+            gather_d(0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                cv[k].zero();
+                if (b0 + k < b1 && colok)
+                    cv[k].load(C + static_cast<int64_t>(s_j[b0 + k]) * ldc + col0);
+            }
+#pragma unroll
+            for (int q = 0; q < kPosCap; ++q) {
+                kq[q] = 0;
+                vq[q] = 0;
+                if (q < np) {
+                    if (kStage && rel0 + q < kStagePos) {
+                        kq[q] = s_kq[rel0 + q];
+                        vq[q] = s_vq[rel0 + q];
+                    } else {
+                        kq[q] = load_stream(kcrd + P0 + q);
+                        vq[q] = widen<Acc>(load_stream(kval + P0 + q));
+                    }
                 }
             }
-        }
-        RowVec<VEC, FT> dv[kPosCap];
 #pragma unroll
-        for (int q = 0; q < kPosCap; ++q) {
-            dv[q].zero();
-            if (q < np && colok) dv[q].load(D + static_cast<int64_t>(kq[q]) * ldd + col0);
+            for (int q = 0; q < kPosCap; ++q) {
+                dv[q].zero();
+                if (q < np && colok) dv[q].load(D + static_cast<int64_t>(kq[q]) * ldd + col0);
+            }
         }
         // the next chunk's staging, when it is a whole piece (no search):
         // issued after this chunk's gathers, it lands while they are used
@@ -460,25 +523,31 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
         // registers: every batch issues all its position loads, then all its
         // D-row gathers, then walks them
         for (int q0 = kPosCap; q0 < np; q0 += kPosCap) {
+            if constexpr (BUF) {
+                load_pos(q0);
+                gather_d(q0);
+            } else {
 #pragma unroll
-            for (int q = 0; q < kPosCap; ++q) {
-                kq[q] = 0;
-                vq[q] = 0;
-                if (q0 + q < np) {
-                    const int64_t qq = q0 + q;
-                    if (kStage && rel0 + qq < kStagePos) {
-                        kq[q] = s_kq[rel0 + qq];
-                        vq[q] = s_vq[rel0 + qq];
-                    } else {
-                        kq[q] = load_stream(kcrd + P0 + qq);
-                        vq[q] = widen<Acc>(load_stream(kval + P0 + qq));
+                for (int q = 0; q < kPosCap; ++q) {
+                    kq[q] = 0;
+                    vq[q] = 0;
+                    if (q0 + q < np) {
+                        const int64_t qq = q0 + q;
+                        if (kStage && rel0 + qq < kStagePos) {
+                            kq[q] = s_kq[rel0 + qq];
+                            vq[q] = s_vq[rel0 + qq];
+                        } else {
+                            kq[q] = load_stream(kcrd + P0 + qq);
+                            vq[q] = widen<Acc>(load_stream(kval + P0 + qq));
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int q = 0; q < kPosCap; ++q) {
-                dv[q].zero();
-                if (q0 + q < np && colok) dv[q].load(D + static_cast<int64_t>(kq[q]) * ldd + col0);
+                for (int q = 0; q < kPosCap; ++q) {
+                    dv[q].zero();
+                    if (q0 + q < np && colok)
+                        dv[q].load(D + static_cast<int64_t>(kq[q]) * ldd + col0);
+                }
             }
 #pragma unroll
             for (int q = 0; q < kPosCap; ++q) {
@@ -592,8 +661,8 @@ __global__ __launch_bounds__(kBlock) void k_inner_final(int64_t nparts,
     if (threadIdx.x == 0) *out = s[0];
 }
 
-template <typename V, typename FT, typename PosT = int32_t>
-hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I, int64_t R,
+template <typename V, typename FT, typename PosT, bool BUF>
+hipError_t mttkrp_types_b(bool stage, int col_tile, int items, int vec, int64_t I, int64_t R,
                         const PosT *pos1, const int32_t *crd1, const PosT *pos2,
                         const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
                         const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
@@ -614,23 +683,23 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
     if constexpr (sizeof(FT) == 4) {
         // FP32 with the chunk's leading positions staged in LDS as for BF16
         if (stage && vec == kMttkrpVec && items == 4) {
-            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT, true>);
-            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float, PosT, true>);
+            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT, true, kMttkrpThreads, BUF>);
+            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float, PosT, true, kMttkrpThreads, BUF>);
             return hipErrorInvalidValue;
         }
     }
     if (vec == kMttkrpVec) {
         if (items == 5)  // col_tile 32 only
-            return lanes == 8 ? go(k_mttkrp_vec<8, 5, kMttkrpVec, V, FT, float, PosT>)
+            return lanes == 8 ? go(k_mttkrp_vec<8, 5, kMttkrpVec, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>)
                               : hipErrorInvalidValue;
         if (items != 8 && items != 4) return hipErrorInvalidValue;
         if (items == 4) {
-            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT>);
-            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float, PosT>);
+            if (lanes == 8) return go(k_mttkrp_vec<8, 4, kMttkrpVec, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
+            if (lanes == 16) return go(k_mttkrp_vec<16, 4, kMttkrpVec, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
             return hipErrorInvalidValue;
         }
-        if (lanes == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVec, V, FT, float, PosT>);
-        if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float, PosT>);
+        if (lanes == 8) return go(k_mttkrp_vec<8, 8, kMttkrpVec, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
+        if (lanes == 16) return go(k_mttkrp_vec<16, 8, kMttkrpVec, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
         return hipErrorInvalidValue;
     }
     if constexpr (sizeof(FT) == 2) {
@@ -638,13 +707,13 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
         // items >= 32), as the one-item-per-thread staging needs
         if (vec == kMttkrpVecWide) {
             if (lanes == 4 && items == 3)
-                return go(k_mttkrp_vec<4, 3, kMttkrpVecWide, V, FT, float, PosT>);
+                return go(k_mttkrp_vec<4, 3, kMttkrpVecWide, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
             if (lanes == 4 && items == 4)
-                return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float, PosT>);
+                return go(k_mttkrp_vec<4, 4, kMttkrpVecWide, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
             if (lanes == 8 && items == 4)
-                return go(k_mttkrp_vec<8, 4, kMttkrpVecWide, V, FT, float, PosT>);
+                return go(k_mttkrp_vec<8, 4, kMttkrpVecWide, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
             if (lanes == 8 && items == 8)
-                return go(k_mttkrp_vec<8, 8, kMttkrpVecWide, V, FT, float, PosT>);
+                return go(k_mttkrp_vec<8, 8, kMttkrpVecWide, V, FT, float, PosT, sizeof(FT) == 2, kMttkrpThreads, BUF>);
             return hipErrorInvalidValue;
         }
     }
@@ -661,7 +730,34 @@ hipError_t mttkrp_types(bool stage, int col_tile, int items, int vec, int64_t I,
     }
 }
 
+
+// BUF (buffer loads, no per-lane branches) when every position and factor
+// span fits kBufRange bytes; the branching loads otherwise
+template <typename V, typename FT, typename PosT = int32_t>
+hipError_t mttkrp_types(bool buf, bool stage, int col_tile, int items, int vec, int64_t I,
+                        int64_t R, const PosT *pos1, const int32_t *crd1, const PosT *pos2,
+                        const int32_t *crd2, const void *vals, const void *C, int64_t ldc,
+                        const void *D, int64_t ldd, float *A, int64_t lda, const Tiles &t,
+                        int64_t stride, float *carry, hipStream_t s) {
+    if (buf)
+        return mttkrp_types_b<V, FT, PosT, true>(stage, col_tile, items, vec, I, R, pos1, crd1,
+                                                 pos2, crd2, vals, C, ldc, D, ldd, A, lda, t,
+                                                 stride, carry, s);
+    return mttkrp_types_b<V, FT, PosT, false>(stage, col_tile, items, vec, I, R, pos1, crd1, pos2,
+                                              crd2, vals, C, ldc, D, ldd, A, lda, t, stride, carry,
+                                              s);
+}
+
 }  // namespace
+
+bool mttkrp_buf(int64_t nnz, size_t val_bytes, int64_t J, int64_t ldc, int64_t K, int64_t ldd,
+                size_t factor_bytes) {
+    auto fits = [](int64_t count, size_t elem) {
+        return count >= 0 && static_cast<double>(count) * static_cast<double>(elem) <= kBufRange;
+    };
+    return fits(nnz, 4) && fits(nnz, val_bytes) && fits(J * ldc, factor_bytes) &&
+           fits(K * ldd, factor_bytes);
+}
 
 hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
                                  int64_t nnz, int64_t T, const Tiles &t, hipStream_t s) {
@@ -670,30 +766,30 @@ hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, cons
     return hipGetLastError();
 }
 
-hipError_t launch_mttkrp_tiles(int vtype, bool stage, int col_tile, int items, int vec, int64_t I,
+hipError_t launch_mttkrp_tiles(int vtype, bool buf, bool stage, int col_tile, int items, int vec, int64_t I,
                                int64_t R, const int32_t *pos1, const int32_t *crd1,
                                const int32_t *pos2, const int32_t *crd2, const void *vals,
                                const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
                                int64_t lda, const Tiles &t, int64_t stride, float *carry,
                                hipStream_t s) {
     if (vtype == SPL_F32)
-        return mttkrp_types<float, float>(stage, col_tile, items, vec, I, R, pos1, crd1, pos2,
+        return mttkrp_types<float, float>(buf, stage, col_tile, items, vec, I, R, pos1, crd1, pos2,
                                           crd2, vals, C, ldc, D, ldd, A, lda, t, stride, carry, s);
-    return mttkrp_types<bf16, bf16>(stage, col_tile, items, vec, I, R, pos1, crd1, pos2, crd2,
+    return mttkrp_types<bf16, bf16>(buf, stage, col_tile, items, vec, I, R, pos1, crd1, pos2, crd2,
                                     vals, C, ldc, D, ldd, A, lda, t, stride, carry, s);
 }
 
-hipError_t launch_mttkrp_tiles64(int vtype, int col_tile, int items, int vec, int64_t I,
+hipError_t launch_mttkrp_tiles64(int vtype, bool buf, int col_tile, int items, int vec, int64_t I,
                                  int64_t R, const int64_t *pos1, const int32_t *crd1,
                                  const int64_t *pos2, const int32_t *crd2, const void *vals,
                                  const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
                                  int64_t lda, const Tiles &t, int64_t stride, float *carry,
                                  hipStream_t s) {
     if (vtype == SPL_F32)
-        return mttkrp_types<float, float, int64_t>(false, col_tile, items, vec, I, R, pos1, crd1, pos2,
+        return mttkrp_types<float, float, int64_t>(buf, false, col_tile, items, vec, I, R, pos1, crd1, pos2,
                                                    crd2, vals, C, ldc, D, ldd, A, lda, t, stride,
                                                    carry, s);
-    return mttkrp_types<bf16, bf16, int64_t>(false, col_tile, items, vec, I, R, pos1, crd1, pos2, crd2,
+    return mttkrp_types<bf16, bf16, int64_t>(buf, false, col_tile, items, vec, I, R, pos1, crd1, pos2, crd2,
                                              vals, C, ldc, D, ldd, A, lda, t, stride, carry, s);
 }
 

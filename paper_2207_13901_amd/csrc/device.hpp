@@ -143,6 +143,21 @@ struct RowVec {
         for (int k = 0; k < VEC; ++k) v[k] = 0;
     }
     __device__ __forceinline__ void load(const BT *p) { load_row<VEC>(p, v); }
+    // 16 bytes at byte offset `off` of buffer `r` (4 FP32 or 2 FP64)
+    __device__ __forceinline__ void load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        static_assert(VEC * sizeof(BT) == 16, "16-byte lanes");
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        // (__builtin_bit_cast of a vector element here compiled to a
+        // one-dword load: the integer-to-float intrinsics instead)
+        if constexpr (sizeof(BT) == 4) {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) v[k] = __uint_as_float(x[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) v[k] = __hiloint2double(x[2 * k + 1], x[2 * k]);
+        }
+    }
     __device__ __forceinline__ BT at(int k) const { return v[k]; }
 };
 template <int VEC>
@@ -168,12 +183,54 @@ struct RowVec<VEC, bf16> {
             for (int k = 0; k < 4; ++k) w[k] = x[k];
         }
     }
+    // 8 (VEC 4) or 16 (VEC 8) bytes at byte offset `off` of buffer `r`
+    __device__ __forceinline__ void load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        if constexpr (VEC == 4) {
+            typedef uint32_t vu32x2 __attribute__((ext_vector_type(2)));
+            const vu32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            w[0] = x[0];
+            w[1] = x[1];
+        } else {
+            static_assert(VEC == 8, "BF16 buffer rows: 4 or 8 per lane");
+            const vu32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = x[k];
+        }
+    }
     // element 2k sits in the low half of word k (little-endian)
     __device__ __forceinline__ float at(int k) const {
         if constexpr (VEC == 1) return __uint_as_float(w[0]);
         return __uint_as_float((k & 1) ? (w[k >> 1] & 0xffff0000u) : (w[k >> 1] << 16));
     }
 };
+
+// Buffer loads for gathers that must not branch.  A lane's load is issued
+// whether or not the lane needs it: a lane that does not passes kBufOut as
+// its offset, which lies past every descriptor range used here, so the
+// hardware's range check returns 0 without touching memory.  With no
+// per-lane branch around them, the compiler counts the loads exactly and
+// waits for each result only when it is used; a load inside a lane-masked
+// branch makes it assume the worst and wait for nearly everything before
+// the next dependent load (for a batch of gathers: one or two in flight).
+// Ranges are at most kBufRange bytes, so the offsets of every in-bounds
+// access fit 32 bits; callers keep to spans of that size.
+constexpr uint32_t kBufRange = 0xFFFFFF00u;
+constexpr uint32_t kBufOut = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
+}
+// 4-byte element at byte offset `off` (non-temporal: streamed arrays)
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2);
+}
+__device__ __forceinline__ float buf_val(const float *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+__device__ __forceinline__ float buf_val(const bf16 *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 2))
+                           << 16);
+}
 
 // Sum over aligned groups of L lanes (L a power of two <= 64) with xor
 // butterflies; every lane of the group ends with the group total.

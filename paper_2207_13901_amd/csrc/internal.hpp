@@ -101,12 +101,17 @@ hipError_t launch_dense_level(int64_t I, int64_t J, int32_t *pos, int32_t *crd, 
 // Fiber-aligned non-zero split of a CSF tensor: t.row = slice, t.pos = fiber.
 hipError_t launch_csf_nnz_bounds(int64_t I, const int32_t *pos1, int64_t F, const int32_t *pos2,
                                  int64_t nnz, int64_t T, const Tiles &t, hipStream_t s);
-// vec: 1, or 4 rank columns per lane (R, ldc, ldd, lda multiples of 4, C and D
-// aligned to 4 elements and A to 16 bytes, col_tile / 4 in {8, 16}, items
-// 8).
+// vec: 1, or 4 (8 for BF16) rank columns per lane (R, ldc, ldd, lda
+// multiples of vec, aligned factors, col_tile 32 or 64).
+// buf: the vector-lane leaf loads through buffer descriptors (mttkrp_buf
+// says when the spans allow it).
 // stage: FP32 vector lanes with 4 items stage the chunk's leading positions
 // in LDS as the BF16 leaf always does.
-hipError_t launch_mttkrp_tiles(int vtype, bool stage, int col_tile, int items, int vec, int64_t I,
+// Whether every position and factor span fits a buffer descriptor's range
+// (the vector-lane leaf's branch-free loads).
+bool mttkrp_buf(int64_t nnz, size_t val_bytes, int64_t J, int64_t ldc, int64_t K, int64_t ldd,
+                size_t factor_bytes);
+hipError_t launch_mttkrp_tiles(int vtype, bool buf, bool stage, int col_tile, int items, int vec, int64_t I,
                                int64_t R, const int32_t *pos1, const int32_t *crd1,
                                const int32_t *pos2, const int32_t *crd2, const void *vals,
                                const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
@@ -114,7 +119,7 @@ hipError_t launch_mttkrp_tiles(int vtype, bool stage, int col_tile, int items, i
                                hipStream_t s);
 // The vector-lane MTTKRP leaf over a CSF with int64 pos1/pos2 (fiber count
 // below 2^31; merge split over slices and fibers, tiles in t.row / t.pos).
-hipError_t launch_mttkrp_tiles64(int vtype, int col_tile, int items, int vec, int64_t I,
+hipError_t launch_mttkrp_tiles64(int vtype, bool buf, int col_tile, int items, int vec, int64_t I,
                                  int64_t R, const int64_t *pos1, const int32_t *crd1,
                                  const int64_t *pos2, const int32_t *crd2, const void *vals,
                                  const void *C, int64_t ldc, const void *D, int64_t ldd, float *A,
