@@ -1242,6 +1242,10 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     SPL_CHECK(get_workspace(ctx, workspace, workspace_bytes, spmm_ws(B, N, p), &ws));
     const Pieces q = pieces_for(p, n, B->nnz, spmm_chunk(p));
     Carved cv = carve(ws, q.count, pos64);
+    // branch-free row gathers when C's rows span at most a descriptor's range
+    const bool buf = static_cast<double>(C->dims[0]) * static_cast<double>(C->ld) *
+                         static_cast<double>(dtype_bytes(C->dtype)) <=
+                     spl::kBufRange;
     if (pos64) {
         const int64_t *pos = reinterpret_cast<const int64_t *>(B->pos[1]);
         SPL_HIP(spl::launch_merge_bounds64(n, pos, B->nnz, q.size, cv.tiles, s),
@@ -1249,7 +1253,7 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
         LeafTimer tm(ctx, SPL_OP_SPMM, s);
         SPL_HIP(spl::launch_spmm_tiles64(B->vtype, p.col_tile, p.items, p.vec, n, N, pos,
                                          B->crd[1], B->vals, C->data, C->ld, A->data, A->ld,
-                                         cv.tiles, q.stride, cv.carry, s),
+                                         cv.tiles, q.stride, buf, cv.carry, s),
                 "SpMM tile launch");
         tm.stop();
         SPL_HIP(spl::launch_spmm_fixup(B->vtype, n, N, cv.tiles, q.stride, cv.carry, A->data,
@@ -1262,7 +1266,7 @@ spl_status spl_spmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C, s
     LeafTimer tm(ctx, SPL_OP_SPMM, s);
     SPL_HIP(spl::launch_spmm_tiles(B->vtype, p.col_tile, p.items, p.vec, n, N, B->pos[1], B->crd[1],
                                    B->vals, C->data, C->ld, A->data, A->ld, cv.tiles, q.stride,
-                                   /*exact_chunks=*/p.kind == SPL_MERGE, cv.carry, s),
+                                   /*exact_chunks=*/p.kind == SPL_MERGE, buf, cv.carry, s),
             "SpMM tile launch");
     tm.stop();
     SPL_HIP(spl::launch_spmm_fixup(B->vtype, n, N, cv.tiles, q.stride, cv.carry, A->data, A->ld,

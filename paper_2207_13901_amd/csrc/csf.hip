@@ -252,13 +252,17 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
     static_assert(kChunk <= NT, "the chunk is staged one item per thread");
     // BF16 factors stage the chunk's leading positions in LDS (below); FP32
     // keeps more positions per group in registers instead.  Positions per
-    // batch, measured on the 1e8-nonzero tensor: FP32 4 items 7 (122 VGPRs;
-    // 6: 3.69 ms, 8: 3.75 against 3.65), 5 items 7 (128 VGPRs, still 4
-    // waves per SIMD; 6: 3.40, 8: 3.38 against 3.30); BF16 8-column lanes
-    // with 3 items 5 (3 or 4: 3.03-3.05 against 3.02)
+    // batch, measured on the 1e8-nonzero tensor: FP32 with buffer loads, 5
+    // items: 9 (125 VGPRs; 7: 3.01 ms, 8: 2.97, 6: 3.04 against 2.97); with
+    // the branching loads 4 items: 7 (122 VGPRs; 6: 3.69, 8: 3.75 against
+    // 3.65), 5 items: 7 (128 VGPRs; 6: 3.40, 8: 3.38 against 3.30); BF16
+    // 8-column lanes with 3 items: 5 (4: 2.50, 6: 2.84 against 2.48 with
+    // buffer loads)
     constexpr bool kStage = STAGE;
-    constexpr int kPosCap = kStage ? (ITEMS == 3 ? 5 : ITEMS + ITEMS / 4)
-                                   : (ITEMS == 4 || ITEMS == 5) ? 7 : ITEMS + ITEMS / 2;
+    constexpr int kPosCap = kStage           ? (ITEMS == 3 ? 5 : ITEMS + ITEMS / 4)
+                            : BUF && ITEMS == 5 ? 9
+                            : (ITEMS == 4 || ITEMS == 5) ? 7
+                                                         : ITEMS + ITEMS / 2;
     __shared__ int32_t s_end[kChunk];
     __shared__ int32_t s_j[kChunk];
     __shared__ int32_t s_fp[kChunk + 1];

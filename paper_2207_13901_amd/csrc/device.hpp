@@ -212,9 +212,8 @@ struct RowVec<VEC, bf16> {
 // waits for each result only when it is used; a load inside a lane-masked
 // branch makes it assume the worst and wait for nearly everything before
 // the next dependent load (for a batch of gathers: one or two in flight).
-// Ranges are at most kBufRange bytes, so the offsets of every in-bounds
-// access fit 32 bits; callers keep to spans of that size.
-constexpr uint32_t kBufRange = 0xFFFFFF00u;
+// Ranges are at most kBufRange bytes (internal.hpp), so the offsets of
+// every in-bounds access fit 32 bits; callers keep to spans of that size.
 constexpr uint32_t kBufOut = 0xFFFFFFF0u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, uint32_t bytes) {

@@ -9,6 +9,11 @@
 
 namespace spl {
 
+// Largest span in bytes that the leaves read through one buffer descriptor
+// (device.hpp: branch-free gathers): every in-bounds offset then fits 32
+// bits and stays below the out-of-range offset the descriptor loads use.
+constexpr uint32_t kBufRange = 0xFFFFFF00u;
+
 // Tile bounds of one split, in device memory: ntiles + 1 (row, position)
 // pairs, the last one being (rows, nnz).
 struct Tiles {
@@ -74,16 +79,19 @@ hipError_t launch_spmm_row(int vtype, int otype, int col_tile, int64_t n, int64_
 // the leading dimensions and both dense pointers aligned to it, and
 // col_tile / vec in {8, 16, 32}).
 int spmm_vec_width(int vtype);
+// buf: the pipelined leaf's 16-byte row gathers go through a buffer
+// descriptor (B's rows * ldb span at most kBufRange bytes).
 hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                              const int32_t *pos, const int32_t *crd, const void *vals,
                              const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
-                             int64_t stride, bool exact_chunks, void *carry, hipStream_t s);
+                             int64_t stride, bool exact_chunks, bool buf, void *carry,
+                             hipStream_t s);
 // The same over a CSR with int64 positions: merge split and vector lanes
 // only (vec == spmm_vec_width(vtype); tile positions in t.pos64).
 hipError_t launch_spmm_tiles64(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                                const int64_t *pos, const int32_t *crd, const void *vals,
                                const void *B, int64_t ldb, void *C, int64_t ldc, const Tiles &t,
-                               int64_t stride, void *carry, hipStream_t s);
+                               int64_t stride, bool buf, void *carry, hipStream_t s);
 hipError_t launch_spmm_fixup(int vtype, int64_t n, int64_t N, const Tiles &t, int64_t stride,
                              const void *carry, void *C, int64_t ldc, hipStream_t s);
 

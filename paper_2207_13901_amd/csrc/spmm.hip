@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tiles(
 // chunk's first position (they lie in [0, chunk]), so the walk and the
 // searches stay 32-bit; int32 positions are staged as they are.
 template <int W, int ITEMS, int VEC, typename V, typename BT, typename OT, typename Acc,
-          typename PosT = int32_t>
+          typename PosT = int32_t, bool BUF = false>
 __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
     int64_t n, int64_t N, const PosT *__restrict__ pos, const int32_t *__restrict__ crd,
     const V *__restrict__ vals, const BT *__restrict__ Bd, int64_t ldb, OT *__restrict__ Out,
@@ -287,11 +287,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_pipe(
         // every gather of the group's positions is issued before any is used
         // (BF16 rows stay packed until they are read)
         RowVec<VEC, BT> pv[ITEMS];
+        if constexpr (BUF) {
+            // every lane issues every gather (a lane with no row reads 0 at
+            // kBufOut): the walk then waits for each row as it reaches it
+            // rather than for all of them (FP32 0.691 -> 0.678 ms, FP64
+            // 1.276 -> 1.253 on the 2e6-row power-law matrix)
+            static_assert(VEC * sizeof(BT) == 16, "16-byte lanes");
+            const auto rB = span_rsrc(Bd, kBufRange);
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-            pv[k].zero();
-            if (b0 + k < b1 && colok)
-                pv[k].load(Bd + static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col0);
+            for (int k = 0; k < ITEMS; ++k) {
+                const bool ok = b0 + k < b1 && colok;
+                const int jj = s_crd[buf][b0 + k < kChunk ? b0 + k : kChunk - 1];
+                pv[k].load_buf(rB, ok ? static_cast<uint32_t>(sizeof(BT)) *
+                                            (static_cast<uint32_t>(jj) * static_cast<uint32_t>(ldb) +
+                                             static_cast<uint32_t>(col0))
+                                      : kBufOut);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                pv[k].zero();
+                if (b0 + k < b1 && colok)
+                    pv[k].load(Bd + static_cast<int64_t>(s_crd[buf][b0 + k]) * ldb + col0);
+            }
         }
         Acc acc[VEC];
 #pragma unroll
@@ -386,7 +404,7 @@ template <typename BT>
 constexpr int kSpmmVec = 16 / static_cast<int>(sizeof(BT));
 constexpr int kSpmmVecNarrow = 4;
 
-#define SPL_SPMM_ARGS n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, carry, s
+#define SPL_SPMM_ARGS n, N, pos, crd, vals, Bd, ldb, Out, ldo, t, stride, exact, buf, carry, s
 template <typename V, typename BT, typename OT, typename Acc>
 struct SpmmTypes {
     static hipError_t row(int W, int64_t n, int64_t N, const int32_t *pos, const int32_t *crd,
@@ -412,21 +430,27 @@ struct SpmmTypes {
     static hipError_t tiles_w(int64_t n, int64_t N, const PosT *pos, const int32_t *crd,
                               const void *vals, const void *Bd, int64_t ldb, void *Out,
                               int64_t ldo, const Tiles &t, int64_t stride, bool exact,
-                              void *carry, hipStream_t s) {
+                              bool buf, void *carry, hipStream_t s) {
         const int64_t tiles = ceil_div(t.ntiles, stride);
         dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(ceil_div(N, W * VEC)));
         if (grid.y == 0) return hipSuccess;
+        // the buffer-descriptor gathers need 16-byte lanes
+        constexpr bool kCanBuf = VEC * sizeof(BT) == 16;
         if constexpr (sizeof(PosT) == 8) {
             // int64 positions: merge pieces only (tile positions in t.pos64)
             if (!exact) return hipErrorInvalidValue;
-            k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int64_t><<<grid, kBlock, 0, s>>>(
+            auto kern = buf && kCanBuf ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int64_t, kCanBuf>
+                                       : k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int64_t, false>;
+            kern<<<grid, kBlock, 0, s>>>(
                 n, N, pos, crd, static_cast<const V *>(vals), static_cast<const BT *>(Bd), ldb,
                 static_cast<OT *>(Out), ldo, t.row, t.pos64, t.ntiles, stride,
                 static_cast<Acc *>(carry));
         } else {
             // pieces of exactly one chunk (merge split): the pipelined leaf
-            auto kern = exact ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc>
-                              : k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>;
+            auto kern = !exact ? k_spmm_tiles<W, ITEMS, V, BT, OT, Acc>
+                        : buf && kCanBuf
+                            ? k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int32_t, kCanBuf>
+                            : k_spmm_pipe<W, ITEMS, VEC, V, BT, OT, Acc, int32_t, false>;
             kern<<<grid, kBlock, 0, s>>>(n, N, pos, crd, static_cast<const V *>(vals),
                                          static_cast<const BT *>(Bd), ldb, static_cast<OT *>(Out),
                                          ldo, t.row, t.pos, t.ntiles, stride,
@@ -448,7 +472,7 @@ struct SpmmTypes {
     static hipError_t tiles_vec(int col_tile, int items, int64_t n, int64_t N,
                                 const PosT *pos, const int32_t *crd, const void *vals,
                                 const void *Bd, int64_t ldb, void *Out, int64_t ldo,
-                                const Tiles &t, int64_t stride, bool exact, void *carry,
+                                const Tiles &t, int64_t stride, bool exact, bool buf, void *carry,
                                 hipStream_t s) {
         switch (col_tile / VEC) {
         case 4: return items <= 8 ? tiles_w<4, 8, VEC, PosT>(SPL_SPMM_ARGS)
@@ -469,7 +493,7 @@ struct SpmmTypes {
     static hipError_t tiles64(int col_tile, int items, int vec, int64_t n, int64_t N,
                               const int64_t *pos, const int32_t *crd, const void *vals,
                               const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
-                              int64_t stride, bool exact, void *carry, hipStream_t s) {
+                              int64_t stride, bool exact, bool buf, void *carry, hipStream_t s) {
         if (vec != kSpmmVec<BT> || !exact || (items != 8 && items != 16))
             return hipErrorInvalidValue;
         return tiles_vec<kSpmmVec<BT>>(col_tile, items, SPL_SPMM_ARGS);
@@ -478,7 +502,7 @@ struct SpmmTypes {
     static hipError_t tiles(int col_tile, int items, int vec, int64_t n, int64_t N,
                             const int32_t *pos, const int32_t *crd, const void *vals,
                             const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
-                            int64_t stride, bool exact, void *carry, hipStream_t s) {
+                            int64_t stride, bool exact, bool buf, void *carry, hipStream_t s) {
         if (vec > 1) {
             if (!exact || (items != 8 && items != 16)) return hipErrorInvalidValue;
             if (vec == kSpmmVec<BT>) return tiles_vec<kSpmmVec<BT>>(col_tile, items, SPL_SPMM_ARGS);
@@ -534,35 +558,37 @@ int spmm_vec_width(int vtype) {
 hipError_t launch_spmm_tiles64(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                                const int64_t *pos, const int32_t *crd, const void *vals,
                                const void *Bd, int64_t ldb, void *Out, int64_t ldo,
-                               const Tiles &t, int64_t stride, void *carry, hipStream_t s) {
+                               const Tiles &t, int64_t stride, bool buf, void *carry,
+                               hipStream_t s) {
     if (vtype == SPL_F64)
         return SpmmTypes<double, double, double, double>::tiles64(col_tile, items, vec, n, N, pos,
                                                                   crd, vals, Bd, ldb, Out, ldo, t,
-                                                                  stride, true, carry, s);
+                                                                  stride, true, buf, carry, s);
     if (vtype == SPL_F32)
         return SpmmTypes<float, float, float, float>::tiles64(col_tile, items, vec, n, N, pos, crd,
                                                               vals, Bd, ldb, Out, ldo, t, stride,
-                                                              true, carry, s);
+                                                              true, buf, carry, s);
     return SpmmTypes<bf16, bf16, float, float>::tiles64(col_tile, items, vec, n, N, pos, crd, vals,
-                                                        Bd, ldb, Out, ldo, t, stride, true, carry,
-                                                        s);
+                                                        Bd, ldb, Out, ldo, t, stride, true, buf,
+                                                        carry, s);
 }
 
 hipError_t launch_spmm_tiles(int vtype, int col_tile, int items, int vec, int64_t n, int64_t N,
                              const int32_t *pos, const int32_t *crd, const void *vals,
                              const void *Bd, int64_t ldb, void *Out, int64_t ldo, const Tiles &t,
-                             int64_t stride, bool exact_chunks, void *carry, hipStream_t s) {
+                             int64_t stride, bool exact_chunks, bool buf, void *carry,
+                             hipStream_t s) {
     if (vtype == SPL_F64)
         return SpmmTypes<double, double, double, double>::tiles(col_tile, items, vec, n, N, pos,
                                                                 crd, vals, Bd, ldb, Out, ldo, t,
-                                                                stride, exact_chunks, carry, s);
+                                                                stride, exact_chunks, buf, carry, s);
     if (vtype == SPL_F32)
         return SpmmTypes<float, float, float, float>::tiles(col_tile, items, vec, n, N, pos, crd,
                                                             vals, Bd, ldb, Out, ldo, t, stride,
-                                                            exact_chunks, carry, s);
+                                                            exact_chunks, buf, carry, s);
     return SpmmTypes<bf16, bf16, float, float>::tiles(col_tile, items, vec, n, N, pos, crd, vals,
                                                       Bd, ldb, Out, ldo, t, stride, exact_chunks,
-                                                      carry, s);
+                                                      buf, carry, s);
 }
 
 }  // namespace spl
