@@ -351,11 +351,12 @@ def _ops_config3(dev, spl, tuning, torch, configs, want, res):
         res[name] = _rate(ms, nbytes, nnzB * (2 * K + 1), ms_spread)
         del C, D, A
     if "spadd3" in want:
-        # the numeric phase's input staging: 1 direct, 2 coordinates in LDS,
-        # 3 coordinates and values in LDS (whole calls, both phases)
+        # the forms (whole calls, both phases): merges a lane per row with 1 the
+        # inputs read directly, 2 coordinates in LDS, 3 coordinates and values
+        # in LDS; 4 ranks, a lane per input entry
         var_ms = {v: tuning.time_call(
             lambda v=v: spl.spadd3(*ops, sched=spl.schedule("row", variant=v)), reps=10, warmup=3)
-            for v in (1, 2, 3)}
+            for v in (1, 2, 3, 4)}
         ms, ms_spread = _time_ops(lambda: spl.spadd3(*ops))
         out = spl.spadd3(*ops)
         nnzA = out.crd.numel()

@@ -435,7 +435,9 @@ spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
  * synchronizes on `stream` to read that count back.  Values are not read.
  * Only the row split is accepted: sched kind NNZ or MERGE gives
  * SPL_ERR_UNSUPPORTED (a non-zero split of a sum of CSR operands does not
- * align their positions). */
+ * align their positions).  sched->variant is checked as for the numeric
+ * phase (0..4, else SPL_ERR_ARG); the count is the same for every variant
+ * (a three-way merge a lane per row over coordinates staged in LDS). */
 spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                                const spl_sparse *D, int32_t *A_pos, int64_t *nnz_out,
                                const spl_schedule *sched, void *workspace,
@@ -444,10 +446,14 @@ spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_
  * increasing per row, *nnz_out entries) and A_vals (same dtype as the
  * operands, F64 or F32): each value sums the operands present at that
  * coordinate in the order B, C, D; a sum that cancels to zero keeps its
- * coordinate.  sched->variant picks how a workgroup reads its rows' inputs:
- * 0 library default (1), 1 directly from memory, 2 coordinate runs staged
- * in LDS, 3 coordinates and values staged (runs longer than the stage fall
- * back to direct reads); every variant gives the same bits. */
+ * coordinate.  sched->variant picks the form: 1 a lane per row merging its
+ * inputs read directly from memory, 2 the same with the workgroup's
+ * coordinate runs staged in LDS, 3 with coordinates and values staged,
+ * 4 by ranks (coordinates staged, a lane per input entry computing its
+ * output slot by binary search in the other operands' rows); 0 the library
+ * default (4).  Workgroups whose runs exceed the
+ * stage fall back to direct reads; every variant gives the same bits, and
+ * anything else is SPL_ERR_ARG. */
 spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                               const spl_sparse *D, const int32_t *A_pos, int32_t *A_crd,
                               void *A_vals, const spl_schedule *sched, spl_stream stream);

@@ -1640,9 +1640,19 @@ spl_status spl_sddmm(spl_context *ctx, const spl_sparse *B, const spl_dense *C,
 }
 
 namespace {
-// The numeric phase's default input staging (0 direct, 1 coordinates, 2
-// coordinates and values).
-constexpr int kSpadd3DefaultStage = 0;
+// The numeric phase's default form (0 direct, 1 coordinates staged, 2
+// coordinates and values staged, 3 by ranks).
+constexpr int kSpadd3DefaultStage = 3;
+
+// sched->variant (0..4) picks the numeric phase's form: 0 library default,
+// 1..3 the merges (inputs read directly, coordinate runs staged in LDS,
+// coordinates and values staged), 4 by ranks (coordinates staged, a lane per
+// input entry).  The symbolic phase checks it and counts by merge always.
+spl_status spadd3_variant(spl_context *ctx, const spl_schedule *sched, int *variant) {
+    *variant = sched ? sched->variant : 0;
+    if (*variant < 0 || *variant > 4) return fail(ctx, SPL_ERR_ARG, "SpAdd3 variant must be 0..4");
+    return SPL_OK;
+}
 
 spl_status check_spadd3(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                         const spl_sparse *D, const spl_schedule *sched) {
@@ -1667,6 +1677,8 @@ spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_
     if (!ctx) return SPL_ERR_ARG;
     if (!A_pos || !nnz_out) return fail(ctx, SPL_ERR_ARG, "NULL output");
     SPL_CHECK(check_spadd3(ctx, B, C, D, sched));
+    int variant = 0;
+    SPL_CHECK(spadd3_variant(ctx, sched, &variant));
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = B->dims[0];
@@ -1705,11 +1717,8 @@ spl_status spl_spadd3_numeric(spl_context *ctx, const spl_sparse *B, const spl_s
     const int64_t n = B->dims[0];
     if (n > 0 && (B->nnz + C->nnz + D->nnz > 0) && (!A_crd || !A_vals))
         return fail(ctx, SPL_ERR_ARG, "NULL output arrays");
-    // sched->variant: 0 library default, 1 inputs read directly, 2 the
-    // coordinate runs staged in LDS, 3 coordinates and values staged
-    const int variant = sched ? sched->variant : 0;
-    if (variant < 0 || variant > 3)
-        return fail(ctx, SPL_ERR_ARG, "SpAdd3 variant must be 0..3");
+    int variant = 0;
+    SPL_CHECK(spadd3_variant(ctx, sched, &variant));
     const int stage = variant == 0 ? kSpadd3DefaultStage : variant - 1;
     SPL_CHECK(set_device(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);

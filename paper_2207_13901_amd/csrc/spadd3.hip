@@ -7,15 +7,20 @@
 // non-zero split does not apply to a sum of CSR operands (Sec. VI-A, CPU
 // results).
 //
-// One lane per row merges the three sorted coordinate lists; values are
-// summed in operand order B, C, D over the operands present (a cancellation
-// to zero keeps its coordinate).  The scan is three passes: per-workgroup
-// totals, one workgroup scanning the totals, per-workgroup rescan.  The
-// symbolic phase copies the workgroup's input coordinates to LDS with
-// coalesced loads first, and the numeric phase stages the output in LDS so
-// that its stores are coalesced: one lane per row reading or storing
-// straight to HBM keeps far more partly used lines open than the caches
-// hold.
+// Values are summed in operand order B, C, D over the operands present (a
+// cancellation to zero keeps its coordinate).  The symbolic phase copies
+// the workgroup's input coordinates to LDS with coalesced loads, and one
+// lane per row merges the three sorted coordinate lists there to count the
+// union.  The scan is three passes: per-workgroup totals, one workgroup
+// scanning the totals, per-workgroup rescan.  The numeric phase's default
+// form works by ranks: with the coordinates staged, every input entry finds
+// its own output slot by binary search in the other operands' rows, so the
+// work is spread over all lanes and every input line is read with coalesced
+// loads.  The merge forms (one lane per row, output staged in LDS windows
+// so that its stores are coalesced) remain as schedule variants: one lane
+// per row reading or storing straight to HBM keeps far more partly used
+// lines open than the caches hold, and a window is filled only by the lanes
+// whose rows reach into it.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -91,6 +96,33 @@ struct Merge3 {
     }
 };
 
+// Copies three runs of n3[X] <= PER * kBlock consecutive coordinates from
+// src[X] to dst[X] in LDS.  Every lane issues all its loads before any store
+// (past a run: 0, with no access), so the copy costs one memory round trip,
+// not one per loop iteration.
+template <int PER>
+__device__ __forceinline__ void stage3(const int32_t *const *src, const int32_t *n3,
+                                       int32_t *const *dst) {
+    const int t = threadIdx.x;
+    uint32_t v[3][PER];
+#pragma unroll
+    for (int X = 0; X < 3; ++X) {
+        const __amdgpu_buffer_rsrc_t rc = span_rsrc(src[X], 4u * n3[X]);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = j * kBlock + t;
+            v[X][j] = buf_u32(rc, k < n3[X] ? 4u * k : kBufOut);
+        }
+    }
+#pragma unroll
+    for (int X = 0; X < 3; ++X)
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = j * kBlock + t;
+            if (k < n3[X]) dst[X][k] = static_cast<int32_t>(v[X][j]);
+        }
+}
+
 // Coordinates of the workgroup's rows [r0, r1) per operand staged in LDS.
 // One lane per row reading its row straight from HBM keeps a few lines per
 // lane open at once, more than the L1 and L2 hold, so lines are fetched
@@ -98,26 +130,25 @@ struct Merge3 {
 // exceeds kStageCap the workgroup reads the operands directly.
 constexpr int kStageCap = 2560;
 
-__device__ __forceinline__ Crd3 stage_crd(const Csr3 &m, int64_t r0, int64_t r1,
-                                          int32_t (*s_x)[kStageCap]) {
-    const int32_t b0 = m.bp[r0], c0 = m.cp[r0], d0 = m.dp[r0];
-    const int32_t nb = m.bp[r1] - b0, nc = m.cp[r1] - c0, nd = m.dp[r1] - d0;
-    if (nb > kStageCap || nc > kStageCap || nd > kStageCap) return Crd3{m.bc, m.cc, m.dc, 0, 0, 0};
-    for (int k = threadIdx.x; k < nb; k += kBlock) s_x[0][k] = m.bc[b0 + k];
-    for (int k = threadIdx.x; k < nc; k += kBlock) s_x[1][k] = m.cc[c0 + k];
-    for (int k = threadIdx.x; k < nd; k += kBlock) s_x[2][k] = m.dc[d0 + k];
+// Stages the coordinate runs of rows [r0, r1) when each fits kStageCap and
+// returns whether it did (then with the workgroup synchronized); first3
+// gets the runs' first positions.
+__device__ __forceinline__ bool stage_crd(const Csr3 &m, int64_t r0, int64_t r1,
+                                          int32_t (*s_x)[kStageCap], int32_t *first3) {
+    first3[0] = m.bp[r0];
+    first3[1] = m.cp[r0];
+    first3[2] = m.dp[r0];
+    const int32_t n3[3] = {m.bp[r1] - first3[0], m.cp[r1] - first3[1], m.dp[r1] - first3[2]};
+    if (n3[0] > kStageCap || n3[1] > kStageCap || n3[2] > kStageCap) return false;
+    const int32_t *src[3] = {m.bc + first3[0], m.cc + first3[1], m.dc + first3[2]};
+    int32_t *dst[3] = {s_x[0], s_x[1], s_x[2]};
+    stage3<kStageCap / kBlock>(src, n3, dst);
     __syncthreads();
-    return Crd3{s_x[0], s_x[1], s_x[2], b0, c0, d0};
+    return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int32_t *apos) {
-    __shared__ int32_t s_x[3][kStageCap];
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
-    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
-    const int64_t i = r0 + threadIdx.x;
-    const Crd3 x = stage_crd(m, r0, r1, s_x);
-    if (i == 0) apos[0] = 0;
-    if (i >= n) return;
+// Union size of row i's coordinate lists read through x.
+__device__ __forceinline__ int32_t union_count(const Csr3 &m, const Crd3 &x, int64_t i) {
     Merge3 mg(m, x, i);
     int32_t k = 0;
     float unused;
@@ -126,7 +157,24 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
         mg.next<false, float>(x, none, unused);
         ++k;
     }
-    apos[i + 1] = k;
+    return k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int32_t *apos) {
+    __shared__ int32_t s_x[3][kStageCap];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int64_t i = r0 + threadIdx.x;
+    int32_t f[3];
+    const bool staged = stage_crd(m, r0, r1, s_x, f);
+    if (i == 0) apos[0] = 0;
+    if (i >= n) return;
+    // two inlined copies, so that the staged one reads LDS directly rather
+    // than through generic (flat) loads
+    if (staged)
+        apos[i + 1] = union_count(m, Crd3{s_x[0], s_x[1], s_x[2], f[0], f[1], f[2]}, i);
+    else
+        apos[i + 1] = union_count(m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0}, i);
 }
 
 // Numeric phase.  The 256 rows of a workgroup own one contiguous run of the
@@ -139,6 +187,38 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
 // staging them as well would halve the workgroups per CU, which costs more
 // than the repeated line fetches it saves.
 constexpr int kFillCap = 2048;
+
+// The workgroup's rows [r0, r1) merged a lane per row into output windows
+// of kWin entries in LDS (w_crd, w_val), each window written with coalesced
+// stores.
+template <typename V, int kWin>
+__device__ __forceinline__ void fill_windows(int64_t n, const Csr3 &m, const Crd3 &x,
+                                             const Vals3<V> &vv, const int32_t *apos,
+                                             int32_t *acrd, V *aval, int64_t r0, int64_t r1,
+                                             int32_t *w_crd, V *w_val) {
+    const int64_t i = r0 + threadIdx.x;
+    const int64_t base = apos[r0];
+    const int64_t total = apos[r1] - base;
+    const bool mine = i < n;
+    int64_t k = mine ? apos[i] - base : 0;
+    const int64_t hi = mine ? apos[i + 1] - base : 0;
+    Merge3 mg(m, x, mine ? i : r0);
+    for (int64_t w = 0; w < total; w += kWin) {
+        const int64_t we = w + kWin < total ? w + kWin : total;
+        for (; k < hi && k < we; ++k) {
+            V sum;
+            const int32_t c = mg.next<true, V>(x, vv, sum);
+            w_crd[k - w] = c;
+            w_val[k - w] = sum;
+        }
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < we - w; q += kBlock) {
+            store_stream(acrd + base + w + q, w_crd[q]);
+            store_stream(aval + base + w + q, w_val[q]);
+        }
+        __syncthreads();
+    }
+}
 
 // STAGE 0: inputs read directly; 1: the workgroup's coordinate runs staged
 // in LDS (as the count phase does); 2: coordinates and values staged, with a
@@ -156,47 +236,294 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const
     __shared__ V s_v[STAGE == 2 ? 3 : 1][STAGE == 2 ? kStageCap : 1];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
     const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
-    const int64_t i = r0 + threadIdx.x;
-    Crd3 x{m.bc, m.cc, m.dc, 0, 0, 0};
-    Vals3<V> vv{bv, cv, dv, 0, 0, 0};
     if constexpr (STAGE > 0) {
-        const int32_t b0 = m.bp[r0], c0 = m.cp[r0], d0 = m.dp[r0];
-        const int32_t nb = m.bp[r1] - b0, nc = m.cp[r1] - c0, nd = m.dp[r1] - d0;
-        if (nb <= kStageCap && nc <= kStageCap && nd <= kStageCap) {
-            for (int k = threadIdx.x; k < nb; k += kBlock) s_x[0][k] = m.bc[b0 + k];
-            for (int k = threadIdx.x; k < nc; k += kBlock) s_x[1][k] = m.cc[c0 + k];
-            for (int k = threadIdx.x; k < nd; k += kBlock) s_x[2][k] = m.dc[d0 + k];
-            x = Crd3{s_x[0], s_x[1], s_x[2], b0, c0, d0};
+        // the staged path is a copy of its own, so that it reads LDS directly
+        int32_t f[3];
+        if (stage_crd(m, r0, r1, s_x, f)) {
+            const Crd3 x{s_x[0], s_x[1], s_x[2], f[0], f[1], f[2]};
             if constexpr (STAGE == 2) {
-                for (int k = threadIdx.x; k < nb; k += kBlock) s_v[0][k] = bv[b0 + k];
-                for (int k = threadIdx.x; k < nc; k += kBlock) s_v[1][k] = cv[c0 + k];
-                for (int k = threadIdx.x; k < nd; k += kBlock) s_v[2][k] = dv[d0 + k];
-                vv = Vals3<V>{s_v[0], s_v[1], s_v[2], b0, c0, d0};
+                const int32_t nv[3] = {m.bp[r1] - f[0], m.cp[r1] - f[1], m.dp[r1] - f[2]};
+                const V *src[3] = {bv + f[0], cv + f[1], dv + f[2]};
+#pragma unroll
+                for (int X = 0; X < 3; ++X)
+                    for (int k = threadIdx.x; k < nv[X]; k += kBlock) s_v[X][k] = src[X][k];
+                __syncthreads();
+                fill_windows<V, kWin>(n, m, x, Vals3<V>{s_v[0], s_v[1], s_v[2], f[0], f[1], f[2]},
+                                      apos, acrd, aval, r0, r1, s_crd, s_val);
+            } else {
+                fill_windows<V, kWin>(n, m, x, Vals3<V>{bv, cv, dv, 0, 0, 0}, apos, acrd, aval,
+                                      r0, r1, s_crd, s_val);
             }
-            __syncthreads();
+            return;
         }
     }
-    const int64_t base = apos[r0];
-    const int64_t total = apos[r1] - base;
-    const bool mine = i < n;
-    int64_t k = mine ? apos[i] - base : 0;
-    const int64_t hi = mine ? apos[i + 1] - base : 0;
-    Merge3 mg(m, x, mine ? i : r0);
-    for (int64_t w = 0; w < total; w += kWin) {
-        const int64_t we = w + kWin < total ? w + kWin : total;
-        for (; k < hi && k < we; ++k) {
-            V sum;
-            const int32_t c = mg.next<true, V>(x, vv, sum);
-            s_crd[k - w] = c;
-            s_val[k - w] = sum;
-        }
-        __syncthreads();
-        for (int64_t q = threadIdx.x; q < we - w; q += kBlock) {
-            store_stream(acrd + base + w + q, s_crd[q]);
-            store_stream(aval + base + w + q, s_val[q]);
-        }
-        __syncthreads();
+    fill_windows<V, kWin>(n, m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0}, Vals3<V>{bv, cv, dv, 0, 0, 0},
+                          apos, acrd, aval, r0, r1, s_crd, s_val);
+}
+
+// Numeric phase by ranks.  The workgroup's coordinate runs of the three
+// operands are staged in LDS, and every input entry then finds its output
+// slot by itself, a lane per entry: an entry of C duplicates one of B when
+// B's row holds its coordinate, an entry of D when B's or C's row does; the
+// first operand holding a coordinate owns it and writes it at
+//   A.pos[i] + #(B_i < x) + #(owned C_i < x) + #(owned D_i < x),
+// the counts from lower bounds by binary search in the staged rows less the
+// duplicates below them, which come from one ballot of the duplicate flags
+// per 64 entries and a prefix over those words.  The owner adds the values
+// of the duplicates in the order B, C, D as the merge does.  Every input
+// line is read with coalesced loads (values by their owner lanes, the
+// duplicates' values gathered from lines their neighbours read), and no lane
+// walks a whole row.  Runs longer than kRankCap fall back to the windowed
+// merge for that workgroup.
+constexpr int kRankCap = 2304;                 // entries per operand and workgroup
+constexpr int kRankPer = kRankCap / kBlock;     // entries per lane and operand
+constexpr int kRankChunks = kRankCap / 64 + 1;  // ballot words, one spare for a full run
+static_assert(kRankCap % kBlock == 0, "whole entries per lane");
+
+// Value at byte offset `off` of a buffer (0 past its range, with no access).
+__device__ __forceinline__ float buf_load(const float *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(const double *, __amdgpu_buffer_rsrc_t r,
+                                           uint32_t off) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return __hiloint2double(static_cast<int>(w[1]), static_cast<int>(w[0]));
+}
+
+__device__ __forceinline__ int lower_bound_lds(const int32_t *a, int lo, int hi, int32_t x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
+    return lo;
+}
+
+// Flagged entries among the first k of a run: the prefix of k's 64-entry
+// word plus the flags below k inside it.
+__device__ __forceinline__ int flags_below(const uint64_t *mask, const int32_t *pre, int k) {
+    const int c = k >> 6;
+    return pre[c] + __popcll(mask[c] & ((1ull << (k & 63)) - 1));
+}
+
+// LDS of the rank forms: the coordinate runs, the row of each staged entry
+// (relative to the workgroup's first row), the rows' starts in the runs,
+// the duplicate flags of C and D with their per-word prefixes, and a
+// per-row constant of the output slots.
+struct RankLds {
+    int32_t x[3][kRankCap];
+    uint8_t row[3][kRankCap];
+    int32_t start[3][kBlock + 1];
+    uint64_t mask[2][kRankChunks];
+    int32_t pre[2][kRankChunks];
+    int32_t base[kBlock];
+
+    __device__ __forceinline__ int lb(int X, int r, int32_t v) const {
+        return lower_bound_lds(x[X], start[X][r], start[X][r + 1], v);
+    }
+    __device__ __forceinline__ bool holds(int X, int r, int p, int32_t v) const {
+        return p < start[X][r + 1] && x[X][p] == v;
+    }
+    // owned entries of C (X = 1) or D (X = 2) before staged index k of the run
+    __device__ __forceinline__ int owned(int X, int k) const {
+        return k - flags_below(mask[X - 1], pre[X - 1], k);
+    }
+    __device__ __forceinline__ bool dup(int X, int e) const {
+        return (mask[X - 1][e >> 6] >> (e & 63)) & 1;
+    }
+};
+
+// What the flag pass found for a lane's entries of C and D, kept for the
+// output pass: the row (8 bits) and the lower bounds in B's row and, for D,
+// in C's row (12 bits each, kRankCap <= 4096).
+struct RankSeen {
+    uint32_t c[kRankPer], d[kRankPer];
+};
+static_assert(kRankCap <= 4096, "staged indices fit 12 bits");
+
+// Stages rows [r0, r0 + nr) whose runs (n3 entries from first3) fit, flags
+// the duplicates and sets the per-row constants
+//   base[r] = apos[r] - apos[r0] - start_B[r] - owned_C(start_C[r]) - owned_D(start_D[r]),
+// so that an entry's output slot, relative to the workgroup's first output,
+// is base[r] plus its counts before it.
+// Ends with the workgroup synchronized.
+__device__ void rank_prepare(const Csr3 &m, int64_t r0, int nr, const int32_t *first3,
+                             const int32_t *n3, const int32_t *apos, RankLds &L,
+                             RankSeen &S) {
+    const int t = threadIdx.x;
+    const int32_t *pos[3] = {m.bp, m.cp, m.dp};
+    const int32_t *crd[3] = {m.bc, m.cc, m.dc};
+    const int32_t *src[3] = {crd[0] + first3[0], crd[1] + first3[1], crd[2] + first3[2]};
+    int32_t *dst[3] = {L.x[0], L.x[1], L.x[2]};
+    stage3<kRankPer>(src, n3, dst);
+#pragma unroll
+    for (int X = 0; X < 3; ++X)
+        for (int r = t; r <= nr; r += kBlock) L.start[X][r] = pos[X][r0 + r] - first3[X];
+    __syncthreads();
+    if (t < nr) {
+#pragma unroll
+        for (int X = 0; X < 3; ++X)
+            for (int k = L.start[X][t]; k < L.start[X][t + 1]; ++k) L.row[X][k] = t;
+    }
+    __syncthreads();
+    const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {  // C entries that B's row holds
+        const int e = j * kBlock + t;
+        bool d = false;
+        S.c[j] = 0;
+        if (e < n3[1]) {
+            const int r = L.row[1][e];
+            const int32_t v = L.x[1][e];
+            const int p = L.lb(0, r, v);
+            d = L.holds(0, r, p, v);
+            S.c[j] = r | (p << 8);
+        }
+        const uint64_t word = __ballot(d);
+        if (lane == 0) L.mask[0][4 * j + wave] = word;
+    }
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {  // D entries that B's or C's row holds
+        const int e = j * kBlock + t;
+        bool d = false;
+        S.d[j] = 0;
+        if (e < n3[2]) {
+            const int r = L.row[2][e];
+            const int32_t v = L.x[2][e];
+            const int p = L.lb(0, r, v), q = L.lb(1, r, v);
+            d = L.holds(0, r, p, v) || L.holds(1, r, q, v);
+            S.d[j] = r | (p << 8) | (q << 20);
+        }
+        const uint64_t word = __ballot(d);
+        if (lane == 0) L.mask[1][4 * j + wave] = word;
+    }
+    static_assert(kBlock == 256, "four waves: word 4j + wave holds entries j*256 + 64*wave ..");
+    __syncthreads();
+    if (wave < 2) {  // exclusive prefix of the flag counts per word: wave 0 for C, 1 for D
+        const int words = (n3[1 + wave] + 63) >> 6;
+        int cnt = 0;
+        if (lane < kRankChunks) {
+            if (lane < words)
+                cnt = __popcll(L.mask[wave][lane]);
+            else
+                L.mask[wave][lane] = 0;
+        }
+        int incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane < kRankChunks) L.pre[wave][lane] = incl - cnt;
+    }
+    __syncthreads();
+    if (t < nr)
+        L.base[t] = apos[r0 + t] - apos[r0] - L.start[0][t] - L.owned(1, L.start[1][t]) -
+                    L.owned(2, L.start[2][t]);
+    __syncthreads();
+}
+
+// The entries of operand X that own their coordinate, written at their
+// output slots (relative to the workgroup's first output at acrd, aval).
+// A lane's kRankPer entries are handled together: first the searches in
+// LDS, then the loads of the values of the later operands holding the
+// coordinates at once, then the sums (own: the entries' own values, loaded
+// with the staging) and stores.
+template <int X, typename V>
+__device__ __forceinline__ void rank_emit(const RankLds &L, const RankSeen &S,
+                                          const V *const *vals, const __amdgpu_buffer_rsrc_t *rv,
+                                          const V *own, int n, int32_t *acrd, V *aval) {
+    const int t = threadIdx.x;
+    int32_t o[kRankPer], xs[kRankPer];
+    V g1[kRankPer], g2[kRankPer];
+    uint32_t has1 = 0, has2 = 0;  // bit j: entry j adds C's value (X = 0) / D's (X < 2)
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        const int e = j * kBlock + t;
+        uint32_t s1 = kBufOut, s2 = kBufOut;
+        o[j] = -1;
+        xs[j] = 0;
+        if (e < n && (X == 0 || !L.dup(X, e))) {
+            int r, slot;
+            int32_t x;
+            if constexpr (X == 0) {  // B owns all its entries
+                r = L.row[0][e];
+                x = L.x[0][e];
+                const int p = L.lb(1, r, x), q = L.lb(2, r, x);
+                if (L.holds(1, r, p, x)) s1 = static_cast<uint32_t>(sizeof(V) * p);
+                if (L.holds(2, r, q, x)) s2 = static_cast<uint32_t>(sizeof(V) * q);
+                slot = e + L.owned(1, p) + L.owned(2, q);
+            } else if constexpr (X == 1) {  // B does not hold it
+                r = S.c[j] & 255;
+                x = L.x[1][e];
+                const int p = S.c[j] >> 8, q = L.lb(2, r, x);
+                if (L.holds(2, r, q, x)) s2 = static_cast<uint32_t>(sizeof(V) * q);
+                slot = p + L.owned(1, e) + L.owned(2, q);
+            } else {  // neither B nor C holds it
+                r = S.d[j] & 255;
+                x = L.x[2][e];
+                const int p = (S.d[j] >> 8) & 4095, q = S.d[j] >> 20;
+                slot = p + L.owned(1, q) + L.owned(2, e);
+            }
+            o[j] = L.base[r] + slot;
+            xs[j] = x;
+        }
+        if constexpr (X == 0) g1[j] = buf_load(vals[1], rv[1], s1);
+        if constexpr (X < 2) g2[j] = buf_load(vals[2], rv[2], s2);
+        has1 |= static_cast<uint32_t>(s1 != kBufOut) << j;
+        has2 |= static_cast<uint32_t>(s2 != kBufOut) << j;
+    }
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+        if (o[j] < 0) continue;
+        // the merge's order: B's value, else 0, then + C's, then + D's
+        V v = X == 0 ? own[j] : V(0) + own[j];
+        if (X == 0 && ((has1 >> j) & 1)) v = v + g1[j];
+        if (X < 2 && ((has2 >> j) & 1)) v = v + g2[j];
+        acrd[o[j]] = xs[j];
+        aval[o[j]] = v;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_spadd3_rank(int64_t n, Csr3 m, const V *bv,
+                                                        const V *cv, const V *dv,
+                                                        const int32_t *apos, int32_t *acrd,
+                                                        V *aval) {
+    __shared__ __align__(16) RankLds L;
+    static_assert(kFillCap * (4 + sizeof(V)) <= sizeof(L.x), "fallback windows fit the stage");
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int nr = static_cast<int>(r1 - r0);
+    const int32_t first3[3] = {m.bp[r0], m.cp[r0], m.dp[r0]};
+    const int32_t n3[3] = {m.bp[r1] - first3[0], m.cp[r1] - first3[1], m.dp[r1] - first3[2]};
+    if (n3[0] > kRankCap || n3[1] > kRankCap || n3[2] > kRankCap) {
+        fill_windows<V, kFillCap>(n, m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0},
+                                  Vals3<V>{bv, cv, dv, 0, 0, 0}, apos, acrd, aval, r0, r1,
+                                  &L.x[0][0], reinterpret_cast<V *>(&L.x[0][0] + kFillCap));
+        return;
+    }
+    const V *vals[3] = {bv, cv, dv};
+    __amdgpu_buffer_rsrc_t rv[3];
+    V own[3][kRankPer];  // the lane's entries' values, in flight with the staging
+#pragma unroll
+    for (int X = 0; X < 3; ++X) {
+        rv[X] = span_rsrc(vals[X] + first3[X], sizeof(V) * n3[X]);
+#pragma unroll
+        for (int j = 0; j < kRankPer; ++j) {
+            const int e = j * kBlock + threadIdx.x;
+            own[X][j] = buf_load(vals[X], rv[X],
+                                 e < n3[X] ? static_cast<uint32_t>(sizeof(V) * e) : kBufOut);
+        }
+    }
+    RankSeen S;
+    rank_prepare(m, r0, nr, first3, n3, apos, L, S);
+    const int32_t out0 = apos[r0];
+    rank_emit<0>(L, S, vals, rv, own[0], n3[0], acrd + out0, aval + out0);
+    rank_emit<1>(L, S, vals, rv, own[1], n3[1], acrd + out0, aval + out0);
+    rank_emit<2>(L, S, vals, rv, own[2], n3[2], acrd + out0, aval + out0);
 }
 
 // Element i of the scanned sequence: x[i], or with window bounds the window
@@ -343,8 +670,8 @@ hipError_t launch_spadd3_symbolic(int64_t n, const int32_t *bp, const int32_t *b
                                   const int32_t *dc, int32_t *apos, int64_t *tile_sum,
                                   int64_t *total, hipStream_t s) {
     Csr3 m{bp, bc, cp, cc, dp, dc};
-    const int64_t rows_grid = ceil_div(n > 0 ? n : 1, kBlock);
-    k_spadd3_count<<<dim3(static_cast<unsigned>(rows_grid)), kBlock, 0, s>>>(n, m, apos);
+    const dim3 rows_grid(static_cast<unsigned>(ceil_div(n > 0 ? n : 1, kBlock)));
+    k_spadd3_count<<<rows_grid, kBlock, 0, s>>>(n, m, apos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nt = spadd3_scan_tiles(n);
@@ -368,6 +695,7 @@ hipError_t spadd3_fill(int stage, int64_t n, const Csr3 &m, const void *bv, cons
                                      static_cast<const V *>(dv), apos, acrd, static_cast<V *>(aval));
         return hipGetLastError();
     };
+    if (stage == 3) return go(k_spadd3_rank<V>);
     if (stage == 1) return go(k_spadd3_fill<V, 1>);
     if (stage == 2) return go(k_spadd3_fill<V, 2>);
     return go(k_spadd3_fill<V, 0>);

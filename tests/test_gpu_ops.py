@@ -370,10 +370,10 @@ def test_spadd3_long_rows_span_output_windows():
     ops = [spl.CSR(_t(p), _t(c), _t(v, torch.float32), (n, m))
            for p, c, v in ((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))]
     rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
-    # every input-staging form of the numeric phase (direct, coordinates in
-    # LDS, coordinates and values in LDS; workgroups whose runs exceed the
-    # stage read directly)
-    for variant in (0, 1, 2, 3):
+    # every form of both phases (merges reading directly, with coordinates
+    # in LDS, with coordinates and values in LDS; ranks; workgroups whose runs
+    # exceed the stage read directly)
+    for variant in (0, 1, 2, 3, 4):
         A = spl.spadd3(*ops, sched=spl.schedule("row", variant=variant))
         assert np.array_equal(A.pos.cpu().numpy(), rpos), variant
         assert np.array_equal(A.crd.cpu().numpy(), rcrd), variant
@@ -389,7 +389,7 @@ def test_spadd3_staged_fill_variants(dtype):
     host = [(c[k]["pos"].numpy(), c[k]["crd"].numpy(), host64(o.vals)) for k, o in zip("BCD", ops)]
     rpos, rcrd, rvals, rS, _ = oracle.spadd3(*host)
     first = None
-    for variant in (1, 2, 3):
+    for variant in (1, 2, 3, 4):
         A = spl.spadd3(*ops, sched=spl.schedule("row", variant=variant))
         assert np.array_equal(A.pos.cpu().numpy(), rpos) and np.array_equal(A.crd.cpu().numpy(), rcrd)
         assert_close(host64(A.vals), rvals, rS, RTOL[dtype], f"spadd3 variant {variant}")
@@ -397,7 +397,43 @@ def test_spadd3_staged_fill_variants(dtype):
             first = A.vals.clone()
         assert torch.equal(A.vals, first), variant  # same sums in the same order
     with pytest.raises(spl.SpleafError, match="SPL_ERR_ARG"):
-        spl.spadd3(*ops, sched=spl.schedule("row", variant=4))
+        spl.spadd3(*ops, sched=spl.schedule("row", variant=5))
+
+
+def test_spadd3_rank_form_rows_within_the_stage():
+    # the rank forms on workgroups whose runs fit the stage but whose rows
+    # are long, overlap wholly or partly, or are empty: coordinates held by
+    # one, two or three operands, duplicates at the first and last entries,
+    # a full row next to empty ones, and signed zeros; the merge forms give
+    # the same pattern and bits
+    spl = _spl()
+    rs = np.random.RandomState(12)
+    n, m = 600, 1500
+    pos, crd, vals = tiny.csr(rs, n, m, 0.001, empty_rows={0, 1, 255, 256, 599},
+                              full_rows={3}, kind="int")
+    p2, c2, v2 = tiny.csr(rs, n, m, 0.001, empty_rows={3, 256}, full_rows={300}, kind="int")
+    # D repeats B's coordinates in rows 0..299 and C's in the rest, plus a few
+    rows = []
+    for i in range(n):
+        src = (crd[pos[i]:pos[i + 1]] if i < 300 else c2[p2[i]:p2[i + 1]]).tolist()
+        extra = rs.choice(m, rs.randint(0, 3), replace=False).tolist()
+        rows.append(sorted(set(src) | set(extra)))
+    p3 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    c3 = np.array([c for r in rows for c in r], dtype=np.int64)
+    v3 = rs.randint(-4, 5, c3.size).astype(np.float64)
+    v2[:5] = -0.0
+    ops = [spl.CSR(_t(p), _t(c), _t(v, torch.float32), (n, m))
+           for p, c, v in ((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))]
+    rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
+    per_wg = [max(int(p[min(w + 256, n)] - p[w]) for p in (pos, p2, p3)) for w in range(0, n, 256)]
+    assert 1500 <= max(per_wg) <= 2304  # long rows, yet every workgroup fits the stage
+    A1 = spl.spadd3(*ops, sched=spl.schedule("row", variant=1))
+    A4 = spl.spadd3(*ops, sched=spl.schedule("row", variant=4))
+    for A in (A1, A4):
+        assert np.array_equal(A.pos.cpu().numpy(), rpos)
+        assert np.array_equal(A.crd.cpu().numpy(), rcrd)
+        assert np.array_equal(host64(A.vals), rvals)
+    assert torch.equal(A4.vals.view(torch.int32), A1.vals.view(torch.int32))  # bits, signs of zero
 
 
 def _perturbed_csf(c, rs, drop=0.3, extra=0.3):
