@@ -25,6 +25,12 @@ struct spl_context {
     void *ws = nullptr;   // context-owned workspace (used when the caller gives none)
     size_t ws_bytes = 0;
     int64_t *flags = nullptr;  // 2 x int64 device scratch for spl_validate
+    // pinned host slot for the counts read back to the host (an output's
+    // nonzero count, spl_validate's flags): a copy into pinned memory is a
+    // plain DMA, where pageable memory goes through the runtime's staging
+    // buffer.  Calls on one context are not meant to overlap across host
+    // threads (the error string is shared too).
+    int64_t *readback = nullptr;  // 2 x int64
     // leaf-kernel timing (spl_timing_enable / spl_timing_read)
     struct Mark {
         hipEvent_t start, stop;
@@ -802,8 +808,11 @@ spl_status spl_context_create(int device, spl_context **out) {
     ctx = new spl_context();
     ctx->device = device;
     if (hipSetDevice(device) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&ctx->flags), 2 * sizeof(int64_t)) != hipSuccess) {
+        hipMalloc(reinterpret_cast<void **>(&ctx->flags), 2 * sizeof(int64_t)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->readback), 2 * sizeof(int64_t),
+                      hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
+        if (ctx->flags) (void)hipFree(ctx->flags);
         delete ctx;
         return SPL_ERR_HIP;
     }
@@ -821,6 +830,7 @@ spl_status spl_context_destroy(spl_context *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->flags) (void)hipFree(ctx->flags);
+    if (ctx->readback) (void)hipHostFree(ctx->readback);
     for (const auto &m : ctx->marks) {
         (void)hipEventDestroy(m.start);
         (void)hipEventDestroy(m.stop);
@@ -1050,10 +1060,11 @@ spl_status spl_validate(spl_context *ctx, const spl_sparse *B, spl_stream stream
         SPL_HIP(spl::launch_validate_level(parents, B->pos[l], B->crd[l], children, extent,
                                            ctx->flags, s),
                 "validate launch");
-        int64_t res[2];
-        SPL_HIP(hipMemcpyAsync(res, ctx->flags, sizeof res, hipMemcpyDeviceToHost, s),
+        SPL_HIP(hipMemcpyAsync(ctx->readback, ctx->flags, 2 * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s),
                 "hipMemcpyAsync");
         SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        const int64_t res[2] = {ctx->readback[0], ctx->readback[1]};
         if (res[0] != 0) {
             const unsigned code = static_cast<unsigned>(res[0]);
             const char *what = (code & 1u)    ? "pos[0] != 0"
@@ -1693,10 +1704,10 @@ spl_status spl_spadd3_symbolic(spl_context *ctx, const spl_sparse *B, const spl_
                                         D->crd[1], A_pos, tile_sum, total, s),
             "SpAdd3 symbolic launch");
     tm.stop();
-    int64_t host_total = 0;
-    SPL_HIP(hipMemcpyAsync(&host_total, total, sizeof host_total, hipMemcpyDeviceToHost, s),
+    SPL_HIP(hipMemcpyAsync(ctx->readback, total, sizeof(int64_t), hipMemcpyDeviceToHost, s),
             "hipMemcpyAsync");
     SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const int64_t host_total = ctx->readback[0];
     if (host_total > kIndexMax)
         return fail(ctx, SPL_ERR_SHAPE, "output nnz %lld exceeds int32 positions",
                     static_cast<long long>(host_total));
@@ -1816,10 +1827,10 @@ spl_status spl_tin_symbolic(spl_context *ctx, const char *tin, int nops, const s
     spl::tin::fill_slots(prog, b, ob, A_pos, nullptr, nullptr, slots);
     SPL_HIP(tin_launch(cp->f_count, prog.rows, slots, s), "generated count launch");
     SPL_HIP(spl::launch_pos_scan(prog.rows, A_pos, tile_sum, total, s), "scan launch");
-    int64_t host_total = 0;
-    SPL_HIP(hipMemcpyAsync(&host_total, total, sizeof host_total, hipMemcpyDeviceToHost, s),
+    SPL_HIP(hipMemcpyAsync(ctx->readback, total, sizeof(int64_t), hipMemcpyDeviceToHost, s),
             "hipMemcpyAsync");
     SPL_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const int64_t host_total = ctx->readback[0];
     if (host_total > kIndexMax)
         return fail(ctx, SPL_ERR_SHAPE, "output nnz %lld exceeds int32 positions",
                     static_cast<long long>(host_total));
