@@ -1580,7 +1580,7 @@ spl_status spl_inner(spl_context *ctx, const spl_sparse *B, const spl_sparse *C,
                     B->vtype, order, B->dims[0], o3 ? B->nfibers : B->nnz, B->pos[1], B->crd[1],
                     o3 ? B->pos[2] : nullptr, o3 ? B->crd[2] : nullptr, B->vals, C->pos[1],
                     C->crd[1], o3 ? C->pos[2] : nullptr, o3 ? C->crd[2] : nullptr, C->vals,
-                    ws, out, s),
+                    B->nnz, C->nnz, o3 ? C->nfibers : C->nnz, ws, out, s),
                 "inner product launch");
     }
     tm.stop();

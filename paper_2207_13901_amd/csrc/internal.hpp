@@ -150,7 +150,8 @@ hipError_t launch_inner_general(int vtype, int order, int64_t n, int64_t units,
                                 const int32_t *bpos, const int32_t *bcrd, const int32_t *bpos2,
                                 const int32_t *bcrd2, const void *bv, const int32_t *cpos,
                                 const int32_t *ccrd, const int32_t *cpos2, const int32_t *ccrd2,
-                                const void *cv, void *ws, double *out, hipStream_t s);
+                                const void *cv, int64_t nnzb, int64_t nnzc, int64_t cunits,
+                                void *ws, double *out, hipStream_t s);
 
 // ---- sddmm.hip -----------------------------------------------------------
 int64_t sddmm_chunk();
