@@ -396,8 +396,8 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
                 const bool ok = qq < np;
                 const bool staged = kStage && rel0 + qq < kStagePos;
                 const uint32_t rel = static_cast<uint32_t>(P0 - cp0 + qq);
-                int k = static_cast<int>(buf_u32(rK, ok && !staged ? 4u * rel : kBufOut));
-                Acc v = buf_val(kval, rV, ok && !staged ? kVs * rel : kBufOut);
+                int k = static_cast<int>(buf_u32<0>(rK, ok && !staged ? 4u * rel : kBufOut));
+                Acc v = buf_val<0>(kval, rV, ok && !staged ? kVs * rel : kBufOut);
                 if constexpr (kStage) {
                     const int si = static_cast<int>(rel0 + qq < kStagePos ? rel0 + qq : kStagePos - 1);
                     const int ksv = s_kq[si];

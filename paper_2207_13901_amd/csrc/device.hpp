@@ -219,15 +219,20 @@ constexpr uint32_t kBufOut = 0xFFFFFFF0u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, 0x00020000);
 }
-// 4-byte element at byte offset `off` (non-temporal: streamed arrays)
+// 4-byte element at byte offset `off`.  AUX is the cache policy: 2 (the
+// default) non-temporal, for arrays streamed once; 0 where later loads of
+// the same lines follow (neighbouring lanes or the next instructions).
+template <int AUX = 2>
 __device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
 }
+template <int AUX = 2>
 __device__ __forceinline__ float buf_val(const float *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
 }
+template <int AUX = 2>
 __device__ __forceinline__ float buf_val(const bf16 *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 2))
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX))
                            << 16);
 }
 

@@ -76,9 +76,9 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_valu(
             const bool has2 = k2 < np;
             const int64_t p = cp + k, p2 = cp + k2;
             const FT *crow = C + static_cast<int64_t>(s_row[k]) * ldc;
-            const FT *drow = D + static_cast<int64_t>(load_stream(crd + p)) * ldd;
+            const FT *drow = D + static_cast<int64_t>(crd[p]) * ldd;
             const FT *crow2 = C + static_cast<int64_t>(s_row[has2 ? k2 : k]) * ldc;
-            const FT *drow2 = D + static_cast<int64_t>(load_stream(crd + (has2 ? p2 : p))) * ldd;
+            const FT *drow2 = D + static_cast<int64_t>(crd[has2 ? p2 : p]) * ldd;
             Acc a1 = 0, a2 = 0;
             for (int64_t kk = lane; kk < K; kk += 32) {
                 a1 += widen<Acc>(crow[kk]) * widen<Acc>(drow[kk]);
@@ -130,7 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_vec(
                 live[u] = ku < np;
                 const int kk = live[u] ? ku : k;  // dead slots reread a live position
                 crow[u] = C + static_cast<int64_t>(s_row[kk]) * ldc;
-                drow[u] = D + static_cast<int64_t>(load_stream(crd + cp + kk)) * ldd;
+                // (the default cache policy: the next iteration's positions
+                // share these lines)
+                drow[u] = D + static_cast<int64_t>(crd[cp + kk]) * ldd;
             }
             Acc a[P];
 #pragma unroll
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_sddmm_mfma(
             const int kk = live ? k : base;  // dead lanes read a live position
             const int64_t p = cp + kk;
             const bf16 *crow = C + static_cast<int64_t>(s_row[kk]) * ldc + kg * 8;
-            const bf16 *drow = D + static_cast<int64_t>(load_stream(crd + p)) * ldd + kg * 8;
+            const bf16 *drow = D + static_cast<int64_t>(crd[p]) * ldd + kg * 8;
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             for (int64_t k0 = 0; k0 < K; k0 += 32) {
                 const u32x4 ca = *reinterpret_cast<const u32x4 *>(crow + k0);
