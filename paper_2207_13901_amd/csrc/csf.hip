@@ -128,9 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
             for (int q = 0; q < kPosCap; ++q) {
                 kq[q] = 0;
                 vq[q] = 0;
-                if (q < np) {
-                    kq[q] = load_stream(crd2 + P0 + q);
-                    vq[q] = widen<Acc>(load_stream(vals + P0 + q));
+                if (q < np) {  // (default cache policy: the next loads share the lines)
+                    kq[q] = crd2[P0 + q];
+                    vq[q] = widen<Acc>(vals[P0 + q]);
                 }
             }
 #pragma unroll
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_tiles(
                         t += s_dv[g][q][lane];
                     } else if (colok) {
                         const int64_t p = P0 + q;
-                        t += widen<Acc>(load_stream(vals + p)) *
-                             widen<Acc>(D[static_cast<int64_t>(load_stream(crd2 + p)) * ldd + col]);
+                        t += widen<Acc>(vals[p]) *
+                             widen<Acc>(D[static_cast<int64_t>(crd2[p]) * ldd + col]);
                     }
                 }
                 acc += cv[k] * t;
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
                         kq[q] = s_kq[rel0 + q];
                         vq[q] = s_vq[rel0 + q];
                     } else {
-                        kq[q] = load_stream(kcrd + P0 + q);
-                        vq[q] = widen<Acc>(load_stream(kval + P0 + q));
+                        kq[q] = kcrd[P0 + q];
+                        vq[q] = widen<Acc>(kval[P0 + q]);
                     }
                 }
             }
@@ -541,8 +541,8 @@ __global__ __launch_bounds__(NT) void k_mttkrp_vec(
                             kq[q] = s_kq[rel0 + qq];
                             vq[q] = s_vq[rel0 + qq];
                         } else {
-                            kq[q] = load_stream(kcrd + P0 + qq);
-                            vq[q] = widen<Acc>(load_stream(kval + P0 + qq));
+                            kq[q] = kcrd[P0 + qq];
+                            vq[q] = widen<Acc>(kval[P0 + qq]);
                         }
                     }
                 }
