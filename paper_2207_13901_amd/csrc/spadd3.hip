@@ -199,7 +199,7 @@ __device__ __forceinline__ void fill_windows(int64_t n, const Csr3 &m, const Crd
     const int64_t i = r0 + threadIdx.x;
     const int64_t base = apos[r0];
     const int64_t total = apos[r1] - base;
-    const bool mine = i < n;
+    const bool mine = i < r1;
     int64_t k = mine ? apos[i] - base : 0;
     const int64_t hi = mine ? apos[i + 1] - base : 0;
     Merge3 mg(m, x, mine ? i : r0);
@@ -274,8 +274,14 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_fill(int64_t n, Csr3 m, const
 // line is read with coalesced loads (values by their owner lanes, the
 // duplicates' values gathered from lines their neighbours read), and no lane
 // walks a whole row.  Runs longer than kRankCap fall back to the windowed
-// merge for that workgroup.
-constexpr int kRankCap = 2304;                 // entries per operand and workgroup
+// merge for that workgroup.  A workgroup takes 128 rows with its 256 lanes
+// (5 entries a lane and operand, 22 KB of LDS): 0.142 ms on three 1e6-row
+// operands of 8 entries a row, against 0.153 with 192 rows (7 a lane,
+// 31 KB), 0.166 with 256 (9 a lane, 40 KB, 4 workgroups a CU) and 0.149
+// with 64 (3 a lane): more workgroups per CU until a lane has too little
+// to overlap.
+constexpr int kRankRows = 128;                 // rows per workgroup
+constexpr int kRankCap = 1280;                 // entries per operand and workgroup
 constexpr int kRankPer = kRankCap / kBlock;     // entries per lane and operand
 constexpr int kRankChunks = kRankCap / 64 + 1;  // ballot words, one spare for a full run
 static_assert(kRankCap % kBlock == 0, "whole entries per lane");
@@ -316,10 +322,10 @@ __device__ __forceinline__ int flags_below(const uint64_t *mask, const int32_t *
 struct RankLds {
     int32_t x[3][kRankCap];
     uint8_t row[3][kRankCap];
-    int32_t start[3][kBlock + 1];
+    int32_t start[3][kRankRows + 1];
     uint64_t mask[2][kRankChunks];
     int32_t pre[2][kRankChunks];
-    int32_t base[kBlock];
+    int32_t base[kRankRows];
 
     __device__ __forceinline__ int lb(int X, int r, int32_t v) const {
         return lower_bound_lds(x[X], start[X][r], start[X][r + 1], v);
@@ -470,22 +476,23 @@ __device__ __forceinline__ void rank_slot(const RankLds &L, const RankSeen &S, i
 // about the same rows, so the group fills its output lines while the L2
 // still holds them (one operand after another left them partly written
 // and evicted: 2.3 times the output's bytes written).  Groups of three
-// entries per operand: 0.167 ms on three 1e6-row operands, against 0.175
-// for groups of one (fewer loads in flight) and 0.189 for one operand
-// after another.
+// entries per operand (at 256 rows a workgroup: 0.167 ms on three 1e6-row
+// operands, against 0.175 for groups of one, fewer loads in flight, and
+// 0.189 for one operand after another).
 constexpr int kRankGroup = 3;
-static_assert(kRankPer % kRankGroup == 0, "whole groups");
 
 template <int J0, typename V>
 __device__ __forceinline__ void rank_emit(const RankLds &L, const RankSeen &S,
                                           const V *const *vals, const __amdgpu_buffer_rsrc_t *rv,
                                           const V (*own)[kRankPer], const int32_t *n3,
                                           int32_t *acrd, V *aval) {
+    // the last group may be short
+    constexpr int NJ = J0 + kRankGroup <= kRankPer ? kRankGroup : kRankPer - J0;
     int32_t o[3][kRankGroup], xs[3][kRankGroup];
     V g1[kRankGroup], g2[2][kRankGroup];
     uint32_t has1 = 0, has2 = 0;  // bit 3X + jj: entry adds C's value (X = 0) / D's (X < 2)
 #pragma unroll
-    for (int jj = 0; jj < kRankGroup; ++jj) {
+    for (int jj = 0; jj < NJ; ++jj) {
         uint32_t s1, s2;
         rank_slot<0, V>(L, S, J0 + jj, n3[0], o[0][jj], xs[0][jj], s1, s2);
         g1[jj] = buf_load(vals[1], rv[1], s1);
@@ -500,7 +507,7 @@ __device__ __forceinline__ void rank_emit(const RankLds &L, const RankSeen &S,
 #pragma unroll
     for (int X = 0; X < 3; ++X)
 #pragma unroll
-        for (int jj = 0; jj < kRankGroup; ++jj) {
+        for (int jj = 0; jj < NJ; ++jj) {
             if (o[X][jj] < 0) continue;
             // the merge's order: B's value, else 0, then + C's, then + D's
             V v = X == 0 ? own[0][J0 + jj] : V(0) + own[X][J0 + jj];
@@ -517,16 +524,17 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_rank(int64_t n, Csr3 m, const
                                                         const int32_t *apos, int32_t *acrd,
                                                         V *aval) {
     __shared__ __align__(16) RankLds L;
-    static_assert(kFillCap * (4 + sizeof(V)) <= sizeof(L.x), "fallback windows fit the stage");
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
-    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    constexpr int kRankWin = 1024;  // output window of the fallback merge
+    static_assert(kRankWin * (4 + sizeof(V)) <= sizeof(L.x), "fallback windows fit the stage");
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRankRows;
+    const int64_t r1 = r0 + kRankRows < n ? r0 + kRankRows : n;
     const int nr = static_cast<int>(r1 - r0);
     const int32_t first3[3] = {m.bp[r0], m.cp[r0], m.dp[r0]};
     const int32_t n3[3] = {m.bp[r1] - first3[0], m.cp[r1] - first3[1], m.dp[r1] - first3[2]};
     if (n3[0] > kRankCap || n3[1] > kRankCap || n3[2] > kRankCap) {
-        fill_windows<V, kFillCap>(n, m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0},
+        fill_windows<V, kRankWin>(n, m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0},
                                   Vals3<V>{bv, cv, dv, 0, 0, 0}, apos, acrd, aval, r0, r1,
-                                  &L.x[0][0], reinterpret_cast<V *>(&L.x[0][0] + kFillCap));
+                                  &L.x[0][0], reinterpret_cast<V *>(&L.x[0][0] + kRankWin));
         return;
     }
     const V *vals[3] = {bv, cv, dv};
@@ -547,8 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_rank(int64_t n, Csr3 m, const
     const int32_t out0 = apos[r0];
     rank_emit<0>(L, S, vals, rv, own, n3, acrd + out0, aval + out0);
     rank_emit<3>(L, S, vals, rv, own, n3, acrd + out0, aval + out0);
-    rank_emit<6>(L, S, vals, rv, own, n3, acrd + out0, aval + out0);
-    static_assert(kRankPer == 9 && kRankGroup == 3, "three groups");
+    static_assert(kRankPer == 5 && kRankGroup == 3, "groups of 3 and 2");
 }
 
 // Element i of the scanned sequence: x[i], or with window bounds the window
@@ -720,7 +727,12 @@ hipError_t spadd3_fill(int stage, int64_t n, const Csr3 &m, const void *bv, cons
                                      static_cast<const V *>(dv), apos, acrd, static_cast<V *>(aval));
         return hipGetLastError();
     };
-    if (stage == 3) return go(k_spadd3_rank<V>);
+    if (stage == 3) {
+        k_spadd3_rank<V><<<dim3(static_cast<unsigned>(ceil_div(n, kRankRows))), kBlock, 0, s>>>(
+            n, m, static_cast<const V *>(bv), static_cast<const V *>(cv),
+            static_cast<const V *>(dv), apos, acrd, static_cast<V *>(aval));
+        return hipGetLastError();
+    }
     if (stage == 1) return go(k_spadd3_fill<V, 1>);
     if (stage == 2) return go(k_spadd3_fill<V, 2>);
     return go(k_spadd3_fill<V, 0>);

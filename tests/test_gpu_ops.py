@@ -408,10 +408,10 @@ def test_spadd3_rank_form_rows_within_the_stage():
     # the same pattern and bits
     spl = _spl()
     rs = np.random.RandomState(12)
-    n, m = 600, 1500
-    pos, crd, vals = tiny.csr(rs, n, m, 0.001, empty_rows={0, 1, 255, 256, 599},
+    n, m = 600, 1000
+    pos, crd, vals = tiny.csr(rs, n, m, 0.001, empty_rows={0, 1, 191, 192, 255, 256, 599},
                               full_rows={3}, kind="int")
-    p2, c2, v2 = tiny.csr(rs, n, m, 0.001, empty_rows={3, 256}, full_rows={300}, kind="int")
+    p2, c2, v2 = tiny.csr(rs, n, m, 0.001, empty_rows={3, 192, 256}, full_rows={300}, kind="int")
     # D repeats B's coordinates in rows 0..299 and C's in the rest, plus a few
     rows = []
     for i in range(n):
@@ -425,8 +425,9 @@ def test_spadd3_rank_form_rows_within_the_stage():
     ops = [spl.CSR(_t(p), _t(c), _t(v, torch.float32), (n, m))
            for p, c, v in ((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))]
     rpos, rcrd, rvals, _, _ = oracle.spadd3((pos, crd, vals), (p2, c2, v2), (p3, c3, v3))
-    per_wg = [max(int(p[min(w + 256, n)] - p[w]) for p in (pos, p2, p3)) for w in range(0, n, 256)]
-    assert 1500 <= max(per_wg) <= 2304  # long rows, yet every workgroup fits the stage
+    # the rank fill's workgroups: 128 rows, at most 1,280 entries per operand
+    per_wg = [max(int(p[min(w + 128, n)] - p[w]) for p in (pos, p2, p3)) for w in range(0, n, 128)]
+    assert 1000 <= max(per_wg) <= 1280  # long rows, yet every workgroup fits the stage
     A1 = spl.spadd3(*ops, sched=spl.schedule("row", variant=1))
     A4 = spl.spadd3(*ops, sched=spl.schedule("row", variant=4))
     for A in (A1, A4):
