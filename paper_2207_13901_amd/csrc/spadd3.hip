@@ -285,6 +285,8 @@ constexpr int kRankCap = 1280;                 // entries per operand and workgr
 constexpr int kRankPer = kRankCap / kBlock;     // entries per lane and operand
 constexpr int kRankChunks = kRankCap / 64 + 1;  // ballot words, one spare for a full run
 static_assert(kRankCap % kBlock == 0, "whole entries per lane");
+static_assert(kRankRows <= 256 && kRankRows <= kBlock, "a row index fits a byte, a lane per row");
+static_assert(kRankChunks <= 64, "one wave scans the ballot words");
 
 // Value at byte offset `off` of a buffer (0 past its range, with no access).
 __device__ __forceinline__ float buf_load(const float *, __amdgpu_buffer_rsrc_t r, uint32_t off) {
