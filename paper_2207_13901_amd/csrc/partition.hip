@@ -82,23 +82,28 @@ __global__ __launch_bounds__(kBlock) void k_merge_bounds(int64_t rows, const P *
 // ends before index d are those of rows 0 .. i-1).  The bounds at or past
 // the end are (rows, nnz).  One lane per row; reading pos once costs less
 // than a 20-step dependent search per tile when rows are few.
+// (log2M >= 0: M is 2^log2M, and the divisions by M are shifts; a 64-bit
+// division per lane costs more than the lane's reads.)
 template <typename P, typename TP>
 __global__ __launch_bounds__(kBlock) void k_merge_sweep(int64_t rows, const P *pos,
-                                                        int64_t nnz, int64_t M, int64_t ntiles,
-                                                        int32_t *trow, TP *tpos) {
+                                                        int64_t nnz, int64_t M, int log2M,
+                                                        int64_t ntiles, int32_t *trow, TP *tpos) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (nnz < 0) nnz = static_cast<int64_t>(pos[rows]);  // the total is on the device
+    auto tiles_to = [&](int64_t d) {  // first tile starting at or after merged index d
+        return log2M >= 0 ? (d + M - 1) >> log2M : (d + M - 1) / M;
+    };
     // every bound at or past the end (the last one, all of them when there
     // are no items, many when the tile count is an upper bound), spread over
     // all threads
     const int64_t nthreads = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = (rows + nnz + M - 1) / M + i; t <= ntiles; t += nthreads) {
+    for (int64_t t = tiles_to(rows + nnz) + i; t <= ntiles; t += nthreads) {
         trow[t] = static_cast<int32_t>(rows);
         tpos[t] = static_cast<TP>(nnz);
     }
     if (i >= rows) return;
     const int64_t lo = i + static_cast<int64_t>(pos[i]), hi = i + static_cast<int64_t>(pos[i + 1]);
-    for (int64_t t = (lo + M - 1) / M; t * M <= hi; ++t) {
+    for (int64_t t = tiles_to(lo); t * M <= hi; ++t) {
         trow[t] = static_cast<int32_t>(i);
         tpos[t] = static_cast<TP>(t * M - i);
     }
@@ -201,12 +206,15 @@ constexpr int64_t kMergeSweepRows = 8000000;
 template <typename P, typename TP>
 hipError_t merge_bounds(int64_t rows, const P *pos, int64_t nnz, int64_t size, int64_t ntiles,
                         int32_t *trow, TP *tpos, hipStream_t s) {
-    if (rows <= kMergeSweepRows && ntiles < rows)
+    if (rows <= kMergeSweepRows && ntiles < rows) {
+        int log2M = -1;  // the tile size is 2^log2M, or -1
+        if (size > 0 && (size & (size - 1)) == 0) log2M = __builtin_ctzll(static_cast<uint64_t>(size));
         k_merge_sweep<P, TP><<<dim3(static_cast<unsigned>(ceil_div(rows + 1, kBlock))), kBlock, 0,
-                               s>>>(rows, pos, nnz, size, ntiles, trow, tpos);
-    else
+                               s>>>(rows, pos, nnz, size, log2M, ntiles, trow, tpos);
+    } else {
         k_merge_bounds<P, TP><<<dim3(static_cast<unsigned>(ceil_div(ntiles + 1, kBlock))), kBlock,
                                 0, s>>>(rows, pos, nnz, size, ntiles, trow, tpos);
+    }
     return hipGetLastError();
 }
 
