@@ -27,6 +27,7 @@ namespace spl {
 
 constexpr int kFixBlock = 256;  // tiles per workgroup, one per lane
 constexpr int kFixShort = 8;    // longest run a lane sums alone
+static_assert(kFixShort >= 2, "the first step of a run is taken before the loop");
 constexpr int kFixLanes = 8;    // lanes per tile for vector carries
 constexpr int kFixBatch = 8;    // carries one lane loads before adding them
 
@@ -46,17 +47,27 @@ __global__ __launch_bounds__(kFixBlock) void k_carry_fixup(int64_t rows, int64_t
         const int64_t piece = (v + 1) * stride;
         return trow[piece < npieces ? piece : npieces];
     };
-    const int32_t r = u < ntiles ? open_row(u) : static_cast<int32_t>(rows);
-    const bool first = r < rows && (u == 0 || open_row(u - 1) != r);
+    // the open rows of tiles u - 1, u and u + 1 loaded together (indices
+    // clamped into [0, ntiles)), so the common case -- a run of one tile --
+    // needs one round of these loads, not three
+    const int64_t uc = u < ntiles ? u : ntiles - 1;
+    const int32_t r_here = open_row(uc);
+    const int32_t r_prev = open_row(uc > 0 ? uc - 1 : 0);
+    const int32_t r_next = open_row(uc + 1 < ntiles ? uc + 1 : uc);
+    const int32_t r = u < ntiles ? r_here : static_cast<int32_t>(rows);
+    const bool first = r < rows && (u == 0 || r_prev != r);
     int64_t end = u + 1;
     bool longrun = false;
-    if (first) {
+    if (first && end < ntiles && r_next == r) {
+        ++end;  // (kFixShort >= 2)
         while (end < ntiles && open_row(end) == r) {
             if (++end - u > kFixShort) {
                 longrun = true;
                 break;
             }
         }
+    }
+    if (first) {
         if (!longrun) {
             OT *orow = out + static_cast<int64_t>(r) * ldo;
             for (int64_t col = c; col < ncols; col += per) {
