@@ -6,7 +6,7 @@ log2(time / best time), and picks the candidate with the smallest
 prediction.  It is trained on timings that the exhaustive autotuner records
 over a seeded corpus of synthetic matrices; training (forward, backward and
 Adam) and inference run in the library's own kernels.  The exhaustive
-autotuner stays the fallback and the judge: regret = t(chosen) / t(best) - 1
+autotuner stays the fallback and the yardstick: regret = t(chosen) / t(best) - 1
 per matrix, measured against it on held-out matrices.
 
 Command line (GPU):
