@@ -147,7 +147,7 @@ __device__ __forceinline__ bool stage_crd(const Csr3 &m, int64_t r0, int64_t r1,
     return true;
 }
 
-// Union size of row i's coordinate lists read through x.
+// Union size of row i's coordinate lists read through x (HBM).
 __device__ __forceinline__ int32_t union_count(const Csr3 &m, const Crd3 &x, int64_t i) {
     Merge3 mg(m, x, i);
     int32_t k = 0;
@@ -155,6 +155,34 @@ __device__ __forceinline__ int32_t union_count(const Csr3 &m, const Crd3 &x, int
     const Vals3<float> none{nullptr, nullptr, nullptr, 0, 0, 0};
     while (!mg.done()) {
         mg.next<false, float>(x, none, unused);
+        ++k;
+    }
+    return k;
+}
+
+// The same from the staged runs s_x (first positions f), without branches:
+// each step takes the smallest head, advances every list holding it and
+// reads all three heads again at indices clamped into the stage, so a step
+// is one round of LDS reads instead of up to three behind lane-masked
+// branches.
+__device__ __forceinline__ int32_t union_count_staged(const Csr3 &m, int32_t (*s_x)[kStageCap],
+                                                      const int32_t *f, int64_t i) {
+    constexpr int32_t kInf = Merge3::kInf;
+    int32_t p[3] = {m.bp[i] - f[0], m.cp[i] - f[1], m.dp[i] - f[2]};
+    const int32_t e[3] = {m.bp[i + 1] - f[0], m.cp[i + 1] - f[1], m.dp[i + 1] - f[2]};
+    auto head = [&](int X) {
+        const int32_t q = p[X] < kStageCap ? p[X] : kStageCap - 1;
+        const int32_t v = s_x[X][q];
+        return p[X] < e[X] ? v : kInf;
+    };
+    int32_t h[3] = {head(0), head(1), head(2)};
+    int32_t k = 0;
+    while (min(h[0], min(h[1], h[2])) != kInf) {
+        const int32_t c = min(h[0], min(h[1], h[2]));
+#pragma unroll
+        for (int X = 0; X < 3; ++X) p[X] += h[X] == c ? 1 : 0;
+#pragma unroll
+        for (int X = 0; X < 3; ++X) h[X] = head(X);
         ++k;
     }
     return k;
@@ -169,10 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_spadd3_count(int64_t n, Csr3 m, int3
     const bool staged = stage_crd(m, r0, r1, s_x, f);
     if (i == 0) apos[0] = 0;
     if (i >= n) return;
-    // two inlined copies, so that the staged one reads LDS directly rather
-    // than through generic (flat) loads
+    // the staged path is code of its own, so that it reads LDS directly
+    // rather than through generic (flat) loads
     if (staged)
-        apos[i + 1] = union_count(m, Crd3{s_x[0], s_x[1], s_x[2], f[0], f[1], f[2]}, i);
+        apos[i + 1] = union_count_staged(m, s_x, f, i);
     else
         apos[i + 1] = union_count(m, Crd3{m.bc, m.cc, m.dc, 0, 0, 0}, i);
 }
